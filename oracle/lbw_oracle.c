@@ -1,0 +1,548 @@
+/*
+ * lbw_oracle.c -- plain FP64 CPU oracle of the coupled LBM + WENO step of
+ * arXiv 2106.07694 (Lemus et al.).
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the
+ * benchmark's CPU-baseline leg, never by the product path.  Written for
+ * readability, not speed: two-lattice streaming, explicit ghost rules, face
+ * fluxes stored per axis and then differenced, one loop per equation.
+ *
+ * What one step computes (section 2.3 of the paper and supplement section 1):
+ *   1. moments of the populations (eq. 19-20) with the Guo half-force shift
+ *      (eq. 22) -> rho, u; buoyancy force from C (and S) (eq. 10, linearised);
+ *   2. C <- TVD-RK3 (S21-S23) of the conservative advection-diffusion-settling
+ *      equation (eq. 6) with WENO face fluxes (S8-S20 gives the third-order
+ *      form; the fifth-order Jiang-Shu form is the default here), velocity
+ *      u - Vs e_vert frozen at time level n, absorbing bottom wall feeding the
+ *      per-column deposit counter;
+ *   3. S <- forward Euler of the first-order upwind conservative scheme
+ *      (S5-S6 in conservative form) with central diffusion;
+ *   4. BGK collision (eq. 18) with Guo forcing (eq. 22);
+ *   5. streaming with half-way bounce-back at the walls (section 2.3.1), the
+ *      moving-wall correction at the top.
+ * All in lattice units: dx = dt = 1, cs^2 = 1/3 (eq. 21), rho0 = 1.
+ *
+ * Parity pins: every routine is exercised by the CPU tests against closed
+ * forms or invariants.  The wall ghost rules of the WENO stencils are pinned
+ * only through conservation (parity unpinned beyond that).
+ */
+#include "lbw_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define MAXQ 19
+
+typedef struct {
+    int q, dim, vert;
+    int n[3];
+    long N;       /* nodes */
+    long ncol;    /* bottom columns */
+    int c[MAXQ][3];
+    double w[MAXQ];
+    int opp[MAXQ];
+} grid_t;
+
+/* ----------------------------------------------------------------------- */
+/* Lattices.  D2Q9: rest, +x, +y, -x, -y, (+,+), (-,+), (-,-), (+,-).      */
+/* D3Q19: rest, +x, -x, +y, -y, +z, -z, then the 12 edge vectors in pairs  */
+/* of opposites.  Weights are the standard second-order ones (the paper    */
+/* cites Kruger et al. for the lattices; Fig. 3 shows D3Q19).              */
+/* ----------------------------------------------------------------------- */
+static int set_lattice(int q, grid_t *g)
+{
+    static const int c9[9][2] = {{0, 0}, {1, 0}, {0, 1}, {-1, 0}, {0, -1},
+                                 {1, 1}, {-1, 1}, {-1, -1}, {1, -1}};
+    static const int c19[19][3] = {
+        {0, 0, 0},
+        {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+        {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+        {1, 0, 1}, {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+        {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+    int i, j;
+    memset(g->c, 0, sizeof(g->c));
+    if (q == 9) {
+        g->q = 9;
+        g->dim = 2;
+        for (i = 0; i < 9; i++) {
+            g->c[i][0] = c9[i][0];
+            g->c[i][1] = c9[i][1];
+            g->w[i] = (i == 0) ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+        }
+    } else if (q == 19) {
+        g->q = 19;
+        g->dim = 3;
+        for (i = 0; i < 19; i++) {
+            for (j = 0; j < 3; j++) g->c[i][j] = c19[i][j];
+            g->w[i] = (i == 0) ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+        }
+    } else {
+        return -1;
+    }
+    /* opposite direction found by search, not tabulated */
+    for (i = 0; i < g->q; i++) {
+        g->opp[i] = -1;
+        for (j = 0; j < g->q; j++)
+            if (g->c[j][0] == -g->c[i][0] && g->c[j][1] == -g->c[i][1] &&
+                g->c[j][2] == -g->c[i][2])
+                g->opp[i] = j;
+    }
+    g->vert = g->dim - 1;
+    return 0;
+}
+
+static int setup(const orc_cfg *cfg, grid_t *g)
+{
+    if (!cfg) return -1;
+    if (set_lattice(cfg->q, g)) return -1;
+    g->n[0] = cfg->nx;
+    g->n[1] = cfg->ny;
+    g->n[2] = cfg->nz;
+    if (g->dim == 2 && cfg->nz != 1) return -1;
+    if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1) return -1;
+    if (g->n[g->vert] < 6) return -1;
+    g->N = (long)cfg->nx * cfg->ny * cfg->nz;
+    g->ncol = (g->dim == 2) ? cfg->nx : (long)cfg->nx * cfg->ny;
+    return 0;
+}
+
+static long node_index(const grid_t *g, const int p[3])
+{
+    return (long)p[0] + (long)g->n[0] * ((long)p[1] + (long)g->n[1] * p[2]);
+}
+
+static void node_coords(const grid_t *g, long k, int p[3])
+{
+    p[0] = (int)(k % g->n[0]);
+    p[1] = (int)((k / g->n[0]) % g->n[1]);
+    p[2] = (int)(k / ((long)g->n[0] * g->n[1]));
+}
+
+static long column_of(const grid_t *g, const int p[3])
+{
+    return (g->dim == 2) ? p[0] : (long)p[0] + (long)g->n[0] * p[1];
+}
+
+/* ----------------------------------------------------------------------- */
+/* Moments, eq. 19-20 with the Guo shift rho u = sum f c + F/2 (eq. 22).    */
+/* Force (eq. 10, linearised in C and S): F = body + e_vert(-gp_c C - gp_s S) */
+/* ----------------------------------------------------------------------- */
+static void force_at(const grid_t *g, const orc_cfg *cfg, const double *c,
+                     const double *s, long k, double F[3])
+{
+    int d;
+    for (d = 0; d < 3; d++) F[d] = cfg->body_force[d];
+    F[g->vert] += -cfg->gp_c * c[k];
+    if (cfg->has_s) F[g->vert] += -cfg->gp_s * s[k];
+}
+
+static void moments_at(const grid_t *g, const orc_cfg *cfg, const double *f,
+                       const double *c, const double *s, long k, double *rho,
+                       double u[3], double F[3])
+{
+    double r = 0.0, m[3] = {0.0, 0.0, 0.0};
+    int i, d;
+    for (i = 0; i < g->q; i++) {
+        double fi = f[(long)i * g->N + k];
+        r += fi;
+        for (d = 0; d < 3; d++) m[d] += fi * g->c[i][d];
+    }
+    if (cfg->shifted) r = 1.0 + r; /* sum of w_i is 1 and sum w_i c_i is 0 */
+    force_at(g, cfg, c, s, k, F);
+    for (d = 0; d < 3; d++) u[d] = (m[d] + 0.5 * F[d]) / r;
+    *rho = r;
+}
+
+/* ----------------------------------------------------------------------- */
+/* Face reconstructions.  h are node fluxes ordered upwind -> downwind, a   */
+/* the transported values in the same order (smoothness is measured on a). */
+/* ----------------------------------------------------------------------- */
+
+/* WENO5-JS (Jiang & Shu 1996): value at the right face of the centre node
+ * of the five-node stencil; the fifth-order counterpart of S10-S16. */
+static double weno5(const double h[5], const double a[5], double eps)
+{
+    double q0 = (2.0 * h[0] - 7.0 * h[1] + 11.0 * h[2]) / 6.0;
+    double q1 = (-h[1] + 5.0 * h[2] + 2.0 * h[3]) / 6.0;
+    double q2 = (2.0 * h[2] + 5.0 * h[3] - h[4]) / 6.0;
+    double t, u;
+    double b0, b1, b2, al0, al1, al2;
+    t = a[0] - 2.0 * a[1] + a[2];
+    u = a[0] - 4.0 * a[1] + 3.0 * a[2];
+    b0 = 13.0 / 12.0 * t * t + 0.25 * u * u;
+    t = a[1] - 2.0 * a[2] + a[3];
+    u = a[1] - a[3];
+    b1 = 13.0 / 12.0 * t * t + 0.25 * u * u;
+    t = a[2] - 2.0 * a[3] + a[4];
+    u = 3.0 * a[2] - 4.0 * a[3] + a[4];
+    b2 = 13.0 / 12.0 * t * t + 0.25 * u * u;
+    al0 = 0.1 / ((eps + b0) * (eps + b0));
+    al1 = 0.6 / ((eps + b1) * (eps + b1));
+    al2 = 0.3 / ((eps + b2) * (eps + b2));
+    return (al0 * q0 + al1 * q1 + al2 * q2) / (al0 + al1 + al2);
+}
+
+/* WENO3 (S10-S16): upwind two-node candidate (S11) with weight 1/3, central
+ * candidate (S10) with weight 2/3; stencil order upwind -> downwind. */
+static double weno3(const double h[3], const double a[3], double eps)
+{
+    double qu = 0.5 * (3.0 * h[1] - h[0]);
+    double qc = 0.5 * (h[1] + h[2]);
+    double bu = (a[1] - a[0]) * (a[1] - a[0]);
+    double bc = (a[2] - a[1]) * (a[2] - a[1]);
+    double au = (1.0 / 3.0) / ((eps + bu) * (eps + bu));
+    double ac = (2.0 / 3.0) / ((eps + bc) * (eps + bc));
+    return (au * qu + ac * qc) / (au + ac);
+}
+
+/* Node index displaced by k along axis ax from p, with lateral periodicity
+ * and, on the vertical axis with walls, even reflection about the walls
+ * (Neumann, eq. 14-15).  *ghost is set when the reflection was applied. */
+static long displaced(const grid_t *g, const orc_cfg *cfg, const int p[3],
+                      int ax, int k, int *ghost)
+{
+    int r[3] = {p[0], p[1], p[2]};
+    int n = g->n[ax];
+    int j = p[ax] + k;
+    *ghost = 0;
+    if (ax != g->vert || cfg->vert_periodic) {
+        j = ((j % n) + n) % n;
+    } else if (j < 0) {
+        j = -1 - j;
+        *ghost = 1;
+    } else if (j >= n) {
+        j = 2 * n - 1 - j;
+        *ghost = 1;
+    }
+    r[ax] = j;
+    return node_index(g, r);
+}
+
+/* Transport velocity along ax at a node: u_ax - vs on the vertical axis.
+ * Beyond a wall the vertical fluid velocity is mirrored with a sign change
+ * (no penetration), while settling keeps its direction. */
+static double transport_velocity(const grid_t *g, const double *u, long k,
+                                 int ax, int ghost, double vs)
+{
+    double ua = u[(long)ax * g->N + k];
+    if (ax == g->vert) {
+        if (ghost) ua = -ua;
+        return ua - vs;
+    }
+    return ua;
+}
+
+/* Face flux through the face between p and p + e_ax for scheme `scheme`,
+ * diffusivity kappa, settling vs (0 for S). */
+static double interior_face_flux(const grid_t *g, const orc_cfg *cfg,
+                                 int scheme, double kappa, double vs,
+                                 const double *a, const double *u,
+                                 const int p[3], int ax)
+{
+    double hv[6], av[6], wv[6];
+    int m, gh;
+    long k;
+    double wf, hhat;
+    /* stencil nodes p-2 .. p+3 along ax */
+    for (m = 0; m < 6; m++) {
+        k = displaced(g, cfg, p, ax, m - 2, &gh);
+        av[m] = a[k];
+        wv[m] = transport_velocity(g, u, k, ax, gh, vs);
+        hv[m] = wv[m] * av[m];
+    }
+    /* upwind direction: sign of the face velocity, ties go left (R11) */
+    wf = 0.5 * (wv[2] + wv[3]);
+    if (scheme == 0) {
+        double hh[5], aa[5];
+        if (wf >= 0.0) {
+            for (m = 0; m < 5; m++) { hh[m] = hv[m]; aa[m] = av[m]; }
+        } else {
+            for (m = 0; m < 5; m++) { hh[m] = hv[5 - m]; aa[m] = av[5 - m]; }
+        }
+        hhat = weno5(hh, aa, cfg->weno_eps);
+    } else if (scheme == 1) {
+        double hh[3], aa[3];
+        if (wf >= 0.0) {
+            for (m = 0; m < 3; m++) { hh[m] = hv[m + 1]; aa[m] = av[m + 1]; }
+        } else {
+            for (m = 0; m < 3; m++) { hh[m] = hv[4 - m]; aa[m] = av[4 - m]; }
+        }
+        hhat = weno3(hh, aa, cfg->weno_eps);
+    } else {
+        hhat = (wf >= 0.0) ? hv[2] : hv[3];
+    }
+    return hhat - kappa * (av[3] - av[2]);
+}
+
+/* L(a) = -sum over axes of (Phi_{j+1/2} - Phi_{j-1/2}).
+ * absorbing = 1: the bottom wall face carries the settling flux -vs*a_0
+ * (outflow per column returned); otherwise walls carry no flux. */
+static void spatial_operator(const grid_t *g, const orc_cfg *cfg, int scheme,
+                             double kappa, double vs, int absorbing,
+                             const double *a, const double *u, double *L,
+                             double *outflow)
+{
+    double *phi = (double *)malloc(sizeof(double) * (size_t)g->dim * g->N);
+    long k;
+    /* phi[ax][k]: flux through the +ax face of node k */
+#pragma omp parallel for schedule(static)
+    for (k = 0; k < g->N; k++) {
+        int p[3], d;
+        node_coords(g, k, p);
+        for (d = 0; d < g->dim; d++) {
+            if (d == g->vert && !cfg->vert_periodic && p[d] == g->n[d] - 1)
+                phi[(long)d * g->N + k] = 0.0; /* top wall: no flux */
+            else
+                phi[(long)d * g->N + k] =
+                    interior_face_flux(g, cfg, scheme, kappa, vs, a, u, p, d);
+        }
+    }
+#pragma omp parallel for schedule(static)
+    for (k = 0; k < g->N; k++) {
+        int p[3], d, gh;
+        double acc = 0.0;
+        node_coords(g, k, p);
+        for (d = 0; d < g->dim; d++) {
+            double right = phi[(long)d * g->N + k], left;
+            if (d == g->vert && !cfg->vert_periodic && p[d] == 0) {
+                left = absorbing ? -vs * a[k] : 0.0; /* bottom wall face */
+            } else {
+                long km = displaced(g, cfg, p, d, -1, &gh);
+                left = phi[(long)d * g->N + km];
+            }
+            acc += right - left;
+        }
+        L[k] = -acc;
+    }
+    if (outflow) {
+        for (k = 0; k < g->ncol; k++) outflow[k] = 0.0;
+        if (absorbing && !cfg->vert_periodic) {
+            for (k = 0; k < g->N; k++) {
+                int p[3];
+                node_coords(g, k, p);
+                if (p[g->vert] == 0) outflow[column_of(g, p)] = vs * a[k];
+            }
+        }
+    }
+    free(phi);
+}
+
+/* ----------------------------------------------------------------------- */
+/* Collision, eq. 18 + 22 (BGK with Guo forcing), and streaming with        */
+/* half-way bounce-back; the moving-wall term is -6 w_i rho_w c_i.u_wall.   */
+/* ----------------------------------------------------------------------- */
+static void collide_stream(const grid_t *g, const orc_cfg *cfg, const double *f,
+                           const double *rho, const double *u,
+                           const double *F, double *fnew)
+{
+    long k;
+    double omega = 1.0 / cfg->tau;
+    double guo = 1.0 - 0.5 / cfg->tau;
+#pragma omp parallel for schedule(static)
+    for (k = 0; k < g->N; k++) {
+        int p[3], i, d;
+        double uk[3], Fk[3], usq = 0.0;
+        node_coords(g, k, p);
+        for (d = 0; d < 3; d++) {
+            uk[d] = u[(long)d * g->N + k];
+            Fk[d] = F[(long)d * g->N + k];
+            if (d >= g->dim) { uk[d] = 0.0; Fk[d] = 0.0; }
+            usq += uk[d] * uk[d];
+        }
+        for (i = 0; i < g->q; i++) {
+            double cu = 0.0, cF = 0.0, uF = 0.0, feq, Fi, fs;
+            int t[3], wall = 0;
+            for (d = 0; d < 3; d++) {
+                cu += g->c[i][d] * uk[d];
+                cF += g->c[i][d] * Fk[d];
+                uF += uk[d] * Fk[d];
+            }
+            if (cfg->shifted)
+                feq = g->w[i] * ((rho[k] - 1.0) +
+                                 rho[k] * (3.0 * cu + 4.5 * cu * cu - 1.5 * usq));
+            else
+                feq = g->w[i] * rho[k] * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+            Fi = guo * g->w[i] * (3.0 * (cF - uF) + 9.0 * cu * cF);
+            fs = f[(long)i * g->N + k];
+            fs = fs - omega * (fs - feq) + Fi;
+            /* destination */
+            for (d = 0; d < 3; d++) t[d] = p[d] + g->c[i][d];
+            for (d = 0; d < g->dim; d++) {
+                if (d != g->vert || cfg->vert_periodic) {
+                    t[d] = ((t[d] % g->n[d]) + g->n[d]) % g->n[d];
+                } else if (t[d] < 0) {
+                    wall = -1;
+                } else if (t[d] >= g->n[d]) {
+                    wall = 1;
+                }
+            }
+            if (wall == 0) {
+                fnew[(long)i * g->N + node_index(g, t)] = fs;
+            } else {
+                double cuw = 0.0;
+                if (wall == 1)
+                    for (d = 0; d < 3; d++) cuw += g->c[i][d] * cfg->u_top[d];
+                fnew[(long)g->opp[i] * g->N + k] = fs - 6.0 * g->w[i] * cuw;
+            }
+        }
+    }
+}
+
+/* ----------------------------------------------------------------------- */
+/* Public entry points                                                      */
+/* ----------------------------------------------------------------------- */
+int orc_lattice(int32_t q, int32_t *c, double *w, int32_t *opp)
+{
+    grid_t g;
+    int i, d;
+    if (set_lattice(q, &g)) return -1;
+    for (i = 0; i < g.q; i++) {
+        for (d = 0; d < 3; d++) c[3 * i + d] = g.c[i][d];
+        w[i] = g.w[i];
+        opp[i] = g.opp[i];
+    }
+    return 0;
+}
+
+int orc_equilibrium(const orc_cfg *cfg, const double *rho, const double *u, double *f)
+{
+    grid_t g;
+    long k;
+    if (setup(cfg, &g)) return -1;
+    for (k = 0; k < g.N; k++) {
+        double r = rho ? rho[k] : 1.0, uk[3] = {0.0, 0.0, 0.0}, usq = 0.0;
+        int i, d;
+        for (d = 0; d < g.dim; d++) {
+            uk[d] = u ? u[(long)d * g.N + k] : 0.0;
+            usq += uk[d] * uk[d];
+        }
+        for (i = 0; i < g.q; i++) {
+            double cu = 0.0, feq;
+            for (d = 0; d < 3; d++) cu += g.c[i][d] * uk[d];
+            feq = g.w[i] * r * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+            f[(long)i * g.N + k] = cfg->shifted ? feq - g.w[i] : feq;
+        }
+    }
+    return 0;
+}
+
+int orc_moments(const orc_cfg *cfg, const double *f, const double *c,
+                const double *s, double *rho, double *u)
+{
+    grid_t g;
+    long k;
+    if (setup(cfg, &g)) return -1;
+    for (k = 0; k < g.N; k++) {
+        double r, uk[3], F[3];
+        int d;
+        moments_at(&g, cfg, f, c, s, k, &r, uk, F);
+        if (rho) rho[k] = r;
+        for (d = 0; d < g.dim; d++) u[(long)d * g.N + k] = uk[d];
+    }
+    return 0;
+}
+
+int orc_rhs_c(const orc_cfg *cfg, const double *a, const double *u,
+              double *out, double *outflow)
+{
+    grid_t g;
+    if (setup(cfg, &g)) return -1;
+    spatial_operator(&g, cfg, cfg->scheme_c, cfg->kappa_c, cfg->vs, 1, a, u,
+                     out, outflow);
+    return 0;
+}
+
+int orc_run(const orc_cfg *cfg, double *f, double *c, double *s, double *dep,
+            const double *u_in, double *u_out, int32_t nsteps)
+{
+    grid_t g;
+    long k, N;
+    int step, d;
+    double *rho, *u, *F, *a1, *a2, *L, *cn, *out0, *out1, *out2, *fnew;
+    if (setup(cfg, &g)) return -1;
+    if (cfg->tau <= 0.5 || nsteps < 0) return -1;
+    if (cfg->frozen && !u_in) return -1;
+    if (cfg->has_s && !s) return -1;
+    N = g.N;
+    rho = (double *)malloc(sizeof(double) * N);
+    u = (double *)calloc((size_t)3 * N, sizeof(double));
+    F = (double *)calloc((size_t)3 * N, sizeof(double));
+    a1 = (double *)malloc(sizeof(double) * N);
+    a2 = (double *)malloc(sizeof(double) * N);
+    L = (double *)malloc(sizeof(double) * N);
+    cn = (double *)malloc(sizeof(double) * N);
+    out0 = (double *)malloc(sizeof(double) * g.ncol);
+    out1 = (double *)malloc(sizeof(double) * g.ncol);
+    out2 = (double *)malloc(sizeof(double) * g.ncol);
+    fnew = cfg->frozen ? NULL : (double *)malloc(sizeof(double) * g.q * N);
+
+    for (step = 0; step < nsteps; step++) {
+        /* 1. moments and force at time level n (used by C, S and collision) */
+        if (cfg->frozen) {
+            for (k = 0; k < (long)g.dim * N; k++) u[k] = u_in[k];
+        } else {
+#pragma omp parallel for schedule(static)
+            for (k = 0; k < N; k++) {
+                double uk[3], Fk[3];
+                int dd;
+                moments_at(&g, cfg, f, c, s, k, &rho[k], uk, Fk);
+                for (dd = 0; dd < 3; dd++) {
+                    u[(long)dd * N + k] = uk[dd];
+                    F[(long)dd * N + k] = Fk[dd];
+                }
+            }
+        }
+        /* 2. C: TVD-RK3 (S21-S23), velocity frozen over the substeps */
+        spatial_operator(&g, cfg, cfg->scheme_c, cfg->kappa_c, cfg->vs, 1, c, u, L, out0);
+        for (k = 0; k < N; k++) a1[k] = c[k] + L[k];
+        spatial_operator(&g, cfg, cfg->scheme_c, cfg->kappa_c, cfg->vs, 1, a1, u, L, out1);
+        for (k = 0; k < N; k++) a2[k] = 0.75 * c[k] + 0.25 * a1[k] + 0.25 * L[k];
+        spatial_operator(&g, cfg, cfg->scheme_c, cfg->kappa_c, cfg->vs, 1, a2, u, L, out2);
+        for (k = 0; k < N; k++)
+            cn[k] = c[k] / 3.0 + 2.0 / 3.0 * a2[k] + 2.0 / 3.0 * L[k];
+        if (dep)
+            for (k = 0; k < g.ncol; k++)
+                dep[k] += out0[k] / 6.0 + out1[k] / 6.0 + 2.0 / 3.0 * out2[k];
+        /* 3. S: forward Euler, first-order upwind, no settling, closed walls */
+        if (cfg->has_s) {
+            spatial_operator(&g, cfg, 2, cfg->kappa_s, 0.0, 0, s, u, L, NULL);
+            for (k = 0; k < N; k++) s[k] = s[k] + L[k];
+        }
+        for (k = 0; k < N; k++) c[k] = cn[k];
+        /* 4-5. collide and stream */
+        if (!cfg->frozen) {
+            collide_stream(&g, cfg, f, rho, u, F, fnew);
+            memcpy(f, fnew, sizeof(double) * g.q * N);
+        }
+    }
+    if (u_out)
+        for (d = 0; d < g.dim; d++)
+            for (k = 0; k < N; k++) u_out[(long)d * N + k] = u[(long)d * N + k];
+
+    free(rho); free(u); free(F); free(a1); free(a2); free(L); free(cn);
+    free(out0); free(out1); free(out2); free(fnew);
+    return 0;
+}
+
+int orc_sums(const orc_cfg *cfg, const double *f, const double *c,
+             const double *s, const double *dep, double *out)
+{
+    grid_t g;
+    long k;
+    int i;
+    if (setup(cfg, &g)) return -1;
+    out[0] = out[1] = out[2] = out[3] = 0.0;
+    for (k = 0; k < g.N; k++) out[0] += c[k];
+    if (s)
+        for (k = 0; k < g.N; k++) out[1] += s[k];
+    if (f)
+        for (k = 0; k < g.N; k++) {
+            double r = cfg->shifted ? 1.0 : 0.0;
+            for (i = 0; i < g.q; i++) r += f[(long)i * g.N + k];
+            out[2] += r;
+        }
+    if (dep)
+        for (k = 0; k < g.ncol; k++) out[3] += dep[k];
+    return 0;
+}

@@ -1,0 +1,72 @@
+/*
+ * lbw_oracle.h -- plain FP64 CPU oracle of the coupled lattice-Boltzmann +
+ * finite-difference transport step (Lemus et al., "Modelling settling-driven
+ * gravitational instabilities at the base of volcanic clouds using the
+ * lattice Boltzmann method", arXiv 2106.07694).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or helper with the HIP path; it exists to be checked against
+ * the paper's closed forms and invariants and then to check the GPU path.
+ *
+ * Layout of every field (same convention as the product library, stated
+ * independently here): x fastest, then y, then z; populations f[q][z][y][x].
+ * The vertical axis (gravity, walls) is y in 2D and z in 3D.
+ *
+ * Every routine returns 0 on success and a negative value on bad arguments.
+ */
+#ifndef LBW_ORACLE_H
+#define LBW_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int32_t q;             /* 9 (D2Q9, 2D) or 19 (D3Q19, 3D) */
+    int32_t nx, ny, nz;    /* nz == 1 in 2D */
+    int32_t vert_periodic; /* 1: vertical axis periodic instead of walls */
+    int32_t frozen;        /* 1: fluid step skipped, node velocity from u_in */
+    int32_t scheme_c;      /* 0 WENO5-JS, 1 WENO3-JS, 2 first-order upwind */
+    int32_t has_s;         /* second scalar S (upwind, forward Euler) */
+    int32_t shifted;       /* populations stored as g_i = f_i - w_i */
+    int32_t reserved;
+    double tau;            /* BGK relaxation time, > 1/2 */
+    double body_force[3];  /* constant force density */
+    double u_top[3];       /* top-wall velocity (moving lid) */
+    double vs;             /* settling speed (downward) */
+    double kappa_c, gp_c;  /* C diffusivity; vertical force -gp_c*C */
+    double kappa_s, gp_s;  /* S diffusivity; vertical force -gp_s*S */
+    double weno_eps;       /* WENO regularisation epsilon */
+} orc_cfg;
+
+/* Lattice table in the documented order: c[q][3], w[q], opp[q]. */
+int orc_lattice(int32_t q, int32_t *c, double *w, int32_t *opp);
+
+/* f <- equilibrium at density rho (NULL: 1) and velocity u[dim][N] (NULL: 0). */
+int orc_equilibrium(const orc_cfg *cfg, const double *rho, const double *u, double *f);
+
+/* rho[N] and u[dim][N] (force-shifted velocity) from f, c, s. */
+int orc_moments(const orc_cfg *cfg, const double *f, const double *c,
+                const double *s, double *rho, double *u);
+
+/* Spatial operator of the C equation for node velocity u[dim][N]:
+ * out[N] = L(a); outflow[columns] = settling flux through the bottom wall. */
+int orc_rhs_c(const orc_cfg *cfg, const double *a, const double *u,
+              double *out, double *outflow);
+
+/* Advance nsteps coupled steps in place.  dep has one entry per bottom
+ * column (nx in 2D, nx*ny in 3D).  u_in is read in frozen mode; u_out
+ * (optional) receives the node velocity used by the last step. */
+int orc_run(const orc_cfg *cfg, double *f, double *c, double *s, double *dep,
+            const double *u_in, double *u_out, int32_t nsteps);
+
+/* out[0..3] = sum C, sum S, sum rho, sum dep (plain sequential sums). */
+int orc_sums(const orc_cfg *cfg, const double *f, const double *c,
+             const double *s, const double *dep, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
