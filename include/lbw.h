@@ -1,0 +1,195 @@
+/*
+ * lbw.h -- C ABI of liblbw.so: the coupled lattice-Boltzmann + WENO step of
+ * Lemus et al., "Modelling settling-driven gravitational instabilities at the
+ * base of volcanic clouds using the lattice Boltzmann method" (arXiv
+ * 2106.07694), as hand-written HIP kernels for AMD Instinct MI355X (gfx950).
+ *
+ * One time step (section 2.3 "Numerical methods" and supplement section 1):
+ *   1. moments rho = sum f_i, rho u = sum f_i c_i + F/2 (eq. 19-20, Guo shift
+ *      of eq. 22) and the buoyancy force F = body + e_v(-gp_c C - gp_s S)
+ *      (eq. 10 linearised in C and S);
+ *   2. particle concentration C: TVD-RK3 (S21-S23) of the conservative
+ *      advection-diffusion-settling equation (eq. 6) with WENO face fluxes
+ *      (S8-S20; fifth-order Jiang-Shu by default), transport velocity
+ *      u - Vs e_v frozen at time level n, central diffusion, absorbing bottom
+ *      wall whose settling flux accumulates in a per-column deposit counter;
+ *   3. optional second scalar S (sugar): first-order upwind in conservative
+ *      form (S5-S6), central diffusion, forward Euler, closed walls;
+ *   4. BGK collision with Guo forcing (eq. 18, 22), tau = nu/cs^2 + 1/2
+ *      (eq. 21), cs^2 = 1/3;
+ *   5. streaming with half-way bounce-back at the bottom and top walls
+ *      (section 2.3.1); a moving top wall adds -6 w_i c_i.u_top.
+ * Lattice units throughout: dx = dt = 1, rho0 = 1.
+ *
+ * Geometry and layout.  Fields are structure-of-arrays with x fastest:
+ * node index k = x + nx*(y + ny*z), N = nx*ny*nz.  Populations f[q][k]
+ * (q-major), velocity u[d][k], scalars C[k], S[k].  The vertical axis (gravity,
+ * walls) is y in 2D (nz = 1) and z in 3D; the lateral axes are periodic.
+ * Deposit: one FP64 value per bottom column, index x (2D) or x + nx*y (3D).
+ *
+ * Population order (fixed):
+ *   D2Q9:  0 rest; 1 (+1,0) 2 (0,+1) 3 (-1,0) 4 (0,-1)
+ *          5 (+1,+1) 6 (-1,+1) 7 (-1,-1) 8 (+1,-1)
+ *   D3Q19: 0 rest; 1 +x 2 -x 3 +y 4 -y 5 +z 6 -z
+ *          7 (+1,+1,0) 8 (-1,-1,0) 9 (+1,-1,0) 10 (-1,+1,0)
+ *          11 (+1,0,+1) 12 (-1,0,-1) 13 (+1,0,-1) 14 (-1,0,+1)
+ *          15 (0,+1,+1) 16 (0,-1,-1) 17 (0,+1,-1) 18 (0,-1,+1)
+ *
+ * Precision.  LBW_FP64 stores f and computes in double.  LBW_FP32_SHIFTED
+ * stores g_i = f_i - w_i (rho0 = 1) and computes in float; the deposit
+ * counter and every reduction stay FP64.  LBW_FP64_SHIFTED is the shifted
+ * algebra in double.
+ *
+ * Streaming is in place (two alternating kernels, "AA" access pattern): after
+ * an odd number of steps the population buffer holds post-collision values in
+ * swapped slots.  Read or write populations only through lbw_export /
+ * lbw_import, which present the canonical pre-collision layout f_i(x, t).
+ *
+ * Ownership.  Every device buffer belongs to the caller and must outlive the
+ * handle.  The library allocates no device memory and never synchronises the
+ * stream except in lbw_reduce.  Calls on one handle must not overlap.
+ *
+ * Errors.  Every int-returning function returns LBW_OK (0) or a negative
+ * LBW_ERR_* code; lbw_last_error() then describes the failure (thread-local
+ * string, valid until the next call on the same thread).  No exception or
+ * abort crosses the ABI.
+ */
+#ifndef LBW_H
+#define LBW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBW_ABI_VERSION 1
+
+enum {
+    LBW_OK = 0,
+    LBW_ERR_INVAL = -1,       /* bad argument or configuration */
+    LBW_ERR_UNSUPPORTED = -2, /* valid request this build does not provide */
+    LBW_ERR_HIP = -3,         /* a HIP runtime call failed */
+    LBW_ERR_NONFINITE = -4    /* a reduction found NaN or Inf */
+};
+
+enum { LBW_D2Q9 = 9, LBW_D3Q19 = 19 };
+enum { LBW_FP64 = 0, LBW_FP32_SHIFTED = 1, LBW_FP64_SHIFTED = 2 };
+enum { LBW_FLUID_LBM = 0, LBW_FLUID_FROZEN = 1 };
+enum { LBW_WENO5 = 0, LBW_WENO3 = 1, LBW_UPWIND1 = 2 };
+enum { LBW_FIELD_F = 0, LBW_FIELD_C = 1, LBW_FIELD_S = 2, LBW_FIELD_U = 3,
+       LBW_FIELD_DEPOSIT = 4 };
+enum { LBW_MASS_C = 0, LBW_MASS_S = 1, LBW_MASS_FLUID = 2, LBW_DEPOSIT = 3 };
+
+/* One run's physics and grid (lattice units). */
+typedef struct {
+    int32_t lattice;       /* LBW_D2Q9 (2D, nz = 1) | LBW_D3Q19 (3D) */
+    int32_t precision;     /* LBW_FP64 | LBW_FP32_SHIFTED | LBW_FP64_SHIFTED */
+    int32_t nx, ny, nz;    /* nx, ny >= 1; vertical extent >= 6 */
+    int32_t vert_periodic; /* 0: bounce-back walls bottom/top; 1: periodic */
+    int32_t fluid_mode;    /* LBW_FLUID_LBM | LBW_FLUID_FROZEN (u is an input,
+                              the populations are not touched) */
+    int32_t scheme_c;      /* LBW_WENO5 | LBW_WENO3 | LBW_UPWIND1 for C */
+    int32_t has_s;         /* 1: transport S and add its buoyancy */
+    int32_t reserved;      /* must be 0 */
+    double tau;            /* BGK relaxation time, > 1/2 (eq. 21) */
+    double body_force[3];  /* constant force density */
+    double u_top[3];       /* top-wall velocity (moving lid) */
+    double vs;             /* settling speed >= 0 (downward) */
+    double kappa_c, gp_c;  /* C diffusivity; vertical force -gp_c*C */
+    double kappa_s, gp_s;  /* S diffusivity; vertical force -gp_s*S */
+    double weno_eps;       /* WENO regularisation, > 0 (1e-6 typical) */
+} lbw_config;
+
+/* One run's device buffers (caller-owned, element type per precision:
+ * double for the FP64 forms, float for LBW_FP32_SHIFTED; deposit is always
+ * double).  Unused pointers may be NULL. */
+typedef struct {
+    void *f;           /* Q*N populations (in place, AA order) */
+    void *c;           /* N: C */
+    void *c_s1;        /* N: RK stage work buffer */
+    void *c_s2;        /* N: RK stage work buffer */
+    void *s;           /* N: S (has_s) */
+    void *s_tmp;       /* N: S work buffer (has_s) */
+    void *u;           /* dim*N: node velocity of the last step; input when
+                          fluid_mode = LBW_FLUID_FROZEN */
+    double *deposit;   /* ncol: settled mass per bottom column (FP64) */
+    void *scratch;     /* reduction partials, >= lbw_scratch_bytes() bytes */
+    size_t scratch_bytes;
+} lbw_buffers;
+
+/* Launch shape of the hot kernels (chosen by the autotuner; 0 = default). */
+typedef struct {
+    int32_t lbm_block;     /* threads per block of the collide-stream kernel */
+    int32_t tile_x;        /* transport tile width (multiple of 64) */
+    int32_t tile_y;        /* transport tile height (rows per block) */
+    int32_t fused;         /* 1: one fused transport kernel per step */
+} lbw_launch;
+
+/* Library ABI version (LBW_ABI_VERSION). */
+int lbw_version(void);
+
+/* Description of the last error on this thread ("" if none). */
+const char *lbw_last_error(void);
+
+/* Bytes of device scratch lbw_reduce needs for these runs. */
+int lbw_scratch_bytes(const lbw_config *cfgs, int32_t nbatch, size_t *out_bytes);
+
+typedef struct lbw_handle lbw_handle;
+
+/* Validate nbatch configurations and their buffers and bind them to a HIP
+ * stream (a hipStream_t passed as void*; NULL = the null stream).
+ * Rejects tau <= 1/2 (BGK stability, eq. 21 and the remark after eq. 23),
+ * a vertical extent < 6 (one WENO5 stencil), negative vs or diffusivities,
+ * kappa above the explicit-diffusion limit 1/(2 dim), |u_top| or vs above the
+ * CFL bound (S7), weno_eps <= 0, NULL required buffers, and, when nbatch > 1,
+ * runs of different lattice, precision, fluid mode, scheme or S option.
+ * Host memory only (freed by lbw_destroy).  *out is NULL on failure. */
+int lbw_create(const lbw_config *cfgs, const lbw_buffers *bufs, int32_t nbatch,
+               void *stream, lbw_handle **out);
+
+/* Release the handle (host memory only).  NULL is accepted. */
+void lbw_destroy(lbw_handle *h);
+
+/* Choose the kernels' launch shape (the autotuner's knob).  Zero fields keep
+ * the defaults; invalid shapes are rejected with LBW_ERR_INVAL. */
+int lbw_set_launch(lbw_handle *h, const lbw_launch *launch);
+int lbw_get_launch(const lbw_handle *h, lbw_launch *launch);
+
+/* Populations of run `run` <- equilibrium at density rho[N] and velocity
+ * u[dim][N] (device arrays of the run's element type; NULL means rho = 1,
+ * u = 0), the initial state of section 2.2 (fluid at rest).  Resets the
+ * in-place streaming parity.  Asynchronous on the handle's stream. */
+int lbw_init_equilibrium(lbw_handle *h, int32_t run, const void *rho, const void *u);
+
+/* Advance every run by nsteps coupled steps (nsteps >= 0).  Asynchronous on
+ * the handle's stream; no host synchronisation, no allocation. */
+int lbw_step(lbw_handle *h, int32_t nsteps);
+
+/* Number of steps taken since creation or the last import of populations. */
+int lbw_steps_done(const lbw_handle *h, int64_t *out);
+
+/* Copy field `field` of run `run` in canonical layout into the device buffer
+ * dst (populations: pre-collision f_i(x, t) -- or g_i for the shifted forms --
+ * in f[q][k] order; u: the last step's node velocity; deposit: FP64 ncol).
+ * Asynchronous on the handle's stream. */
+int lbw_export(lbw_handle *h, int32_t run, int32_t field, void *dst);
+
+/* Overwrite field `field` of run `run` from the canonical device buffer src
+ * (same layouts as lbw_export).  Importing populations resets the streaming
+ * parity and the step counter.  Asynchronous on the handle's stream. */
+int lbw_import(lbw_handle *h, int32_t run, int32_t field, const void *src);
+
+/* FP64 sums per run into out_host[nbatch]: LBW_MASS_C (sum C), LBW_MASS_S
+ * (sum S), LBW_MASS_FLUID (sum rho), LBW_DEPOSIT (sum of the deposit
+ * counters), the particle mass and deposited mass m_b of section 4.3.
+ * Wavefront shuffles, per-block partials, then a fixed-order final pass:
+ * the result is bitwise reproducible.  Synchronises the stream.  Returns
+ * LBW_ERR_NONFINITE if any sum is NaN or Inf (the values are still written). */
+int lbw_reduce(lbw_handle *h, int32_t what, double *out_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,325 @@
+// api.cpp -- the C ABI declared in include/lbw.h: argument validation, the
+// per-step launch sequence and the canonical export/import of fields.  The
+// library never allocates device memory and synchronises only in lbw_reduce.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbw_internal.h"
+
+struct lbw_handle {
+    int nbatch = 0;
+    int q = 9, dim = 2, precision = LBW_FP64, fluid_mode = LBW_FLUID_LBM, scheme = LBW_WENO5;
+    int has_s = 0;
+    hipStream_t stream = nullptr;
+    std::vector<lbw_config> cfg;
+    std::vector<lbw_buffers> buf;
+    std::vector<lbw::RunDev> run;
+    int64_t steps = 0;
+    bool odd = false;  // next collide-stream kernel is the odd one of the pair
+    lbw_launch launch{256, 0, 0, 0};
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...) {
+    char msg[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(msg, sizeof msg, fmt, ap);
+    va_end(ap);
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(LBW_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t elem_size(int precision) { return precision == LBW_FP32_SHIFTED ? 4 : 8; }
+
+int validate(const lbw_config &c, const lbw_buffers &b, int idx) {
+    if (c.lattice != LBW_D2Q9 && c.lattice != LBW_D3Q19)
+        return fail(LBW_ERR_INVAL, "run %d: lattice must be LBW_D2Q9 or LBW_D3Q19", idx);
+    if (c.precision != LBW_FP64 && c.precision != LBW_FP32_SHIFTED && c.precision != LBW_FP64_SHIFTED)
+        return fail(LBW_ERR_INVAL, "run %d: unknown precision %d", idx, c.precision);
+    if (c.reserved != 0) return fail(LBW_ERR_INVAL, "run %d: reserved field must be 0", idx);
+    if (c.nx < 1 || c.ny < 1 || c.nz < 1) return fail(LBW_ERR_INVAL, "run %d: grid sizes must be >= 1", idx);
+    const int dim = c.lattice == LBW_D2Q9 ? 2 : 3;
+    if (dim == 2 && c.nz != 1) return fail(LBW_ERR_INVAL, "run %d: D2Q9 needs nz == 1", idx);
+    const int nv = dim == 2 ? c.ny : c.nz;
+    if (nv < 6) return fail(LBW_ERR_INVAL, "run %d: vertical extent %d < 6 (one WENO5 stencil)", idx, nv);
+    const int64_t N = (int64_t)c.nx * c.ny * c.nz;
+    if (N * (int64_t)c.lattice > (int64_t)1 << 40) return fail(LBW_ERR_INVAL, "run %d: grid too large", idx);
+    if (c.fluid_mode != LBW_FLUID_LBM && c.fluid_mode != LBW_FLUID_FROZEN)
+        return fail(LBW_ERR_INVAL, "run %d: unknown fluid mode", idx);
+    if (c.scheme_c != LBW_WENO5 && c.scheme_c != LBW_WENO3 && c.scheme_c != LBW_UPWIND1)
+        return fail(LBW_ERR_INVAL, "run %d: unknown scheme", idx);
+    if (c.fluid_mode == LBW_FLUID_LBM && !(c.tau > 0.5))
+        return fail(LBW_ERR_INVAL, "run %d: tau = %g must exceed 1/2", idx, c.tau);
+    if (!(c.vs >= 0.0) || c.vs > 1.0) return fail(LBW_ERR_INVAL, "run %d: vs must lie in [0, 1] (CFL)", idx);
+    const double kmax = 1.0 / (2.0 * dim);
+    if (!(c.kappa_c >= 0.0) || c.kappa_c > kmax)
+        return fail(LBW_ERR_INVAL, "run %d: kappa_c must lie in [0, %g]", idx, kmax);
+    if (c.has_s && (!(c.kappa_s >= 0.0) || c.kappa_s > kmax))
+        return fail(LBW_ERR_INVAL, "run %d: kappa_s must lie in [0, %g]", idx, kmax);
+    if (!(c.weno_eps > 0.0)) return fail(LBW_ERR_INVAL, "run %d: weno_eps must be > 0", idx);
+    for (int d = 0; d < 3; ++d) {
+        if (!std::isfinite(c.body_force[d]) || !std::isfinite(c.u_top[d]) || std::fabs(c.u_top[d]) > 1.0)
+            return fail(LBW_ERR_INVAL, "run %d: body force / lid velocity invalid", idx);
+    }
+    if (!std::isfinite(c.gp_c) || !std::isfinite(c.gp_s))
+        return fail(LBW_ERR_INVAL, "run %d: buoyancy coefficients must be finite", idx);
+    if (c.fluid_mode == LBW_FLUID_LBM && !b.f) return fail(LBW_ERR_INVAL, "run %d: f is NULL", idx);
+    if (!b.c || !b.c_s1 || !b.c_s2) return fail(LBW_ERR_INVAL, "run %d: C buffers are NULL", idx);
+    if (!b.u) return fail(LBW_ERR_INVAL, "run %d: u is NULL", idx);
+    if (!b.deposit) return fail(LBW_ERR_INVAL, "run %d: deposit is NULL", idx);
+    if (c.has_s && (!b.s || !b.s_tmp)) return fail(LBW_ERR_INVAL, "run %d: S buffers are NULL", idx);
+    return LBW_OK;
+}
+
+lbw::RunDev make_run(const lbw_config &c, const lbw_buffers &b) {
+    lbw::RunDev r{};
+    r.f = b.f;
+    r.c = b.c;
+    r.c1 = b.c_s1;
+    r.c2 = b.c_s2;
+    r.s = b.s;
+    r.s2 = b.s_tmp;
+    r.u = b.u;
+    r.dep = b.deposit;
+    r.nx = c.nx;
+    r.ny = c.ny;
+    r.nz = c.nz;
+    r.vper = c.vert_periodic ? 1 : 0;
+    r.N = (int64_t)c.nx * c.ny * c.nz;
+    r.ncol = c.lattice == LBW_D2Q9 ? c.nx : (int64_t)c.nx * c.ny;
+    r.has_s = c.has_s ? 1 : 0;
+    r.scheme = c.scheme_c;
+    r.tau = c.tau;
+    r.omega = 1.0 / c.tau;
+    r.guo = 1.0 - 0.5 / c.tau;
+    for (int d = 0; d < 3; ++d) {
+        r.body[d] = c.body_force[d];
+        r.utop[d] = c.u_top[d];
+    }
+    r.vs = c.vs;
+    r.kappa_c = c.kappa_c;
+    r.gp_c = c.gp_c;
+    r.kappa_s = c.kappa_s;
+    r.gp_s = c.gp_s;
+    r.eps = c.weno_eps;
+    return r;
+}
+
+int check_run(const lbw_handle *h, int32_t run) {
+    if (!h) return fail(LBW_ERR_INVAL, "NULL handle");
+    if (run < 0 || run >= h->nbatch) return fail(LBW_ERR_INVAL, "run %d out of range [0, %d)", run, h->nbatch);
+    return LBW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbw_version(void) { return LBW_ABI_VERSION; }
+
+const char *lbw_last_error(void) { return g_err.c_str(); }
+
+int lbw_scratch_bytes(const lbw_config *cfgs, int32_t nbatch, size_t *out_bytes) {
+    if (!cfgs || nbatch < 1 || !out_bytes) return fail(LBW_ERR_INVAL, "bad arguments");
+    *out_bytes = sizeof(double) * ((size_t)nbatch * lbw::kReduceBlocks + (size_t)nbatch);
+    return LBW_OK;
+}
+
+int lbw_create(const lbw_config *cfgs, const lbw_buffers *bufs, int32_t nbatch, void *stream,
+               lbw_handle **out) {
+    g_err.clear();
+    if (!out) return fail(LBW_ERR_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!cfgs || !bufs || nbatch < 1) return fail(LBW_ERR_INVAL, "need nbatch >= 1 configs and buffers");
+    for (int b = 0; b < nbatch; ++b) {
+        const int rc = validate(cfgs[b], bufs[b], b);
+        if (rc) return rc;
+        if (b > 0) {
+            const lbw_config &a = cfgs[0], &c = cfgs[b];
+            if (a.lattice != c.lattice || a.precision != c.precision || a.fluid_mode != c.fluid_mode ||
+                a.scheme_c != c.scheme_c || a.has_s != c.has_s)
+                return fail(LBW_ERR_INVAL, "run %d: batched runs must share lattice, precision, "
+                                           "fluid mode, scheme and S option", b);
+        }
+    }
+    lbw_handle *h = new (std::nothrow) lbw_handle;
+    if (!h) return fail(LBW_ERR_INVAL, "out of host memory");
+    h->nbatch = nbatch;
+    h->q = cfgs[0].lattice;
+    h->dim = h->q == LBW_D2Q9 ? 2 : 3;
+    h->precision = cfgs[0].precision;
+    h->fluid_mode = cfgs[0].fluid_mode;
+    h->scheme = cfgs[0].scheme_c;
+    h->has_s = cfgs[0].has_s;
+    h->stream = (hipStream_t)stream;
+    h->cfg.assign(cfgs, cfgs + nbatch);
+    h->buf.assign(bufs, bufs + nbatch);
+    for (int b = 0; b < nbatch; ++b) h->run.push_back(make_run(cfgs[b], bufs[b]));
+    *out = h;
+    return LBW_OK;
+}
+
+void lbw_destroy(lbw_handle *h) { delete h; }
+
+int lbw_set_launch(lbw_handle *h, const lbw_launch *l) {
+    if (!h || !l) return fail(LBW_ERR_INVAL, "NULL argument");
+    lbw_launch n = h->launch;
+    if (l->lbm_block) {
+        if (l->lbm_block < 64 || l->lbm_block > 1024 || l->lbm_block % 64)
+            return fail(LBW_ERR_INVAL, "lbm_block must be a multiple of 64 in [64, 1024]");
+        n.lbm_block = l->lbm_block;
+    }
+    if (l->tile_x) {
+        if (l->tile_x < 64 || l->tile_x > 1024 || l->tile_x % 64)
+            return fail(LBW_ERR_INVAL, "tile_x must be a multiple of 64 in [64, 1024]");
+        n.tile_x = l->tile_x;
+    }
+    if (l->tile_y) {
+        if (l->tile_y < 1 || l->tile_y > 4096) return fail(LBW_ERR_INVAL, "tile_y must lie in [1, 4096]");
+        n.tile_y = l->tile_y;
+    }
+    n.fused = l->fused ? 1 : 0;
+    h->launch = n;
+    return LBW_OK;
+}
+
+int lbw_get_launch(const lbw_handle *h, lbw_launch *l) {
+    if (!h || !l) return fail(LBW_ERR_INVAL, "NULL argument");
+    *l = h->launch;
+    return LBW_OK;
+}
+
+int lbw_init_equilibrium(lbw_handle *h, int32_t run, const void *rho, const void *u) {
+    int rc = check_run(h, run);
+    if (rc) return rc;
+    if (h->fluid_mode != LBW_FLUID_LBM) return fail(LBW_ERR_INVAL, "frozen fluid has no populations");
+    hipError_t e = lbw::launch_equilibrium(h->q, h->precision, h->run[run], h->odd, rho, u, h->stream);
+    return e == hipSuccess ? LBW_OK : hip_fail(e, "equilibrium");
+}
+
+int lbw_step(lbw_handle *h, int32_t nsteps) {
+    if (!h) return fail(LBW_ERR_INVAL, "NULL handle");
+    if (nsteps < 0) return fail(LBW_ERR_INVAL, "nsteps must be >= 0");
+    for (int32_t s = 0; s < nsteps; ++s) {
+        if (h->fluid_mode == LBW_FLUID_LBM) {
+            for (int b = 0; b < h->nbatch; ++b) {
+                hipError_t e = lbw::launch_collide_stream(h->q, h->precision, h->run[b], h->odd,
+                                                          h->launch.lbm_block, h->stream);
+                if (e != hipSuccess) return hip_fail(e, "collide-stream launch");
+            }
+        }
+        for (int b = 0; b < h->nbatch; ++b) {
+            hipError_t e = lbw::launch_transport(h->dim, h->precision, h->run[b], h->launch, h->stream);
+            if (e != hipSuccess) return hip_fail(e, "transport launch");
+        }
+        if (h->has_s)
+            for (auto &r : h->run) std::swap(r.s, r.s2);
+        if (h->fluid_mode == LBW_FLUID_LBM) h->odd = !h->odd;
+        ++h->steps;
+    }
+    return LBW_OK;
+}
+
+int lbw_steps_done(const lbw_handle *h, int64_t *out) {
+    if (!h || !out) return fail(LBW_ERR_INVAL, "NULL argument");
+    *out = h->steps;
+    return LBW_OK;
+}
+
+int lbw_export(lbw_handle *h, int32_t run, int32_t field, void *dst) {
+    int rc = check_run(h, run);
+    if (rc) return rc;
+    if (!dst) return fail(LBW_ERR_INVAL, "dst is NULL");
+    const lbw::RunDev &r = h->run[run];
+    const size_t es = elem_size(h->precision);
+    hipError_t e = hipSuccess;
+    switch (field) {
+        case LBW_FIELD_F:
+            if (h->fluid_mode != LBW_FLUID_LBM) return fail(LBW_ERR_INVAL, "frozen fluid has no populations");
+            e = lbw::launch_export_f(h->q, h->precision, r, h->odd, dst, h->stream);
+            break;
+        case LBW_FIELD_C: e = hipMemcpyAsync(dst, r.c, r.N * es, hipMemcpyDeviceToDevice, h->stream); break;
+        case LBW_FIELD_S:
+            if (!h->has_s) return fail(LBW_ERR_INVAL, "run has no S");
+            e = hipMemcpyAsync(dst, r.s, r.N * es, hipMemcpyDeviceToDevice, h->stream);
+            break;
+        case LBW_FIELD_U:
+            e = hipMemcpyAsync(dst, r.u, (size_t)h->dim * r.N * es, hipMemcpyDeviceToDevice, h->stream);
+            break;
+        case LBW_FIELD_DEPOSIT:
+            e = hipMemcpyAsync(dst, r.dep, r.ncol * sizeof(double), hipMemcpyDeviceToDevice, h->stream);
+            break;
+        default: return fail(LBW_ERR_INVAL, "unknown field %d", field);
+    }
+    return e == hipSuccess ? LBW_OK : hip_fail(e, "export");
+}
+
+int lbw_import(lbw_handle *h, int32_t run, int32_t field, const void *src) {
+    int rc = check_run(h, run);
+    if (rc) return rc;
+    if (!src) return fail(LBW_ERR_INVAL, "src is NULL");
+    const lbw::RunDev &r = h->run[run];
+    const size_t es = elem_size(h->precision);
+    hipError_t e = hipSuccess;
+    switch (field) {
+        case LBW_FIELD_F:
+            if (h->fluid_mode != LBW_FLUID_LBM) return fail(LBW_ERR_INVAL, "frozen fluid has no populations");
+            e = lbw::launch_import_f(h->q, h->precision, r, h->odd, src, h->stream);
+            break;
+        case LBW_FIELD_C: e = hipMemcpyAsync(r.c, src, r.N * es, hipMemcpyDeviceToDevice, h->stream); break;
+        case LBW_FIELD_S:
+            if (!h->has_s) return fail(LBW_ERR_INVAL, "run has no S");
+            e = hipMemcpyAsync(r.s, src, r.N * es, hipMemcpyDeviceToDevice, h->stream);
+            break;
+        case LBW_FIELD_U:
+            e = hipMemcpyAsync(r.u, src, (size_t)h->dim * r.N * es, hipMemcpyDeviceToDevice, h->stream);
+            break;
+        case LBW_FIELD_DEPOSIT:
+            e = hipMemcpyAsync(r.dep, src, r.ncol * sizeof(double), hipMemcpyDeviceToDevice, h->stream);
+            break;
+        default: return fail(LBW_ERR_INVAL, "unknown field %d", field);
+    }
+    return e == hipSuccess ? LBW_OK : hip_fail(e, "import");
+}
+
+int lbw_reduce(lbw_handle *h, int32_t what, double *out_host) {
+    if (!h || !out_host) return fail(LBW_ERR_INVAL, "NULL argument");
+    if (what < LBW_MASS_C || what > LBW_DEPOSIT) return fail(LBW_ERR_INVAL, "unknown reduction %d", what);
+    if (what == LBW_MASS_S && !h->has_s) return fail(LBW_ERR_INVAL, "run has no S");
+    if (what == LBW_MASS_FLUID && h->fluid_mode != LBW_FLUID_LBM)
+        return fail(LBW_ERR_INVAL, "frozen fluid has no populations");
+    size_t need = 0;
+    lbw_scratch_bytes(h->cfg.data(), h->nbatch, &need);
+    const lbw_buffers &b0 = h->buf[0];
+    if (!b0.scratch || b0.scratch_bytes < need)
+        return fail(LBW_ERR_INVAL, "scratch of run 0 must hold %zu bytes", need);
+    double *scratch = (double *)b0.scratch;
+    hipError_t e = lbw::launch_reduce(h->q, h->precision, h->run.data(), h->nbatch, what, h->odd,
+                                      scratch, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "reduce launch");
+    e = hipMemcpyAsync(out_host, scratch + (size_t)h->nbatch * lbw::kReduceBlocks,
+                       sizeof(double) * h->nbatch, hipMemcpyDeviceToHost, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "reduce copy");
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "reduce sync");
+    for (int b = 0; b < h->nbatch; ++b)
+        if (!std::isfinite(out_host[b])) return fail(LBW_ERR_NONFINITE, "run %d: sum is not finite", b);
+    return LBW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,111 @@
+// lbm_device.h -- device helpers of the in-place streaming scheme shared by
+// the collide-stream, export, reduction and adjoint kernels.
+#pragma once
+
+#include "lbw_internal.h"
+
+namespace lbw {
+
+// Linear index of the node displaced by (dx, dy, dz) from (x, y, z): lateral
+// axes wrap; on the vertical axis with walls the result is -1 below the
+// bottom wall and -2 above the top wall.
+template <int D>
+__device__ __forceinline__ int64_t displaced(const RunDev &r, int x, int y, int z, int dx,
+                                             int dy, int dz) {
+    int xs = x + dx;
+    xs += (xs < 0) ? r.nx : 0;
+    xs -= (xs >= r.nx) ? r.nx : 0;
+    if constexpr (D == 2) {
+        int ys = y + dy;
+        if (r.vper) {
+            ys += (ys < 0) ? r.ny : 0;
+            ys -= (ys >= r.ny) ? r.ny : 0;
+        } else {
+            if (ys < 0) return -1;
+            if (ys >= r.ny) return -2;
+        }
+        return (int64_t)xs + (int64_t)r.nx * ys;
+    } else {
+        int ys = y + dy;
+        ys += (ys < 0) ? r.ny : 0;
+        ys -= (ys >= r.ny) ? r.ny : 0;
+        int zs = z + dz;
+        if (r.vper) {
+            zs += (zs < 0) ? r.nz : 0;
+            zs -= (zs >= r.nz) ? r.nz : 0;
+        } else {
+            if (zs < 0) return -1;
+            if (zs >= r.nz) return -2;
+        }
+        return (int64_t)xs + (int64_t)r.nx * ((int64_t)ys + (int64_t)r.ny * zs);
+    }
+}
+
+// 6 w_i (c_i . u_top): momentum a moving top wall hands to a reflected
+// population (half-way bounce-back with a wall velocity).
+template <int Q>
+__device__ __forceinline__ double lid_term(const RunDev &r, int i) {
+    using L = Lattice<Q>;
+    return 6.0 * L::w[i] * (L::cx[i] * r.utop[0] + L::cy[i] * r.utop[1] + L::cz[i] * r.utop[2]);
+}
+
+// Canonical pre-collision population f_i at node k when the buffer holds the
+// state after an even-step kernel (odd = true) or after an odd-step kernel.
+template <int Q, typename T>
+__device__ __forceinline__ T load_canonical(const RunDev &r, const T *__restrict__ f, int i,
+                                            int64_t k, int x, int y, int z, bool odd) {
+    using L = Lattice<Q>;
+    if (!odd) return f[(int64_t)i * r.N + k];
+    const int64_t src = displaced<L::D>(r, x, y, z, -L::cx[i], -L::cy[i], -L::cz[i]);
+    if (src >= 0) return f[(int64_t)L::opp[i] * r.N + src];
+    T v = f[(int64_t)i * r.N + k];
+    if (src == -2) v += (T)lid_term<Q>(r, i);  // f_i = f*_opp(i) + 6 w_i c_i.u_top
+    return v;
+}
+
+template <int D>
+__device__ __forceinline__ void coords(const RunDev &r, int64_t k, int &x, int &y, int &z) {
+    x = (int)(k % r.nx);
+    const int64_t t = k / r.nx;
+    if constexpr (D == 2) {
+        y = (int)t;
+        z = 0;
+    } else {
+        y = (int)(t % r.ny);
+        z = (int)(t / r.ny);
+    }
+}
+
+// Inverse of load_canonical: place the canonical value v of f_i at node k
+// where the next kernel of the pair expects it.
+template <int Q, typename T>
+__device__ __forceinline__ void store_canonical(const RunDev &r, T *__restrict__ f, int i,
+                                                int64_t k, int x, int y, int z, bool odd, T v) {
+    using L = Lattice<Q>;
+    if (!odd) {
+        f[(int64_t)i * r.N + k] = v;
+        return;
+    }
+    const int64_t src = displaced<L::D>(r, x, y, z, -L::cx[i], -L::cy[i], -L::cz[i]);
+    if (src >= 0) {
+        f[(int64_t)L::opp[i] * r.N + src] = v;
+    } else {
+        if (src == -2) v -= (T)lid_term<Q>(r, i);
+        f[(int64_t)i * r.N + k] = v;
+    }
+}
+
+// Canonical density at node k (shifted storage adds back rho0 = 1).
+template <int Q, typename T>
+__device__ __forceinline__ T node_density(const RunDev &r, const T *__restrict__ f, int64_t k,
+                                          bool odd, bool shifted) {
+    using L = Lattice<Q>;
+    int x, y, z;
+    coords<L::D>(r, k, x, y, z);
+    T s = shifted ? (T)1 : (T)0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) s += load_canonical<Q, T>(r, f, i, k, x, y, z, odd);
+    return s;
+}
+
+}  // namespace lbw

@@ -1,0 +1,79 @@
+// lbw_internal.h -- definitions shared by the HIP translation units of
+// liblbw.so (not part of the public ABI; see include/lbw.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/lbw.h"
+
+namespace lbw {
+
+// ---------------------------------------------------------------------------
+// Lattices (velocity sets, weights, opposite directions) in the order fixed by
+// the public header.  D3Q19 is the lattice of the paper's Fig. 3; D2Q9 is its
+// two-dimensional counterpart.  Weights are the standard second-order ones
+// (cs^2 = 1/3, eq. 21).
+// ---------------------------------------------------------------------------
+template <int Q> struct Lattice;
+
+template <> struct Lattice<9> {
+    static constexpr int D = 2;
+    static constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    static constexpr int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    static constexpr int cz[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    static constexpr int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    static constexpr double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                                    1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+};
+
+template <> struct Lattice<19> {
+    static constexpr int D = 3;
+    static constexpr int cx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    static constexpr int cy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    static constexpr int cz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    static constexpr int opp[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+    static constexpr double w[19] = {1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
+                                     1.0 / 18, 1.0 / 18, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                                     1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                                     1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+};
+
+// ---------------------------------------------------------------------------
+// One run as the kernels see it (passed by value).
+// ---------------------------------------------------------------------------
+struct RunDev {
+    void *f;
+    void *c, *c1, *c2;   // C and the two RK stage buffers
+    void *s, *s2;        // S and its work buffer (current S is `s`)
+    void *u;             // dim*N node velocity
+    double *dep;         // per-column deposit
+    int32_t nx, ny, nz;  // grid
+    int32_t vper;        // vertical axis periodic
+    int64_t N;           // nodes
+    int64_t ncol;        // bottom columns
+    int32_t has_s;
+    int32_t scheme;
+    double tau, omega, guo;          // 1/tau and 1 - 1/(2 tau)
+    double body[3], utop[3];
+    double vs, kappa_c, gp_c, kappa_s, gp_s, eps;
+};
+
+// Launchers (return the launch error, if any).  `odd` selects the second
+// kernel of the in-place streaming pair.
+hipError_t launch_collide_stream(int q, int precision, const RunDev &r, bool odd,
+                                 int block, hipStream_t st);
+hipError_t launch_equilibrium(int q, int precision, const RunDev &r, bool odd, const void *rho,
+                              const void *u, hipStream_t st);
+hipError_t launch_import_f(int q, int precision, const RunDev &r, bool odd, const void *src,
+                           hipStream_t st);
+hipError_t launch_export_f(int q, int precision, const RunDev &r, bool odd, void *dst,
+                           hipStream_t st);
+hipError_t launch_transport(int dim, int precision, const RunDev &r, const lbw_launch &l,
+                            hipStream_t st);
+hipError_t launch_reduce(int q, int precision, const RunDev *runs, int nbatch, int what,
+                         bool odd, double *scratch, hipStream_t st);
+
+constexpr int kReduceBlocks = 256;  // partial sums per run
+
+}  // namespace lbw

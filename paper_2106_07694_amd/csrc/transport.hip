@@ -1,0 +1,154 @@
+// transport.hip -- scalar transport part of the coupled step (supplement
+// section 1): the particle concentration C advances by the TVD-RK3 scheme of
+// S21-S23 with the transport velocity w = u - Vs e_v frozen at time level n,
+//
+//   a1 = C + L(C),  a2 = 3/4 C + 1/4 a1 + 1/4 L(a1),  C+ = 1/3 C + 2/3 a2 + 2/3 L(a2),
+//
+// where L(a) = -sum over axes of the face-flux differences (conservative form
+// of eq. 6).  Faces on the lateral axes wrap periodically.  On the vertical
+// axis with walls, stencils that reach past a wall see the mirror image of the
+// field (zero normal gradient, eq. 14-15) and of the fluid's vertical velocity
+// with its sign flipped (no penetration), settling unchanged; the top wall
+// face carries no flux and the bottom wall face carries the settling flux
+// -Vs a_0 out of the domain into the per-column deposit counter, weighted
+// 1/6, 1/6, 2/3 over the three stages so that sum C + deposit is conserved.
+// S (when present) takes one forward-Euler step of first-order upwind in
+// conservative form (S5-S6) with central diffusion and closed walls.
+//
+// This unit holds the plain global-memory kernels: one thread per node,
+// stencil values read through the caches.
+#include "transport_device.h"
+
+namespace lbw {
+namespace {
+
+template <int D>
+__device__ __forceinline__ void node_coords(const RunDev &r, int64_t k, int &x, int &y, int &z) {
+    x = (int)(k % r.nx);
+    const int64_t t = k / r.nx;
+    if constexpr (D == 2) {
+        y = (int)t;
+        z = 0;
+    } else {
+        y = (int)(t % r.ny);
+        z = (int)(t / r.ny);
+    }
+}
+
+// L(a) at node k.  absorbing: bottom wall face carries -vs*a_0 (C); otherwise
+// the walls are closed (S).
+template <typename T, int D, int SCHEME, bool ABSORB>
+__device__ T spatial_op(const RunDev &r, const T *__restrict__ a, const T *__restrict__ u,
+                        int64_t k, int x, int y, int z, T vs, T kappa, T eps) {
+    T L = 0;
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+        const bool vert = (ax == D - 1);
+        const bool walls = vert && !r.vper;
+        const int j = ax == 0 ? x : (ax == 1 ? y : z);
+        const int n = ax == 0 ? r.nx : (ax == 1 ? r.ny : r.nz);
+        const int64_t stride = ax == 0 ? 1 : (ax == 1 ? (int64_t)r.nx : (int64_t)r.nx * r.ny);
+        T av[7], wv[7];
+#pragma unroll
+        for (int m = 0; m < 7; ++m) {
+            int jj = j + m - 3;
+            bool ghost = false;
+            if (!walls) {
+                jj = ((jj % n) + n) % n;
+            } else if (jj < 0) {
+                jj = -1 - jj;
+                ghost = true;
+            } else if (jj >= n) {
+                jj = 2 * n - 1 - jj;
+                ghost = true;
+            }
+            const int64_t kk = k + (int64_t)(jj - j) * stride;
+            av[m] = a[kk];
+            T uu = u[(int64_t)ax * r.N + kk];
+            if (ghost) uu = -uu;
+            wv[m] = vert ? uu - vs : uu;
+        }
+        const T Fp = (walls && j == n - 1) ? (T)0 : face_flux<T, SCHEME>(av + 1, wv + 1, kappa, eps);
+        const T Fm = (walls && j == 0) ? (ABSORB ? -vs * av[3] : (T)0)
+                                       : face_flux<T, SCHEME>(av, wv, kappa, eps);
+        L -= (Fp - Fm);
+    }
+    return L;
+}
+
+template <typename T, int D, int SCHEME, int STAGE>
+__global__ void __launch_bounds__(256) k_rk_stage(RunDev r) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= r.N) return;
+    int x, y, z;
+    node_coords<D>(r, k, x, y, z);
+    T *__restrict__ C = (T *)r.c;
+    const T *__restrict__ ain = (const T *)(STAGE == 1 ? r.c : (STAGE == 2 ? r.c1 : r.c2));
+    const T *__restrict__ u = (const T *)r.u;
+    const T vs = (T)r.vs;
+    const T L = spatial_op<T, D, SCHEME, true>(r, ain, u, k, x, y, z, vs, (T)r.kappa_c, (T)r.eps);
+    const T a = ain[k];
+    if constexpr (STAGE == 1) {
+        ((T *)r.c1)[k] = a + L;
+    } else if constexpr (STAGE == 2) {
+        ((T *)r.c2)[k] = (T)0.75 * C[k] + (T)0.25 * a + (T)0.25 * L;
+    } else {
+        const T c0 = C[k];
+        const int v = (D == 2) ? y : z;
+        if (!r.vper && v == 0) {
+            // settled mass through the bottom face over the three stages
+            const double o0 = r.vs * (double)c0;
+            const double o1 = r.vs * (double)((const T *)r.c1)[k];
+            const double o2 = r.vs * (double)a;
+            const int64_t col = (D == 2) ? x : (int64_t)x + (int64_t)r.nx * y;
+            r.dep[col] += o0 / 6.0 + o1 / 6.0 + 2.0 / 3.0 * o2;
+        }
+        C[k] = c0 / (T)3 + (T)(2.0 / 3.0) * a + (T)(2.0 / 3.0) * L;
+    }
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_s_euler(RunDev r) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= r.N) return;
+    int x, y, z;
+    node_coords<D>(r, k, x, y, z);
+    const T *__restrict__ s = (const T *)r.s;
+    const T L = spatial_op<T, D, LBW_UPWIND1, false>(r, s, (const T *)r.u, k, x, y, z, (T)0,
+                                                     (T)r.kappa_s, (T)r.eps);
+    ((T *)r.s2)[k] = s[k] + L;
+}
+
+template <typename T, int D, int SCHEME>
+hipError_t transport_t(const RunDev &r, hipStream_t st) {
+    const int block = 256;
+    const dim3 grid((unsigned)((r.N + block - 1) / block));
+    k_rk_stage<T, D, SCHEME, 1><<<grid, block, 0, st>>>(r);
+    k_rk_stage<T, D, SCHEME, 2><<<grid, block, 0, st>>>(r);
+    // S reads u and S^n only; it runs before stage 3 overwrites nothing it needs
+    if (r.has_s) k_s_euler<T, D><<<grid, block, 0, st>>>(r);
+    k_rk_stage<T, D, SCHEME, 3><<<grid, block, 0, st>>>(r);
+    return hipGetLastError();
+}
+
+template <typename T, int D>
+hipError_t transport_d(const RunDev &r, hipStream_t st) {
+    switch (r.scheme) {
+        case LBW_WENO5: return transport_t<T, D, LBW_WENO5>(r, st);
+        case LBW_WENO3: return transport_t<T, D, LBW_WENO3>(r, st);
+        case LBW_UPWIND1: return transport_t<T, D, LBW_UPWIND1>(r, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_transport(int dim, int precision, const RunDev &r, const lbw_launch &l,
+                            hipStream_t st) {
+    (void)l;
+    if (precision == LBW_FP32_SHIFTED)
+        return dim == 2 ? transport_d<float, 2>(r, st) : transport_d<float, 3>(r, st);
+    return dim == 2 ? transport_d<double, 2>(r, st) : transport_d<double, 3>(r, st);
+}
+
+}  // namespace lbw

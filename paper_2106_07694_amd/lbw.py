@@ -1,0 +1,291 @@
+"""ctypes binding of liblbw.so (include/lbw.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  PyTorch provides device memory (tensors) and the HIP stream.  The
+library must have been built (``paper_2106_07694_amd.build``); there is no
+fallback of any kind -- a missing library or GPU raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbw.so")
+
+D2Q9, D3Q19 = 9, 19
+FP64, FP32_SHIFTED, FP64_SHIFTED = 0, 1, 2
+FLUID_LBM, FLUID_FROZEN = 0, 1
+WENO5, WENO3, UPWIND1 = 0, 1, 2
+FIELD_F, FIELD_C, FIELD_S, FIELD_U, FIELD_DEPOSIT = 0, 1, 2, 3, 4
+MASS_C, MASS_S, MASS_FLUID, DEPOSIT = 0, 1, 2, 3
+ERR_INVAL, ERR_UNSUPPORTED, ERR_HIP, ERR_NONFINITE = -1, -2, -3, -4
+
+PRECISIONS = {"fp64": FP64, "fp32_shifted": FP32_SHIFTED, "fp64_shifted": FP64_SHIFTED}
+SCHEMES = {"weno5": WENO5, "weno3": WENO3, "upwind1": UPWIND1}
+
+EXPORTED = ("lbw_version", "lbw_last_error", "lbw_scratch_bytes", "lbw_create", "lbw_destroy",
+            "lbw_set_launch", "lbw_get_launch", "lbw_init_equilibrium", "lbw_step",
+            "lbw_steps_done", "lbw_export", "lbw_import", "lbw_reduce")
+
+
+class LbwError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lbw error {code}: {msg}")
+        self.code = code
+
+
+class CConfig(ctypes.Structure):
+    _fields_ = [
+        ("lattice", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("vert_periodic", ctypes.c_int32), ("fluid_mode", ctypes.c_int32),
+        ("scheme_c", ctypes.c_int32), ("has_s", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("tau", ctypes.c_double), ("body_force", ctypes.c_double * 3),
+        ("u_top", ctypes.c_double * 3), ("vs", ctypes.c_double),
+        ("kappa_c", ctypes.c_double), ("gp_c", ctypes.c_double),
+        ("kappa_s", ctypes.c_double), ("gp_s", ctypes.c_double),
+        ("weno_eps", ctypes.c_double),
+    ]
+
+
+class CBuffers(ctypes.Structure):
+    _fields_ = [
+        ("f", ctypes.c_void_p), ("c", ctypes.c_void_p), ("c_s1", ctypes.c_void_p),
+        ("c_s2", ctypes.c_void_p), ("s", ctypes.c_void_p), ("s_tmp", ctypes.c_void_p),
+        ("u", ctypes.c_void_p), ("deposit", ctypes.c_void_p), ("scratch", ctypes.c_void_p),
+        ("scratch_bytes", ctypes.c_size_t),
+    ]
+
+
+class CLaunch(ctypes.Structure):
+    _fields_ = [("lbm_block", ctypes.c_int32), ("tile_x", ctypes.c_int32),
+                ("tile_y", ctypes.c_int32), ("fused", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load liblbw.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2106_07694_amd.build` (no fallback path exists)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32 = ctypes.c_void_p, ctypes.c_int32
+    lib.lbw_version.restype = ctypes.c_int
+    lib.lbw_last_error.restype = ctypes.c_char_p
+    lib.lbw_scratch_bytes.argtypes = [P, I32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.lbw_create.argtypes = [P, P, I32, P, ctypes.POINTER(ctypes.c_void_p)]
+    lib.lbw_destroy.argtypes = [P]
+    lib.lbw_destroy.restype = None
+    lib.lbw_set_launch.argtypes = [P, ctypes.POINTER(CLaunch)]
+    lib.lbw_get_launch.argtypes = [P, ctypes.POINTER(CLaunch)]
+    lib.lbw_init_equilibrium.argtypes = [P, I32, P, P]
+    lib.lbw_step.argtypes = [P, I32]
+    lib.lbw_steps_done.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
+    lib.lbw_export.argtypes = [P, I32, I32, P]
+    lib.lbw_import.argtypes = [P, I32, I32, P]
+    lib.lbw_reduce.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double)]
+    for name in EXPORTED:
+        getattr(lib, name)
+    _lib = lib
+    return lib
+
+
+def check(rc: int) -> None:
+    if rc != 0:
+        raise LbwError(rc, load().lbw_last_error().decode())
+
+
+@dataclasses.dataclass
+class RunConfig:
+    """Mirror of lbw_config with Python defaults."""
+    lattice: int = D2Q9
+    precision: str = "fp64"
+    nx: int = 64
+    ny: int = 128
+    nz: int = 1
+    vert_periodic: bool = False
+    fluid_mode: int = FLUID_LBM
+    scheme_c: str = "weno5"
+    has_s: bool = False
+    tau: float = 0.6
+    body_force: tuple = (0.0, 0.0, 0.0)
+    u_top: tuple = (0.0, 0.0, 0.0)
+    vs: float = 0.0
+    kappa_c: float = 0.0
+    gp_c: float = 0.0
+    kappa_s: float = 0.0
+    gp_s: float = 0.0
+    weno_eps: float = 1e-6
+
+    @property
+    def dim(self) -> int:
+        return 2 if self.lattice == D2Q9 else 3
+
+    @property
+    def shape(self) -> tuple:
+        return (self.nz, self.ny, self.nx)
+
+    @property
+    def ncol(self) -> int:
+        return self.nx if self.dim == 2 else self.nx * self.ny
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def to_c(self) -> CConfig:
+        c = CConfig()
+        c.lattice, c.precision = self.lattice, PRECISIONS[self.precision]
+        c.nx, c.ny, c.nz = self.nx, self.ny, self.nz
+        c.vert_periodic, c.fluid_mode = int(self.vert_periodic), int(self.fluid_mode)
+        c.scheme_c, c.has_s, c.reserved = SCHEMES[self.scheme_c], int(self.has_s), 0
+        c.tau = self.tau
+        c.body_force = (ctypes.c_double * 3)(*self.body_force)
+        c.u_top = (ctypes.c_double * 3)(*self.u_top)
+        c.vs, c.kappa_c, c.gp_c = self.vs, self.kappa_c, self.gp_c
+        c.kappa_s, c.gp_s, c.weno_eps = self.kappa_s, self.gp_s, self.weno_eps
+        return c
+
+    @staticmethod
+    def from_workload(wl, **over) -> "RunConfig":
+        kw = dict(lattice=wl.q, precision=wl.precision, nx=wl.nx, ny=wl.ny, nz=wl.nz,
+                  tau=wl.tau, vs=wl.vs, kappa_c=wl.kappa_c, gp_c=wl.gp_c, has_s=wl.has_s,
+                  kappa_s=wl.kappa_s, gp_s=wl.gp_s)
+        kw.update(over)
+        return RunConfig(**kw)
+
+
+class Solver:
+    """A batch of runs bound to torch-owned device buffers and a HIP stream."""
+
+    def __init__(self, cfgs, device="cuda", stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("liblbw needs a ROCm GPU; none is visible")
+        lib = load()
+        if isinstance(cfgs, RunConfig):
+            cfgs = [cfgs]
+        self.cfgs = list(cfgs)
+        self.nbatch = len(self.cfgs)
+        self.device = torch.device(device)
+        c0 = self.cfgs[0]
+        self.dtype = torch.float32 if c0.precision == "fp32_shifted" else torch.float64
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._ccfg = (CConfig * self.nbatch)(*[c.to_c() for c in self.cfgs])
+        nbytes = ctypes.c_size_t(0)
+        check(lib.lbw_scratch_bytes(self._ccfg, self.nbatch, ctypes.byref(nbytes)))
+        self.tensors = []
+        cbufs = []
+        for i, c in enumerate(self.cfgs):
+            z = lambda *shape, dt=self.dtype: torch.zeros(shape, dtype=dt, device=self.device)
+            t = {
+                "f": z(c.lattice, *c.shape) if c.fluid_mode == FLUID_LBM else None,
+                "c": z(*c.shape), "c_s1": z(*c.shape), "c_s2": z(*c.shape),
+                "s": z(*c.shape) if c.has_s else None,
+                "s_tmp": z(*c.shape) if c.has_s else None,
+                "u": z(c.dim, *c.shape),
+                "deposit": z(c.ncol, dt=torch.float64),
+                "scratch": z(nbytes.value // 8, dt=torch.float64) if i == 0 else None,
+            }
+            self.tensors.append(t)
+            b = CBuffers()
+            for k in ("f", "c", "c_s1", "c_s2", "s", "s_tmp", "u", "deposit", "scratch"):
+                setattr(b, k, t[k].data_ptr() if t[k] is not None else None)
+            b.scratch_bytes = nbytes.value if i == 0 else 0
+            cbufs.append(b)
+        self._cbuf = (CBuffers * self.nbatch)(*cbufs)
+        h = ctypes.c_void_p()
+        check(lib.lbw_create(self._ccfg, self._cbuf, self.nbatch,
+                             ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self._lib = lib
+
+    # -- lifetime --------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.lbw_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- state -----------------------------------------------------------
+    def _dev(self, x, dtype=None):
+        import torch
+        dt = self.dtype if dtype is None else dtype
+        if isinstance(x, np.ndarray):
+            x = torch.from_numpy(np.ascontiguousarray(x))
+        return x.to(device=self.device, dtype=dt).contiguous()
+
+    def init_equilibrium(self, run=0, rho=None, u=None):
+        keep = [self._dev(rho) if rho is not None else None, self._dev(u) if u is not None else None]
+        check(self._lib.lbw_init_equilibrium(
+            self._h, run, keep[0].data_ptr() if keep[0] is not None else None,
+            keep[1].data_ptr() if keep[1] is not None else None))
+        self.stream.synchronize()
+
+    def set_field(self, name, value, run=0):
+        fid = {"f": FIELD_F, "c": FIELD_C, "s": FIELD_S, "u": FIELD_U, "deposit": FIELD_DEPOSIT}[name]
+        import torch
+        dt = torch.float64 if name == "deposit" else None
+        src = self._dev(value, dt)
+        check(self._lib.lbw_import(self._h, run, fid, src.data_ptr()))
+        self.stream.synchronize()
+
+    def field(self, name, run=0):
+        """Canonical copy of a field as a new device tensor."""
+        import torch
+        c = self.cfgs[run]
+        shapes = {"f": (c.lattice, *c.shape), "c": c.shape, "s": c.shape, "u": (c.dim, *c.shape),
+                  "deposit": (c.ncol,)}
+        fid = {"f": FIELD_F, "c": FIELD_C, "s": FIELD_S, "u": FIELD_U, "deposit": FIELD_DEPOSIT}[name]
+        dt = torch.float64 if name == "deposit" else self.dtype
+        out = torch.empty(shapes[name], dtype=dt, device=self.device)
+        check(self._lib.lbw_export(self._h, run, fid, out.data_ptr()))
+        self.stream.synchronize()
+        return out
+
+    def step(self, n=1):
+        check(self._lib.lbw_step(self._h, int(n)))
+
+    def steps_done(self) -> int:
+        v = ctypes.c_int64(0)
+        check(self._lib.lbw_steps_done(self._h, ctypes.byref(v)))
+        return v.value
+
+    def set_launch(self, lbm_block=0, tile_x=0, tile_y=0, fused=0):
+        lc = CLaunch(lbm_block, tile_x, tile_y, fused)
+        check(self._lib.lbw_set_launch(self._h, ctypes.byref(lc)))
+
+    def get_launch(self) -> dict:
+        lc = CLaunch()
+        check(self._lib.lbw_get_launch(self._h, ctypes.byref(lc)))
+        return {"lbm_block": lc.lbm_block, "tile_x": lc.tile_x, "tile_y": lc.tile_y, "fused": lc.fused}
+
+    def reduce(self, what) -> np.ndarray:
+        out = (ctypes.c_double * self.nbatch)()
+        check(self._lib.lbw_reduce(self._h, int(what), out))
+        return np.array(out[:], dtype=np.float64)
+
+    def setup_workload(self, wl, run=0, seed=None):
+        """Initial state of a seeded workload: two-layer scalars, fluid at rest."""
+        from . import workloads
+        c, s = workloads.initial_scalars(wl, seed)
+        self.set_field("c", c, run)
+        if s is not None:
+            self.set_field("s", s, run)
+        if self.cfgs[run].fluid_mode == FLUID_LBM:
+            self.init_equilibrium(run)

@@ -1,0 +1,140 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function the public header declares, and rejects invalid runs."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2106_07694_amd import lbw
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "lbw.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\s*\*)\s*\*?\s*(lbw_\w+)\s*\(",
+                                 text, re.M)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = lbw.load()
+    names = _declared()
+    assert "lbw_step" in names and "lbw_create" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(lbw.EXPORTED)
+
+
+def test_version():
+    assert lbw.load().lbw_version() == 1
+
+
+def _fake_buffers(cfg: lbw.RunConfig) -> lbw.CBuffers:
+    b = lbw.CBuffers()
+    for i, k in enumerate(("f", "c", "c_s1", "c_s2", "s", "s_tmp", "u", "deposit", "scratch")):
+        setattr(b, k, 0x10000 * (i + 1))   # never dereferenced: create only validates
+    b.scratch_bytes = 1 << 20
+    return b
+
+
+def _create(cfgs):
+    lib = lbw.load()
+    arr = (lbw.CConfig * len(cfgs))(*[c.to_c() for c in cfgs])
+    bufs = (lbw.CBuffers * len(cfgs))(*[_fake_buffers(c) for c in cfgs])
+    h = ctypes.c_void_p()
+    rc = lib.lbw_create(arr, bufs, len(cfgs), None, ctypes.byref(h))
+    msg = lib.lbw_last_error().decode()
+    if h:
+        lib.lbw_destroy(h)
+    return rc, msg
+
+
+def test_valid_config_creates():
+    assert _create([lbw.RunConfig()])[0] == 0
+    assert _create([lbw.RunConfig(lattice=19, nx=8, ny=8, nz=16, precision="fp32_shifted")])[0] == 0
+
+
+@pytest.mark.parametrize("bad,frag", [
+    (dict(tau=0.5), "tau"),
+    (dict(tau=0.3), "tau"),
+    (dict(ny=5), "vertical"),
+    (dict(nz=2), "nz"),
+    (dict(lattice=27), "lattice"),
+    (dict(vs=-1e-3), "vs"),
+    (dict(vs=1.5), "vs"),
+    (dict(kappa_c=0.3), "kappa_c"),
+    (dict(kappa_c=-1.0), "kappa_c"),
+    (dict(weno_eps=0.0), "weno_eps"),
+    (dict(u_top=(2.0, 0, 0)), "lid"),
+    (dict(nx=0), "grid"),
+])
+def test_invalid_configs_rejected(bad, frag):
+    rc, msg = _create([lbw.RunConfig(**bad)])
+    assert rc == lbw.ERR_INVAL and frag in msg, (rc, msg)
+
+
+def test_bad_precision_and_scheme_codes():
+    lib = lbw.load()
+    c = lbw.RunConfig().to_c()
+    c.precision = 7
+    b = _fake_buffers(lbw.RunConfig())
+    h = ctypes.c_void_p()
+    assert lib.lbw_create(ctypes.byref(c), ctypes.byref(b), 1, None, ctypes.byref(h)) == lbw.ERR_INVAL
+    assert not h
+    c = lbw.RunConfig().to_c()
+    c.reserved = 1
+    assert lib.lbw_create(ctypes.byref(c), ctypes.byref(b), 1, None, ctypes.byref(h)) == lbw.ERR_INVAL
+
+
+def test_missing_buffers_rejected():
+    lib = lbw.load()
+    cfg = lbw.RunConfig(has_s=True)
+    c = cfg.to_c()
+    for field in ("f", "c", "c_s2", "u", "deposit", "s_tmp"):
+        b = _fake_buffers(cfg)
+        setattr(b, field, None)
+        h = ctypes.c_void_p()
+        assert lib.lbw_create(ctypes.byref(c), ctypes.byref(b), 1, None, ctypes.byref(h)) == lbw.ERR_INVAL
+        assert not h
+
+
+def test_batch_must_be_homogeneous():
+    a = lbw.RunConfig(precision="fp32_shifted")
+    rc, _ = _create([a, lbw.RunConfig(precision="fp32_shifted", nx=128, ny=256)])
+    assert rc == 0
+    rc, msg = _create([a, lbw.RunConfig(precision="fp64")])
+    assert rc == lbw.ERR_INVAL and "batched" in msg
+
+
+def test_launch_shape_validation():
+    lib = lbw.load()
+    cfg = lbw.RunConfig()
+    c, b = cfg.to_c(), _fake_buffers(cfg)
+    h = ctypes.c_void_p()
+    assert lib.lbw_create(ctypes.byref(c), ctypes.byref(b), 1, None, ctypes.byref(h)) == 0
+    try:
+        ok = lbw.CLaunch(512, 128, 16, 1)
+        assert lib.lbw_set_launch(h, ctypes.byref(ok)) == 0
+        got = lbw.CLaunch()
+        assert lib.lbw_get_launch(h, ctypes.byref(got)) == 0
+        assert (got.lbm_block, got.tile_x, got.tile_y, got.fused) == (512, 128, 16, 1)
+        for bad in (lbw.CLaunch(100, 0, 0, 0), lbw.CLaunch(2048, 0, 0, 0), lbw.CLaunch(0, 96, 0, 0)):
+            assert lib.lbw_set_launch(h, ctypes.byref(bad)) == lbw.ERR_INVAL
+        assert lib.lbw_step(h, -1) == lbw.ERR_INVAL
+        v = ctypes.c_int64(-1)
+        assert lib.lbw_steps_done(h, ctypes.byref(v)) == 0 and v.value == 0
+        assert lib.lbw_export(h, 5, 1, ctypes.c_void_p(0x1000)) == lbw.ERR_INVAL
+        assert lib.lbw_export(h, 0, 9, ctypes.c_void_p(0x1000)) == lbw.ERR_INVAL
+        assert lib.lbw_export(h, 0, lbw.FIELD_S, ctypes.c_void_p(0x1000)) == lbw.ERR_INVAL
+    finally:
+        lib.lbw_destroy(h)
+
+
+def test_scratch_bytes():
+    lib = lbw.load()
+    arr = (lbw.CConfig * 3)(*[lbw.RunConfig().to_c()] * 3)
+    n = ctypes.c_size_t()
+    assert lib.lbw_scratch_bytes(arr, 3, ctypes.byref(n)) == 0
+    assert n.value >= 3 * 8
+    assert lib.lbw_scratch_bytes(arr, 0, ctypes.byref(n)) == lbw.ERR_INVAL

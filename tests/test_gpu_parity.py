@@ -1,0 +1,116 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs, element by element.
+
+FP64 forms must agree to 1e-12 relative (max |gpu - oracle| / max |oracle|
+per field).  The velocity is a difference of populations a hundred thousand
+times larger than itself early in a run, so its bound is 1e-12 relative plus
+an absolute floor of 64 units in the last place of the largest population.
+Cases span several blocks with ragged tails, both lattices, walls and
+periodic vertical axes, a moving lid and body force, the frozen
+(transport-only) mode with every scheme, the S scalar and the shifted form.
+"""
+import numpy as np
+import pytest
+
+from paper_2106_07694_amd import lbw, workloads as W
+
+from parity import as_input, compare, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+TOL64 = 1e-12
+
+
+def _check(cfg, nsteps, c0, s0=None, u=None, f0=None, tol=TOL64, launch=None):
+    c0, s0, u = as_input(c0, cfg), as_input(s0, cfg), as_input(u, cfg)
+    g = run_gpu(cfg, c0, s0, u, f0, nsteps, launch=launch)
+    o = run_oracle(cfg, c0, s0, u, f0, nsteps)
+    errs = compare(g, o)
+    print(f"\n{cfg.lattice} {cfg.precision} {cfg.nx}x{cfg.ny}x{cfg.nz} steps={nsteps}: {errs}")
+    bad = {k: v for k, v in errs.items() if k != "u" and not v <= tol}
+    assert not bad, errs
+    if "f" in o:
+        du = float(np.max(np.abs(g["u"] - o["u"])))
+        fscale = float(np.max(np.abs(o["f"])))
+        bound = tol * float(np.max(np.abs(o["u"]))) + 64 * np.finfo(np.float64).eps * fscale
+        assert du <= bound, (du, bound, errs)
+    else:
+        assert errs["u"] == 0.0       # frozen: the velocity is an input
+    return errs
+
+
+@pytest.mark.parametrize("nsteps", [1, 10, 100, 1000])
+def test_c1_full_fp64(nsteps):
+    """2D D2Q9 FP64 on 64x128, the seeded two-layer workload."""
+    wl = W.C1
+    cfg = lbw.RunConfig.from_workload(wl)
+    c0, _ = W.initial_scalars(wl)
+    _check(cfg, nsteps, c0)
+
+
+def _rng_fields(cfg, seed):
+    rng = np.random.default_rng(seed)
+    c0 = rng.uniform(0, 1, cfg.shape)
+    s0 = rng.uniform(0, 1, cfg.shape) if cfg.has_s else None
+    return c0, s0
+
+
+@pytest.mark.parametrize("kw", [
+    dict(nx=37, ny=29),                                             # ragged tail
+    dict(nx=37, ny=29, vert_periodic=True),
+    dict(nx=33, ny=21, u_top=(0.02, 0, 0), body_force=(1e-4, 0, 0)),
+    dict(nx=1, ny=6),                                               # degenerate lateral, minimal height
+    dict(nx=64, ny=40, has_s=True, kappa_s=1e-3, gp_s=-2e-4),
+    dict(nx=40, ny=24, precision="fp64_shifted", has_s=True, kappa_s=1e-3, gp_s=2e-4),
+])
+def test_d2q9_fp64_variants(kw):
+    base = dict(tau=0.6, vs=2e-3, kappa_c=2e-3, gp_c=5e-4)
+    base.update(kw)
+    cfg = lbw.RunConfig(**base)
+    c0, s0 = _rng_fields(cfg, 3)
+    _check(cfg, 25, c0, s0)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(nx=12, ny=10, nz=16),
+    dict(nx=9, ny=7, nz=11, vert_periodic=True),
+    dict(nx=8, ny=6, nz=12, u_top=(0.02, -0.01, 0), body_force=(1e-4, 0, 2e-5)),
+    dict(nx=10, ny=6, nz=8, precision="fp64_shifted", has_s=True, kappa_s=1e-3, gp_s=1e-4),
+])
+def test_d3q19_fp64_variants(kw):
+    base = dict(lattice=19, tau=0.55, vs=2e-3, kappa_c=2e-3, gp_c=5e-4)
+    base.update(kw)
+    cfg = lbw.RunConfig(**base)
+    c0, s0 = _rng_fields(cfg, 4)
+    _check(cfg, 20, c0, s0)
+
+
+@pytest.mark.parametrize("lattice", [9, 19])
+@pytest.mark.parametrize("scheme", ["weno5", "weno3", "upwind1"])
+@pytest.mark.parametrize("vper", [False, True])
+def test_frozen_transport(lattice, scheme, vper):
+    shape = dict(nx=29, ny=23) if lattice == 9 else dict(nx=11, ny=9, nz=13)
+    cfg = lbw.RunConfig(lattice=lattice, fluid_mode=lbw.FLUID_FROZEN, scheme_c=scheme,
+                        vert_periodic=vper, vs=0.03, kappa_c=5e-3, has_s=True, kappa_s=2e-3,
+                        **shape)
+    rng = np.random.default_rng(5)
+    c0, s0 = _rng_fields(cfg, 6)
+    u = 0.05 * rng.standard_normal((cfg.dim,) + cfg.shape)
+    _check(cfg, 15, c0, s0, u)
+
+
+def test_zero_steps_is_identity():
+    cfg = lbw.RunConfig(nx=16, ny=12, vs=1e-3, kappa_c=1e-3, gp_c=1e-4)
+    c0, _ = _rng_fields(cfg, 7)
+    errs = _check(cfg, 0, c0)
+    assert errs["c"] == 0.0
+
+
+@pytest.mark.parametrize("lbm_block", [64, 128, 512, 1024])
+def test_launch_shapes_give_identical_bits(lbm_block):
+    wl = W.C1.replace(nx=48, ny=40)
+    cfg = lbw.RunConfig.from_workload(wl)
+    c0, _ = W.initial_scalars(wl)
+    ref = run_gpu(cfg, c0, nsteps=7)
+    got = run_gpu(cfg, c0, nsteps=7, launch=dict(lbm_block=lbm_block))
+    for k in ref:
+        assert np.array_equal(ref[k], got[k]), k
