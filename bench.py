@@ -1,0 +1,212 @@
+"""Benchmark of the coupled LBM + WENO step on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 3d|2d]
+
+A step is one coupled time step of the whole hot path: moments + force,
+BGK-Guo collide + in-place stream (D3Q19 or D2Q9), and the three TVD-RK3
+WENO5 stages of the particle concentration (plus the S update in 2D), with
+inputs already resident in device memory.  The default workload is the 3D
+D3Q19 FP32 (shifted populations) run on 256x256x512 cells; the 2D D2Q9 FP32
+run with the second scalar S on 1024x2048 is timed in the same invocation
+and reported under "also".  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+METRIC = "coupled LBM+WENO MLUPS & HBM GB/s vs roofline; adjoint/forward time ratio"
+PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+
+
+def _alg_bytes(wl) -> dict:
+    """Algorithmic bytes per cell update (minimum the method must move).
+
+    step: read + write every population and every transported scalar once.
+    collide_stream kernel: read + write every population, read the scalars
+    that set the buoyancy force.
+    """
+    s = 4 if wl.precision == "fp32_shifted" else 8
+    nsc = 2 if wl.has_s else 1
+    return {"step": 2 * wl.q * s + 2 * nsc * s,
+            "collide_stream": 2 * wl.q * s + nsc * s}
+
+
+def _kernel_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("lbm.hip", "lbm_device.h", "lbw_internal.h"):
+        with open(os.path.join(ROOT, "paper_2106_07694_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(wl_name: str, kernel: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel source; else None."""
+    try:
+        with open(PROFILE_COUNTERS) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = d.get(wl_name, {}).get(kernel)
+    if not e or e.get("source_hash") != _kernel_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def run_gpu(wl, steps: int, warmup: int) -> dict:
+    import torch
+    from paper_2106_07694_amd import lbw
+
+    cfg = lbw.RunConfig.from_workload(wl)
+    sol = lbw.Solver(cfg)
+    tuned = _tuned_launch(wl)
+    if tuned:
+        sol.set_launch(**tuned)
+    sol.setup_workload(wl)
+    sol.step(warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    sol.timing_begin()
+    torch.cuda.synchronize()
+    start.record(sol.stream)
+    sol.step(steps)
+    stop.record(sol.stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    phases = sol.timing_end()
+    # untimed sanity: the particle budget must close
+    mass = sol.reduce(lbw.MASS_C)[0] + sol.reduce(lbw.DEPOSIT)[0]
+    sol.close()
+    cells = wl.cells
+    ab = _alg_bytes(wl)
+    avg_cs_s = phases["collide_stream_ms"] / max(phases["steps"], 1) * 1e-3
+    achieved = cells * ab["collide_stream"] / avg_cs_s / 1e9
+    traffic = _traffic(wl.name, "collide_stream")
+    return {
+        "mlups": cells * steps / (ms * 1e-3) / 1e6,
+        "ms_per_step": ms / steps,
+        "phase_ms_per_step": {"collide_stream": phases["collide_stream_ms"] / max(phases["steps"], 1),
+                              "transport": phases["transport_ms"] / max(phases["steps"], 1)},
+        "step_alg_gbs": cells * ab["step"] * steps / (ms * 1e-3) / 1e9,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "collide_stream", "alg_bytes_per_cell": ab["collide_stream"],
+                     "cells_per_launch": cells},
+        "particle_budget": mass,
+    }
+
+
+def _tuned_launch(wl):
+    path = os.path.join(ROOT, "paper_2106_07694_amd", "tuned.json")
+    try:
+        with open(path) as fh:
+            return json.load(fh).get(wl.name)
+    except (OSError, ValueError):
+        return None
+
+
+def cpu_baseline(wl, nz_crop: int, ny_crop: int, steps: int) -> dict:
+    """The FP64 oracle as it stands, timed on the host cores on a crop of
+    the workload (vertical extent cut), reported as MLUPS."""
+    import oracle
+    from paper_2106_07694_amd import workloads as W
+
+    sample = wl.replace(nz=nz_crop) if wl.dim == 3 else wl.replace(ny=ny_crop)
+    ocfg = oracle.OracleConfig(q=sample.q, nx=sample.nx, ny=sample.ny, nz=sample.nz,
+                               shifted=True, tau=sample.tau, vs=sample.vs,
+                               kappa_c=sample.kappa_c, gp_c=sample.gp_c, has_s=sample.has_s,
+                               kappa_s=sample.kappa_s, gp_s=sample.gp_s)
+    c, s = W.initial_scalars(sample)
+    f = oracle.equilibrium(ocfg)
+    t0 = time.perf_counter()
+    oracle.run(ocfg, f, c, s, nsteps=steps)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
+    return {"value": sample.cells * steps / dt / 1e6, "unit": "MLUPS", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{steps} FP64 oracle steps on a {sample.nx}x{sample.ny}x{sample.nz} crop "
+                      f"of the workload ({dt:.1f} s)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", choices=["3d", "2d"], default="3d")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-also", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}).", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2106_07694_amd import lbw, workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        return 1
+    if not os.path.exists(lbw.LIB_PATH):
+        from paper_2106_07694_amd import build
+        build.build()
+
+    main_wl, other = (W.C3, W.C2) if args.workload == "3d" else (W.C2, W.C3)
+    print(f"[bench] {main_wl.name}: warmup {args.warmup}, timing {args.steps} steps", file=sys.stderr,
+          flush=True)
+    res = run_gpu(main_wl, args.steps, args.warmup)
+    print(f"[bench] {main_wl.name}: {res['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+    also = None
+    if not args.no_also:
+        o = run_gpu(other, args.steps, args.warmup)
+        print(f"[bench] {other.name}: {o['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        also = {"workload": other.name, "value": o["mlups"], "unit": "MLUPS",
+                "ms_per_step": o["ms_per_step"], "phase_ms_per_step": o["phase_ms_per_step"],
+                "step_alg_gbs": o["step_alg_gbs"], "roofline": o["roofline"]}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = (cpu_baseline(main_wl, nz_crop=32, ny_crop=0, steps=4) if main_wl.dim == 3
+               else cpu_baseline(main_wl, nz_crop=0, ny_crop=512, steps=16))
+        print(f"[bench] cpu baseline: {cpu['value']:.2f} MLUPS on {cpu['cores']} cores",
+              file=sys.stderr, flush=True)
+    line = {
+        "metric": METRIC,
+        "value": res["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if main_wl.precision == "fp32_shifted" else "f64",
+        "data": "synthetic (seeded two-layer initial state, fluid at rest)",
+        "config": {"workload": main_wl.name, "lattice": f"D{main_wl.dim}Q{main_wl.q}",
+                   "grid": [main_wl.nx, main_wl.ny, main_wl.nz], "cells": main_wl.cells,
+                   "precision": main_wl.precision, "scheme": "WENO5-JS + TVD-RK3",
+                   "parallelism": "single GPU"},
+        "phase_ms_per_step": res["phase_ms_per_step"],
+        "step_alg_gbs": res["step_alg_gbs"],
+        "step_alg_frac": res["step_alg_gbs"] / HBM_PEAK_GBS,
+        "roofline": res["roofline"],
+        "cpu_baseline": cpu,
+        "also": also,
+    }
+    print(json.dumps(line))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

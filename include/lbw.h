@@ -81,6 +81,7 @@ enum { LBW_WENO5 = 0, LBW_WENO3 = 1, LBW_UPWIND1 = 2 };
 enum { LBW_FIELD_F = 0, LBW_FIELD_C = 1, LBW_FIELD_S = 2, LBW_FIELD_U = 3,
        LBW_FIELD_DEPOSIT = 4 };
 enum { LBW_MASS_C = 0, LBW_MASS_S = 1, LBW_MASS_FLUID = 2, LBW_DEPOSIT = 3 };
+enum { LBW_PHASE_COLLIDE_STREAM = 0, LBW_PHASE_TRANSPORT = 1, LBW_NPHASES = 2 };
 
 /* One run's physics and grid (lattice units). */
 typedef struct {
@@ -188,6 +189,16 @@ int lbw_import(lbw_handle *h, int32_t run, int32_t field, const void *src);
  * the result is bitwise reproducible.  Synchronises the stream.  Returns
  * LBW_ERR_NONFINITE if any sum is NaN or Inf (the values are still written). */
 int lbw_reduce(lbw_handle *h, int32_t what, double *out_host);
+
+/* Per-phase GPU time of the lbw_step calls made between lbw_timing_begin and
+ * lbw_timing_end: HIP events are recorded on the handle's stream around the
+ * collide-stream launches and around the transport launches of every step.
+ * lbw_timing_end waits for the last event and writes the summed milliseconds
+ * per phase to ms_out[LBW_NPHASES] and the number of steps timed to *steps.
+ * The events are host-side objects created by the runtime (no device memory
+ * is allocated); timing adds two event records per phase and step. */
+int lbw_timing_begin(lbw_handle *h);
+int lbw_timing_end(lbw_handle *h, double *ms_out, int64_t *steps);
 
 #ifdef __cplusplus
 }

@@ -23,6 +23,8 @@ struct lbw_handle {
     int64_t steps = 0;
     bool odd = false;  // next collide-stream kernel is the odd one of the pair
     lbw_launch launch{256, 0, 0, 0};
+    bool timing = false;
+    std::vector<hipEvent_t> events;  // 2 per phase per timed step
 };
 
 namespace {
@@ -174,7 +176,11 @@ int lbw_create(const lbw_config *cfgs, const lbw_buffers *bufs, int32_t nbatch, 
     return LBW_OK;
 }
 
-void lbw_destroy(lbw_handle *h) { delete h; }
+void lbw_destroy(lbw_handle *h) {
+    if (!h) return;
+    for (hipEvent_t ev : h->events) (void)hipEventDestroy(ev);
+    delete h;
+}
 
 int lbw_set_launch(lbw_handle *h, const lbw_launch *l) {
     if (!h || !l) return fail(LBW_ERR_INVAL, "NULL argument");
@@ -212,10 +218,25 @@ int lbw_init_equilibrium(lbw_handle *h, int32_t run, const void *rho, const void
     return e == hipSuccess ? LBW_OK : hip_fail(e, "equilibrium");
 }
 
+namespace {
+// Record one timing event on the handle's stream (timing mode only).
+int mark(lbw_handle *h) {
+    if (!h->timing) return LBW_OK;
+    hipEvent_t ev;
+    hipError_t e = hipEventCreate(&ev);
+    if (e != hipSuccess) return hip_fail(e, "event create");
+    h->events.push_back(ev);
+    e = hipEventRecord(ev, h->stream);
+    return e == hipSuccess ? LBW_OK : hip_fail(e, "event record");
+}
+}  // namespace
+
 int lbw_step(lbw_handle *h, int32_t nsteps) {
     if (!h) return fail(LBW_ERR_INVAL, "NULL handle");
     if (nsteps < 0) return fail(LBW_ERR_INVAL, "nsteps must be >= 0");
+    int rc;
     for (int32_t s = 0; s < nsteps; ++s) {
+        if ((rc = mark(h))) return rc;
         if (h->fluid_mode == LBW_FLUID_LBM) {
             for (int b = 0; b < h->nbatch; ++b) {
                 hipError_t e = lbw::launch_collide_stream(h->q, h->precision, h->run[b], h->odd,
@@ -223,16 +244,50 @@ int lbw_step(lbw_handle *h, int32_t nsteps) {
                 if (e != hipSuccess) return hip_fail(e, "collide-stream launch");
             }
         }
+        if ((rc = mark(h))) return rc;
+        if ((rc = mark(h))) return rc;
         for (int b = 0; b < h->nbatch; ++b) {
             hipError_t e = lbw::launch_transport(h->dim, h->precision, h->run[b], h->launch, h->stream);
             if (e != hipSuccess) return hip_fail(e, "transport launch");
         }
+        if ((rc = mark(h))) return rc;
         if (h->has_s)
             for (auto &r : h->run) std::swap(r.s, r.s2);
         if (h->fluid_mode == LBW_FLUID_LBM) h->odd = !h->odd;
         ++h->steps;
     }
     return LBW_OK;
+}
+
+int lbw_timing_begin(lbw_handle *h) {
+    if (!h) return fail(LBW_ERR_INVAL, "NULL handle");
+    for (hipEvent_t ev : h->events) (void)hipEventDestroy(ev);
+    h->events.clear();
+    h->timing = true;
+    return LBW_OK;
+}
+
+int lbw_timing_end(lbw_handle *h, double *ms_out, int64_t *steps) {
+    if (!h || !ms_out || !steps) return fail(LBW_ERR_INVAL, "NULL argument");
+    h->timing = false;
+    for (int p = 0; p < LBW_NPHASES; ++p) ms_out[p] = 0.0;
+    *steps = (int64_t)(h->events.size() / 4);
+    int rc = LBW_OK;
+    if (!h->events.empty()) {
+        hipError_t e = hipEventSynchronize(h->events.back());
+        if (e != hipSuccess) rc = hip_fail(e, "event sync");
+        for (size_t i = 0; rc == LBW_OK && i + 3 < h->events.size(); i += 4) {
+            float a = 0.f, b = 0.f;
+            e = hipEventElapsedTime(&a, h->events[i], h->events[i + 1]);
+            if (e == hipSuccess) e = hipEventElapsedTime(&b, h->events[i + 2], h->events[i + 3]);
+            if (e != hipSuccess) rc = hip_fail(e, "event elapsed");
+            ms_out[LBW_PHASE_COLLIDE_STREAM] += a;
+            ms_out[LBW_PHASE_TRANSPORT] += b;
+        }
+    }
+    for (hipEvent_t ev : h->events) (void)hipEventDestroy(ev);
+    h->events.clear();
+    return rc;
 }
 
 int lbw_steps_done(const lbw_handle *h, int64_t *out) {

@@ -29,7 +29,8 @@ SCHEMES = {"weno5": WENO5, "weno3": WENO3, "upwind1": UPWIND1}
 
 EXPORTED = ("lbw_version", "lbw_last_error", "lbw_scratch_bytes", "lbw_create", "lbw_destroy",
             "lbw_set_launch", "lbw_get_launch", "lbw_init_equilibrium", "lbw_step",
-            "lbw_steps_done", "lbw_export", "lbw_import", "lbw_reduce")
+            "lbw_steps_done", "lbw_export", "lbw_import", "lbw_reduce", "lbw_timing_begin",
+            "lbw_timing_end")
 
 
 class LbwError(RuntimeError):
@@ -93,6 +94,8 @@ def load() -> ctypes.CDLL:
     lib.lbw_export.argtypes = [P, I32, I32, P]
     lib.lbw_import.argtypes = [P, I32, I32, P]
     lib.lbw_reduce.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double)]
+    lib.lbw_timing_begin.argtypes = [P]
+    lib.lbw_timing_end.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     for name in EXPORTED:
         getattr(lib, name)
     _lib = lib
@@ -279,6 +282,15 @@ class Solver:
         out = (ctypes.c_double * self.nbatch)()
         check(self._lib.lbw_reduce(self._h, int(what), out))
         return np.array(out[:], dtype=np.float64)
+
+    def timing_begin(self):
+        check(self._lib.lbw_timing_begin(self._h))
+
+    def timing_end(self) -> dict:
+        ms = (ctypes.c_double * 2)()
+        n = ctypes.c_int64(0)
+        check(self._lib.lbw_timing_end(self._h, ms, ctypes.byref(n)))
+        return {"collide_stream_ms": ms[0], "transport_ms": ms[1], "steps": n.value}
 
     def setup_workload(self, wl, run=0, seed=None):
         """Initial state of a seeded workload: two-layer scalars, fluid at rest."""
