@@ -123,9 +123,11 @@ typedef struct {
 /* Launch shape of the hot kernels (chosen by the autotuner; 0 = default). */
 typedef struct {
     int32_t lbm_block;     /* threads per block of the collide-stream kernel */
-    int32_t tile_x;        /* transport tile width (multiple of 64) */
-    int32_t tile_y;        /* transport tile height (rows per block) */
-    int32_t fused;         /* 1: one fused transport kernel per step */
+    int32_t tile_x;        /* transport tile width: 32, 64, 128 (3D) or
+                              64, 128, 256 (2D) columns */
+    int32_t tile_y;        /* transport chunk: vertical planes per block */
+    int32_t variant;       /* transport kernels: 0 tiled (LDS, marching),
+                              1 plain (one thread per node, no LDS) */
 } lbw_launch;
 
 /* Library ABI version (LBW_ABI_VERSION). */

@@ -191,15 +191,17 @@ int lbw_set_launch(lbw_handle *h, const lbw_launch *l) {
         n.lbm_block = l->lbm_block;
     }
     if (l->tile_x) {
-        if (l->tile_x < 64 || l->tile_x > 1024 || l->tile_x % 64)
-            return fail(LBW_ERR_INVAL, "tile_x must be a multiple of 64 in [64, 1024]");
+        const bool ok = h->dim == 3 ? (l->tile_x == 32 || l->tile_x == 64 || l->tile_x == 128)
+                                    : (l->tile_x == 64 || l->tile_x == 128 || l->tile_x == 256);
+        if (!ok) return fail(LBW_ERR_INVAL, "tile_x must be 32, 64 or 128 (3D) or 64, 128 or 256 (2D)");
         n.tile_x = l->tile_x;
     }
     if (l->tile_y) {
         if (l->tile_y < 1 || l->tile_y > 4096) return fail(LBW_ERR_INVAL, "tile_y must lie in [1, 4096]");
         n.tile_y = l->tile_y;
     }
-    n.fused = l->fused ? 1 : 0;
+    if (l->variant < 0 || l->variant > 1) return fail(LBW_ERR_INVAL, "variant must be 0 or 1");
+    n.variant = l->variant;
     h->launch = n;
     return LBW_OK;
 }

@@ -71,6 +71,9 @@ hipError_t launch_export_f(int q, int precision, const RunDev &r, bool odd, void
                            hipStream_t st);
 hipError_t launch_transport(int dim, int precision, const RunDev &r, const lbw_launch &l,
                             hipStream_t st);
+hipError_t launch_transport_tiled(int dim, int precision, const RunDev &r, const lbw_launch &l,
+                                  hipStream_t st);
+hipError_t launch_s_update(int dim, int precision, const RunDev &r, hipStream_t st);
 hipError_t launch_reduce(int q, int precision, const RunDev *runs, int nbatch, int what,
                          bool odd, double *scratch, hipStream_t st);
 

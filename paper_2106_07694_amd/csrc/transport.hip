@@ -125,7 +125,6 @@ hipError_t transport_t(const RunDev &r, hipStream_t st) {
     const dim3 grid((unsigned)((r.N + block - 1) / block));
     k_rk_stage<T, D, SCHEME, 1><<<grid, block, 0, st>>>(r);
     k_rk_stage<T, D, SCHEME, 2><<<grid, block, 0, st>>>(r);
-    // S reads u and S^n only; it runs before stage 3 overwrites nothing it needs
     if (r.has_s) k_s_euler<T, D><<<grid, block, 0, st>>>(r);
     k_rk_stage<T, D, SCHEME, 3><<<grid, block, 0, st>>>(r);
     return hipGetLastError();
@@ -143,9 +142,22 @@ hipError_t transport_d(const RunDev &r, hipStream_t st) {
 
 }  // namespace
 
+hipError_t launch_s_update(int dim, int precision, const RunDev &r, hipStream_t st) {
+    const int block = 256;
+    const dim3 grid((unsigned)((r.N + block - 1) / block));
+    if (precision == LBW_FP32_SHIFTED) {
+        if (dim == 2) k_s_euler<float, 2><<<grid, block, 0, st>>>(r);
+        else k_s_euler<float, 3><<<grid, block, 0, st>>>(r);
+    } else {
+        if (dim == 2) k_s_euler<double, 2><<<grid, block, 0, st>>>(r);
+        else k_s_euler<double, 3><<<grid, block, 0, st>>>(r);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_transport(int dim, int precision, const RunDev &r, const lbw_launch &l,
                             hipStream_t st) {
-    (void)l;
+    if (l.variant == 0) return launch_transport_tiled(dim, precision, r, l, st);
     if (precision == LBW_FP32_SHIFTED)
         return dim == 2 ? transport_d<float, 2>(r, st) : transport_d<float, 3>(r, st);
     return dim == 2 ? transport_d<double, 2>(r, st) : transport_d<double, 3>(r, st);

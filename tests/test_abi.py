@@ -118,8 +118,9 @@ def test_launch_shape_validation():
         assert lib.lbw_set_launch(h, ctypes.byref(ok)) == 0
         got = lbw.CLaunch()
         assert lib.lbw_get_launch(h, ctypes.byref(got)) == 0
-        assert (got.lbm_block, got.tile_x, got.tile_y, got.fused) == (512, 128, 16, 1)
-        for bad in (lbw.CLaunch(100, 0, 0, 0), lbw.CLaunch(2048, 0, 0, 0), lbw.CLaunch(0, 96, 0, 0)):
+        assert (got.lbm_block, got.tile_x, got.tile_y, got.variant) == (512, 128, 16, 1)
+        for bad in (lbw.CLaunch(100, 0, 0, 0), lbw.CLaunch(2048, 0, 0, 0), lbw.CLaunch(0, 96, 0, 0),
+                    lbw.CLaunch(0, 32, 0, 0), lbw.CLaunch(0, 0, 0, 2)):
             assert lib.lbw_set_launch(h, ctypes.byref(bad)) == lbw.ERR_INVAL
         assert lib.lbw_step(h, -1) == lbw.ERR_INVAL
         v = ctypes.c_int64(-1)

@@ -114,3 +114,31 @@ def test_launch_shapes_give_identical_bits(lbm_block):
     got = run_gpu(cfg, c0, nsteps=7, launch=dict(lbm_block=lbm_block))
     for k in ref:
         assert np.array_equal(ref[k], got[k]), k
+
+
+@pytest.mark.parametrize("launch", [
+    dict(variant=1),
+    dict(tile_x=64, tile_y=7),
+    dict(tile_x=128, tile_y=5),
+    dict(tile_x=256, tile_y=1000),
+])
+def test_2d_transport_launches(launch):
+    """Every transport tiling, ragged chunks included, matches the oracle."""
+    cfg = lbw.RunConfig(nx=150, ny=37, tau=0.6, vs=2e-3, kappa_c=2e-3, gp_c=5e-4,
+                        has_s=True, kappa_s=1e-3, gp_s=1e-4)
+    c0, s0 = _rng_fields(cfg, 8)
+    _check(cfg, 12, c0, s0, launch=launch)
+
+
+@pytest.mark.parametrize("launch", [
+    dict(variant=1),
+    dict(tile_x=32, tile_y=5),
+    dict(tile_x=64, tile_y=3),
+    dict(tile_x=128, tile_y=64),
+])
+@pytest.mark.parametrize("vper", [False, True])
+def test_3d_transport_launches(launch, vper):
+    cfg = lbw.RunConfig(lattice=19, nx=45, ny=11, nz=14, tau=0.55, vs=2e-3, kappa_c=2e-3,
+                        gp_c=5e-4, vert_periodic=vper)
+    c0, _ = _rng_fields(cfg, 9)
+    _check(cfg, 8, c0, launch=launch)
