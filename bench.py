@@ -107,12 +107,57 @@ def run_gpu(wl, steps: int, warmup: int) -> dict:
 
 
 def _tuned_launch(wl):
-    path = os.path.join(ROOT, "paper_2106_07694_amd", "tuned.json")
-    try:
-        with open(path) as fh:
-            return json.load(fh).get(wl.name)
-    except (OSError, ValueError):
-        return None
+    from paper_2106_07694_amd import autotune
+    return autotune.lookup(wl.name)
+
+
+def run_sweep(steps: int, warmup: int) -> dict:
+    """The 64-run parameter sweep (uneven 2D grids): all runs batched into one
+    persistent launch per phase and replayed through a HIP graph, against the
+    same runs advanced one at a time through the single-run path."""
+    import torch
+    from paper_2106_07694_amd import autotune, lbw, workloads as W
+
+    runs = W.sweep_runs()
+    cfgs = [lbw.RunConfig.from_workload(w) for w in runs]
+    cells = sum(w.cells for w in runs)
+    side = torch.cuda.Stream()
+    sol = lbw.Solver(cfgs, stream=side)
+    launch = autotune.lookup("sweep_64") or {}
+    launch = dict(launch, graph=1)
+    sol.set_launch(**launch)
+    for i, w in enumerate(runs):
+        sol.setup_workload(w, run=i)
+    sol.step(warmup)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(side)
+    sol.step(steps)
+    stop.record(side)
+    torch.cuda.synchronize()
+    ms_batched = start.elapsed_time(stop)
+    sol.close()
+    del sol
+    # one at a time: each run's own solver and launches, same stream
+    singles = []
+    for w, c in zip(runs, cfgs):
+        one = lbw.Solver(c, stream=side)
+        one.setup_workload(w)
+        one.step(2)
+        singles.append(one)
+    torch.cuda.synchronize()
+    start.record(side)
+    for one in singles:
+        one.step(steps)
+    stop.record(side)
+    torch.cuda.synchronize()
+    ms_seq = start.elapsed_time(stop)
+    for one in singles:
+        one.close()
+    return {"workload": "sweep_64_uneven_2d_fp32", "runs": len(runs), "cells": cells,
+            "steps": steps, "batched_mlups": cells * steps / (ms_batched * 1e-3) / 1e6,
+            "sequential_mlups": cells * steps / (ms_seq * 1e-3) / 1e6,
+            "speedup": ms_seq / ms_batched, "launch": launch}
 
 
 def cpu_baseline(wl, nz_crop: int, ny_crop: int, steps: int) -> dict:
@@ -146,6 +191,7 @@ def main() -> int:
     ap.add_argument("--workload", choices=["3d", "2d"], default="3d")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-also", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path "
@@ -174,10 +220,16 @@ def main() -> int:
         also = {"workload": other.name, "value": o["mlups"], "unit": "MLUPS",
                 "ms_per_step": o["ms_per_step"], "phase_ms_per_step": o["phase_ms_per_step"],
                 "step_alg_gbs": o["step_alg_gbs"], "roofline": o["roofline"]}
+    sweep = None
+    if not args.no_sweep:
+        sweep = run_sweep(min(args.steps, 200), 4)
+        print(f"[bench] sweep: batched {sweep['batched_mlups']:.0f} MLUPS, one at a time "
+              f"{sweep['sequential_mlups']:.0f} MLUPS ({sweep['speedup']:.1f}x)", file=sys.stderr,
+              flush=True)
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = (cpu_baseline(main_wl, nz_crop=32, ny_crop=0, steps=4) if main_wl.dim == 3
-               else cpu_baseline(main_wl, nz_crop=0, ny_crop=512, steps=16))
+        cpu = (cpu_baseline(main_wl, nz_crop=128, ny_crop=0, steps=20) if main_wl.dim == 3
+               else cpu_baseline(main_wl, nz_crop=0, ny_crop=2048, steps=40))
         print(f"[bench] cpu baseline: {cpu['value']:.2f} MLUPS on {cpu['cores']} cores",
               file=sys.stderr, flush=True)
     line = {
@@ -203,6 +255,7 @@ def main() -> int:
         "roofline": res["roofline"],
         "cpu_baseline": cpu,
         "also": also,
+        "sweep": sweep,
     }
     print(json.dumps(line))
     return 0

@@ -128,6 +128,9 @@ typedef struct {
     int32_t tile_y;        /* transport chunk: vertical planes per block */
     int32_t variant;       /* transport kernels: 0 tiled (LDS, marching),
                               1 plain (one thread per node, no LDS) */
+    int32_t graph;         /* 1: lbw_step replays a captured HIP graph of two
+                              steps (needs a non-null stream; the graph is
+                              runtime-owned and rebuilt after lbw_set_launch) */
 } lbw_launch;
 
 /* Library ABI version (LBW_ABI_VERSION). */
@@ -136,7 +139,10 @@ int lbw_version(void);
 /* Description of the last error on this thread ("" if none). */
 const char *lbw_last_error(void);
 
-/* Bytes of device scratch lbw_reduce needs for these runs. */
+/* Bytes of device scratch the runs need: reduction partials, plus, when
+ * nbatch > 1, the device copy of the run table and the work lists of the
+ * batched (persistent) kernels.  Batched runs must pass this scratch in
+ * run 0's buffers at creation. */
 int lbw_scratch_bytes(const lbw_config *cfgs, int32_t nbatch, size_t *out_bytes);
 
 typedef struct lbw_handle lbw_handle;

@@ -1,0 +1,122 @@
+"""Launch-shape autotuner for liblbw.
+
+For a workload (one run or a batch) it times candidate launch shapes with the
+library's own per-phase HIP-event timing and keeps, independently, the
+collide-stream block size with the least collide-stream time and the
+transport tile (width, vertical chunk) with the least transport time.  The
+winners are cached in ``tuned.json`` beside this file, keyed by workload
+name, with the device architecture, grid and precision they were taken on.
+
+    python -m paper_2106_07694_amd.autotune [3d|2d|sweep|all]
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(HERE, "tuned.json")
+
+LBM_BLOCKS = (128, 256, 512, 1024)
+TILES = {2: (64, 128, 256), 3: (32, 64, 128)}
+CHUNKS = {2: (8, 16, 32, 64, 128), 3: (16, 32, 64, 128)}
+
+
+def _time_phases(sol, steps: int) -> dict:
+    import torch
+    sol.step(2)
+    torch.cuda.synchronize()
+    sol.timing_begin()
+    sol.step(steps)
+    return sol.timing_end()
+
+
+def tune(cfgs, setup, steps: int = 20, graph: bool = False, log=print) -> dict:
+    """Best launch for the runs `cfgs`; `setup(sol)` writes initial state."""
+    import torch
+    from . import lbw
+
+    stream = torch.cuda.Stream() if graph else None
+    sol = lbw.Solver(cfgs, stream=stream)
+    setup(sol)
+    dim = cfgs[0].dim if isinstance(cfgs, list) else cfgs.dim
+    best_lbm, best_lbm_ms = 256, float("inf")
+    for blk in LBM_BLOCKS:
+        sol.set_launch(lbm_block=blk)
+        ms = _time_phases(sol, steps)["collide_stream_ms"] / steps
+        log(f"  lbm_block={blk}: {ms * 1e3:.1f} us/step")
+        if ms < best_lbm_ms:
+            best_lbm, best_lbm_ms = blk, ms
+    best_tile, best_tr_ms = None, float("inf")
+    for tx in TILES[dim]:
+        for ch in CHUNKS[dim]:
+            sol.set_launch(lbm_block=best_lbm, tile_x=tx, tile_y=ch)
+            ms = _time_phases(sol, steps)["transport_ms"] / steps
+            log(f"  tile_x={tx} chunk={ch}: {ms * 1e3:.1f} us/step")
+            if ms < best_tr_ms:
+                best_tile, best_tr_ms = (tx, ch), ms
+    sol.close()
+    out = {"lbm_block": best_lbm, "tile_x": best_tile[0], "tile_y": best_tile[1]}
+    if graph:
+        out["graph"] = 1
+    out["_ms"] = {"collide_stream": best_lbm_ms, "transport": best_tr_ms}
+    return out
+
+
+def load_cache() -> dict:
+    try:
+        with open(CACHE) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def lookup(name: str):
+    """Launch dict for a workload (tuning metadata removed) or None."""
+    e = load_cache().get(name)
+    if not e:
+        return None
+    return {k: v for k, v in e.items() if not k.startswith("_")}
+
+
+def _arch() -> str:
+    import torch
+    try:
+        return torch.cuda.get_device_properties(0).gcnArchName
+    except Exception:
+        return "unknown"
+
+
+def main(which: str = "all") -> int:
+    from . import lbw, workloads as W
+
+    cache = load_cache()
+    jobs = []
+    if which in ("3d", "all"):
+        jobs.append((W.C3.name, [lbw.RunConfig.from_workload(W.C3)], [W.C3], False))
+    if which in ("2d", "all"):
+        jobs.append((W.C2.name, [lbw.RunConfig.from_workload(W.C2)], [W.C2], False))
+    if which in ("sweep", "all"):
+        runs = W.sweep_runs()
+        jobs.append(("sweep_64", [lbw.RunConfig.from_workload(w) for w in runs], runs, True))
+    for name, cfgs, wls, graph in jobs:
+        print(f"[autotune] {name}", flush=True)
+
+        def setup(sol, wls=wls):
+            for i, w in enumerate(wls):
+                sol.setup_workload(w, run=i)
+
+        best = tune(cfgs, setup, graph=graph, log=lambda m: print(m, flush=True))
+        best["_arch"] = _arch()
+        best["_grids"] = sorted({(c.nx, c.ny, c.nz) for c in cfgs})
+        best["_precision"] = cfgs[0].precision
+        cache[name] = best
+        print(f"[autotune] {name}: {best}", flush=True)
+    with open(CACHE, "w") as fh:
+        json.dump(cache, fh, indent=1, sort_keys=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv[1] if len(sys.argv) > 1 else "all"))

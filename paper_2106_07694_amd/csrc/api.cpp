@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <algorithm>
 #include <vector>
 
 #include "lbw_internal.h"
@@ -22,9 +23,20 @@ struct lbw_handle {
     std::vector<lbw::RunDev> run;
     int64_t steps = 0;
     bool odd = false;  // next collide-stream kernel is the odd one of the pair
-    lbw_launch launch{256, 0, 0, 0};
+    lbw_launch launch{256, 0, 0, 0, 0};
     bool timing = false;
     std::vector<hipEvent_t> events;  // 2 per phase per timed step
+    bool sflip = false;              // S currently lives in s_tmp
+    int num_cu = 256;
+    // batched mode (nbatch > 1): tables in run 0's scratch
+    lbw::RunDev *d_runs = nullptr;
+    int *d_blk = nullptr, *d_tiles = nullptr;
+    std::vector<int> blk_start, tile_start;
+    int grid_lbm = 0, grid_tr = 0;
+    // graph replay
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool graph_odd = false, graph_sflip = false;
 };
 
 namespace {
@@ -47,6 +59,71 @@ int hip_fail(hipError_t e, const char *what) {
 }
 
 size_t elem_size(int precision) { return precision == LBW_FP32_SHIFTED ? 4 : 8; }
+
+struct ScratchLayout {
+    size_t out, runs, blk, tiles, total;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+ScratchLayout scratch_layout(int nbatch) {
+    ScratchLayout L;
+    L.out = sizeof(double) * (size_t)nbatch * lbw::kReduceBlocks;
+    L.runs = align256(L.out + sizeof(double) * nbatch);
+    if (nbatch > 1) {
+        L.blk = align256(L.runs + sizeof(lbw::RunDev) * nbatch);
+        L.tiles = align256(L.blk + sizeof(int) * (nbatch + 1));
+        L.total = align256(L.tiles + sizeof(int) * (nbatch + 1));
+    } else {
+        L.blk = L.tiles = L.total = L.runs;
+    }
+    return L;
+}
+
+// The run as the kernels must see it now (S and its work buffer swap roles
+// after every step).
+lbw::RunDev current(const lbw_handle *h, int b) {
+    lbw::RunDev r = h->run[b];
+    if (h->sflip) std::swap(r.s, r.s2);
+    return r;
+}
+
+void release_graph(lbw_handle *h) {
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    h->gexec = nullptr;
+    h->graph = nullptr;
+}
+
+// Work lists of the batched kernels for the current launch shape, copied
+// into the scratch tables (ordered on the handle's stream).
+int upload_tables(lbw_handle *h) {
+    if (h->nbatch < 2) return LBW_OK;
+    const int block = h->launch.lbm_block;
+    h->blk_start.assign(h->nbatch + 1, 0);
+    h->tile_start.assign(h->nbatch + 1, 0);
+    for (int b = 0; b < h->nbatch; ++b) {
+        const int64_t nb = (h->run[b].N + block - 1) / block;
+        const int64_t nt = lbw::transport_tiles(h->dim, h->run[b], h->launch);
+        if ((int64_t)h->blk_start[b] + nb > 0x7fffffff || (int64_t)h->tile_start[b] + nt > 0x7fffffff)
+            return fail(LBW_ERR_INVAL, "batched work list too large");
+        h->blk_start[b + 1] = h->blk_start[b] + (int)nb;
+        h->tile_start[b + 1] = h->tile_start[b] + (int)nt;
+    }
+    const int per_cu_lbm = 2048 / block;
+    h->grid_lbm = std::min(h->blk_start[h->nbatch], h->num_cu * per_cu_lbm);
+    h->grid_tr = std::min(h->tile_start[h->nbatch], h->num_cu * 8);
+    hipError_t e = hipMemcpyAsync(h->d_runs, h->run.data(), sizeof(lbw::RunDev) * h->nbatch,
+                                  hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->d_blk, h->blk_start.data(), sizeof(int) * (h->nbatch + 1),
+                           hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->d_tiles, h->tile_start.data(), sizeof(int) * (h->nbatch + 1),
+                           hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // host tables may change later
+    return e == hipSuccess ? LBW_OK : hip_fail(e, "upload of the batched work lists");
+}
 
 int validate(const lbw_config &c, const lbw_buffers &b, int idx) {
     if (c.lattice != LBW_D2Q9 && c.lattice != LBW_D3Q19)
@@ -138,7 +215,7 @@ const char *lbw_last_error(void) { return g_err.c_str(); }
 
 int lbw_scratch_bytes(const lbw_config *cfgs, int32_t nbatch, size_t *out_bytes) {
     if (!cfgs || nbatch < 1 || !out_bytes) return fail(LBW_ERR_INVAL, "bad arguments");
-    *out_bytes = sizeof(double) * ((size_t)nbatch * lbw::kReduceBlocks + (size_t)nbatch);
+    *out_bytes = scratch_layout(nbatch).total;
     return LBW_OK;
 }
 
@@ -172,6 +249,26 @@ int lbw_create(const lbw_config *cfgs, const lbw_buffers *bufs, int32_t nbatch, 
     h->cfg.assign(cfgs, cfgs + nbatch);
     h->buf.assign(bufs, bufs + nbatch);
     for (int b = 0; b < nbatch; ++b) h->run.push_back(make_run(cfgs[b], bufs[b]));
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+        h->num_cu = ncu;
+    if (nbatch > 1) {
+        const ScratchLayout L = scratch_layout(nbatch);
+        if (!bufs[0].scratch || bufs[0].scratch_bytes < L.total) {
+            delete h;
+            return fail(LBW_ERR_INVAL, "batched runs need %zu bytes of scratch in run 0", L.total);
+        }
+        char *base = (char *)bufs[0].scratch;
+        h->d_runs = (lbw::RunDev *)(base + L.runs);
+        h->d_blk = (int *)(base + L.blk);
+        h->d_tiles = (int *)(base + L.tiles);
+        const int rc = upload_tables(h);
+        if (rc) {
+            delete h;
+            return rc;
+        }
+    }
     *out = h;
     return LBW_OK;
 }
@@ -179,6 +276,7 @@ int lbw_create(const lbw_config *cfgs, const lbw_buffers *bufs, int32_t nbatch, 
 void lbw_destroy(lbw_handle *h) {
     if (!h) return;
     for (hipEvent_t ev : h->events) (void)hipEventDestroy(ev);
+    release_graph(h);
     delete h;
 }
 
@@ -202,8 +300,11 @@ int lbw_set_launch(lbw_handle *h, const lbw_launch *l) {
     }
     if (l->variant < 0 || l->variant > 1) return fail(LBW_ERR_INVAL, "variant must be 0 or 1");
     n.variant = l->variant;
+    if (l->graph < 0 || l->graph > 1) return fail(LBW_ERR_INVAL, "graph must be 0 or 1");
+    n.graph = l->graph;
     h->launch = n;
-    return LBW_OK;
+    release_graph(h);
+    return upload_tables(h);
 }
 
 int lbw_get_launch(const lbw_handle *h, lbw_launch *l) {
@@ -216,7 +317,7 @@ int lbw_init_equilibrium(lbw_handle *h, int32_t run, const void *rho, const void
     int rc = check_run(h, run);
     if (rc) return rc;
     if (h->fluid_mode != LBW_FLUID_LBM) return fail(LBW_ERR_INVAL, "frozen fluid has no populations");
-    hipError_t e = lbw::launch_equilibrium(h->q, h->precision, h->run[run], h->odd, rho, u, h->stream);
+    hipError_t e = lbw::launch_equilibrium(h->q, h->precision, current(h, run), h->odd, rho, u, h->stream);
     return e == hipSuccess ? LBW_OK : hip_fail(e, "equilibrium");
 }
 
@@ -233,31 +334,98 @@ int mark(lbw_handle *h) {
 }
 }  // namespace
 
+namespace {
+// Enqueue one coupled step on the handle's stream and advance the host-side
+// state (streaming parity, S buffer roles, step count).
+int enqueue_step(lbw_handle *h) {
+    int rc;
+    if ((rc = mark(h))) return rc;
+    if (h->fluid_mode == LBW_FLUID_LBM) {
+        hipError_t e;
+        if (h->nbatch > 1)
+            e = lbw::launch_collide_stream_batched(h->q, h->precision, h->d_runs, h->d_blk, h->nbatch,
+                                                   h->sflip ? 1 : 0, h->odd, h->launch.lbm_block,
+                                                   h->grid_lbm, h->stream);
+        else
+            e = lbw::launch_collide_stream(h->q, h->precision, current(h, 0), h->odd,
+                                           h->launch.lbm_block, h->stream);
+        if (e != hipSuccess) return hip_fail(e, "collide-stream launch");
+    }
+    if ((rc = mark(h))) return rc;
+    if ((rc = mark(h))) return rc;
+    if (h->nbatch > 1 && h->launch.variant == 0) {
+        lbw::BatchArgs a;
+        a.runs = h->d_runs;
+        a.tile_start = h->d_tiles;
+        a.host_runs = h->run.data();
+        a.nbatch = h->nbatch;
+        a.chunk = lbw::resolve_tile_shape(h->dim, h->launch).chunk;
+        a.sflip = h->sflip ? 1 : 0;
+        a.grid = h->grid_tr;
+        hipError_t e = lbw::launch_transport_batched(h->dim, h->precision, a, h->launch, h->stream);
+        if (e != hipSuccess) return hip_fail(e, "batched transport launch");
+    } else {
+        for (int b = 0; b < h->nbatch; ++b) {
+            hipError_t e = lbw::launch_transport(h->dim, h->precision, current(h, b), h->launch, h->stream);
+            if (e != hipSuccess) return hip_fail(e, "transport launch");
+        }
+    }
+    if ((rc = mark(h))) return rc;
+    if (h->has_s) h->sflip = !h->sflip;
+    if (h->fluid_mode == LBW_FLUID_LBM) h->odd = !h->odd;
+    ++h->steps;
+    return LBW_OK;
+}
+
+// Capture two steps from the current state into a graph (the state returns
+// to where it was: two steps restore the parity and the S roles).
+int build_graph(lbw_handle *h) {
+    release_graph(h);
+    const bool odd = h->odd, sflip = h->sflip;
+    const int64_t steps = h->steps;
+    hipError_t e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return hip_fail(e, "graph capture begin");
+    int rc = enqueue_step(h);
+    if (!rc) rc = enqueue_step(h);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(h->stream, &g);
+    h->odd = odd;
+    h->sflip = sflip;
+    h->steps = steps;
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "graph capture end");
+    h->graph = g;
+    e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        release_graph(h);
+        return hip_fail(e, "graph instantiate");
+    }
+    h->graph_odd = odd;
+    h->graph_sflip = sflip;
+    return LBW_OK;
+}
+}  // namespace
+
 int lbw_step(lbw_handle *h, int32_t nsteps) {
     if (!h) return fail(LBW_ERR_INVAL, "NULL handle");
     if (nsteps < 0) return fail(LBW_ERR_INVAL, "nsteps must be >= 0");
     int rc;
-    for (int32_t s = 0; s < nsteps; ++s) {
-        if ((rc = mark(h))) return rc;
-        if (h->fluid_mode == LBW_FLUID_LBM) {
-            for (int b = 0; b < h->nbatch; ++b) {
-                hipError_t e = lbw::launch_collide_stream(h->q, h->precision, h->run[b], h->odd,
-                                                          h->launch.lbm_block, h->stream);
-                if (e != hipSuccess) return hip_fail(e, "collide-stream launch");
-            }
+    if (h->launch.graph && !h->timing && nsteps >= 2) {
+        if (!h->stream) return fail(LBW_ERR_UNSUPPORTED, "graph replay needs a non-null stream");
+        if (!h->gexec || h->graph_odd != h->odd || h->graph_sflip != h->sflip)
+            if ((rc = build_graph(h))) return rc;
+        while (nsteps >= 2) {
+            hipError_t e = hipGraphLaunch(h->gexec, h->stream);
+            if (e != hipSuccess) return hip_fail(e, "graph launch");
+            h->steps += 2;
+            nsteps -= 2;
         }
-        if ((rc = mark(h))) return rc;
-        if ((rc = mark(h))) return rc;
-        for (int b = 0; b < h->nbatch; ++b) {
-            hipError_t e = lbw::launch_transport(h->dim, h->precision, h->run[b], h->launch, h->stream);
-            if (e != hipSuccess) return hip_fail(e, "transport launch");
-        }
-        if ((rc = mark(h))) return rc;
-        if (h->has_s)
-            for (auto &r : h->run) std::swap(r.s, r.s2);
-        if (h->fluid_mode == LBW_FLUID_LBM) h->odd = !h->odd;
-        ++h->steps;
     }
+    for (int32_t s = 0; s < nsteps; ++s)
+        if ((rc = enqueue_step(h))) return rc;
     return LBW_OK;
 }
 
@@ -313,7 +481,7 @@ int lbw_export(lbw_handle *h, int32_t run, int32_t field, void *dst) {
         case LBW_FIELD_C: e = hipMemcpyAsync(dst, r.c, r.N * es, hipMemcpyDeviceToDevice, h->stream); break;
         case LBW_FIELD_S:
             if (!h->has_s) return fail(LBW_ERR_INVAL, "run has no S");
-            e = hipMemcpyAsync(dst, r.s, r.N * es, hipMemcpyDeviceToDevice, h->stream);
+            e = hipMemcpyAsync(dst, current(h, run).s, r.N * es, hipMemcpyDeviceToDevice, h->stream);
             break;
         case LBW_FIELD_U:
             e = hipMemcpyAsync(dst, r.u, (size_t)h->dim * r.N * es, hipMemcpyDeviceToDevice, h->stream);
@@ -341,7 +509,7 @@ int lbw_import(lbw_handle *h, int32_t run, int32_t field, const void *src) {
         case LBW_FIELD_C: e = hipMemcpyAsync(r.c, src, r.N * es, hipMemcpyDeviceToDevice, h->stream); break;
         case LBW_FIELD_S:
             if (!h->has_s) return fail(LBW_ERR_INVAL, "run has no S");
-            e = hipMemcpyAsync(r.s, src, r.N * es, hipMemcpyDeviceToDevice, h->stream);
+            e = hipMemcpyAsync(current(h, run).s, src, r.N * es, hipMemcpyDeviceToDevice, h->stream);
             break;
         case LBW_FIELD_U:
             e = hipMemcpyAsync(r.u, src, (size_t)h->dim * r.N * es, hipMemcpyDeviceToDevice, h->stream);
@@ -366,10 +534,12 @@ int lbw_reduce(lbw_handle *h, int32_t what, double *out_host) {
     if (!b0.scratch || b0.scratch_bytes < need)
         return fail(LBW_ERR_INVAL, "scratch of run 0 must hold %zu bytes", need);
     double *scratch = (double *)b0.scratch;
-    hipError_t e = lbw::launch_reduce(h->q, h->precision, h->run.data(), h->nbatch, what, h->odd,
+    std::vector<lbw::RunDev> cur(h->nbatch);
+    for (int b = 0; b < h->nbatch; ++b) cur[b] = current(h, b);
+    hipError_t e = lbw::launch_reduce(h->q, h->precision, cur.data(), h->nbatch, what, h->odd,
                                       scratch, h->stream);
     if (e != hipSuccess) return hip_fail(e, "reduce launch");
-    e = hipMemcpyAsync(out_host, scratch + (size_t)h->nbatch * lbw::kReduceBlocks,
+    e = hipMemcpyAsync(out_host, (char *)b0.scratch + scratch_layout(h->nbatch).out,
                        sizeof(double) * h->nbatch, hipMemcpyDeviceToHost, h->stream);
     if (e != hipSuccess) return hip_fail(e, "reduce copy");
     e = hipStreamSynchronize(h->stream);

@@ -22,11 +22,9 @@ namespace lbw {
 namespace {
 
 template <int Q, typename T, bool SH, bool ODD>
-__global__ void __launch_bounds__(1024) k_collide_stream(RunDev r) {
+__device__ __forceinline__ void collide_stream_node(const RunDev &r, int64_t k) {
     using L = Lattice<Q>;
     constexpr int D = L::D;
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= r.N) return;
     T *__restrict__ f = (T *)r.f;
     int x, y, z;
     coords<D>(r, k, x, y, z);
@@ -100,6 +98,30 @@ __global__ void __launch_bounds__(1024) k_collide_stream(RunDev r) {
     }
 }
 
+template <int Q, typename T, bool SH, bool ODD>
+__global__ void __launch_bounds__(1024) k_collide_stream(RunDev r) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= r.N) return;
+    collide_stream_node<Q, T, SH, ODD>(r, k);
+}
+
+// Batched form: a persistent grid walks the thread blocks of every run;
+// blk_start[b] is the first block of run b (prefix sum, nbatch + 1 entries).
+template <int Q, typename T, bool SH, bool ODD>
+__global__ void __launch_bounds__(1024) k_collide_stream_batched(const RunDev *__restrict__ runs,
+                                                                 const int *__restrict__ blk_start,
+                                                                 int nbatch, int sflip) {
+    const int total = blk_start[nbatch];
+    int b = 0;
+    for (int w = blockIdx.x; w < total; w += gridDim.x) {
+        while (blk_start[b + 1] <= w) ++b;   // w only grows, so b only grows
+        RunDev r = runs[b];
+        if (sflip) { void *t = r.s; r.s = r.s2; r.s2 = t; }
+        const int64_t k = (int64_t)(w - blk_start[b]) * blockDim.x + threadIdx.x;
+        if (k < r.N) collide_stream_node<Q, T, SH, ODD>(r, k);
+    }
+}
+
 template <int Q, typename T, bool SH>
 __global__ void k_equilibrium(RunDev r, bool odd, const T *__restrict__ rho_in,
                               const T *__restrict__ u_in) {
@@ -164,6 +186,16 @@ hipError_t collide_stream_t(const RunDev &r, bool odd, int block, hipStream_t st
     return hipGetLastError();
 }
 
+template <int Q, typename T, bool SH>
+hipError_t collide_stream_batched_t(const RunDev *runs, const int *blk_start, int nbatch, int sflip,
+                                    bool odd, int block, int grid, hipStream_t st) {
+    if (odd)
+        k_collide_stream_batched<Q, T, SH, true><<<grid, block, 0, st>>>(runs, blk_start, nbatch, sflip);
+    else
+        k_collide_stream_batched<Q, T, SH, false><<<grid, block, 0, st>>>(runs, blk_start, nbatch, sflip);
+    return hipGetLastError();
+}
+
 template <int Q>
 hipError_t collide_stream_q(int precision, const RunDev &r, bool odd, int block, hipStream_t st) {
     switch (precision) {
@@ -223,6 +255,24 @@ hipError_t launch_collide_stream(int q, int precision, const RunDev &r, bool odd
     if (block <= 0 || block > 1024 || block % 64) return hipErrorInvalidValue;
     return q == 9 ? collide_stream_q<9>(precision, r, odd, block, st)
                   : collide_stream_q<19>(precision, r, odd, block, st);
+}
+
+hipError_t launch_collide_stream_batched(int q, int precision, const RunDev *runs, const int *blk_start,
+                                         int nbatch, int sflip, bool odd, int block, int grid,
+                                         hipStream_t st) {
+    if (block <= 0 || block > 1024 || block % 64 || grid <= 0) return hipErrorInvalidValue;
+    switch (precision) {
+        case LBW_FP64:
+            return q == 9 ? collide_stream_batched_t<9, double, false>(runs, blk_start, nbatch, sflip, odd, block, grid, st)
+                          : collide_stream_batched_t<19, double, false>(runs, blk_start, nbatch, sflip, odd, block, grid, st);
+        case LBW_FP64_SHIFTED:
+            return q == 9 ? collide_stream_batched_t<9, double, true>(runs, blk_start, nbatch, sflip, odd, block, grid, st)
+                          : collide_stream_batched_t<19, double, true>(runs, blk_start, nbatch, sflip, odd, block, grid, st);
+        case LBW_FP32_SHIFTED:
+            return q == 9 ? collide_stream_batched_t<9, float, true>(runs, blk_start, nbatch, sflip, odd, block, grid, st)
+                          : collide_stream_batched_t<19, float, true>(runs, blk_start, nbatch, sflip, odd, block, grid, st);
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_equilibrium(int q, int precision, const RunDev &r, bool odd, const void *rho,

@@ -59,6 +59,22 @@ struct RunDev {
     double vs, kappa_c, gp_c, kappa_s, gp_s, eps;
 };
 
+// Tile shape of the tiled transport kernels for a launch choice.
+struct TileShape {
+    int tx, ty, chunk;
+};
+
+// Arguments of the batched (persistent, work-list) transport launch.
+struct BatchArgs {
+    const RunDev *runs;        // device copy of the run table
+    const int *tile_start;     // device prefix sum of tiles per run (nbatch + 1)
+    const RunDev *host_runs;   // host copy of the same table
+    int nbatch;
+    int chunk;
+    int sflip;                 // 1: S and its work buffer are swapped
+    int grid;                  // persistent grid size
+};
+
 // Launchers (return the launch error, if any).  `odd` selects the second
 // kernel of the in-place streaming pair.
 hipError_t launch_collide_stream(int q, int precision, const RunDev &r, bool odd,
@@ -74,6 +90,13 @@ hipError_t launch_transport(int dim, int precision, const RunDev &r, const lbw_l
 hipError_t launch_transport_tiled(int dim, int precision, const RunDev &r, const lbw_launch &l,
                                   hipStream_t st);
 hipError_t launch_s_update(int dim, int precision, const RunDev &r, hipStream_t st);
+TileShape resolve_tile_shape(int dim, const lbw_launch &l);
+int64_t transport_tiles(int dim, const RunDev &r, const lbw_launch &l);
+hipError_t launch_transport_batched(int dim, int precision, const BatchArgs &b, const lbw_launch &l,
+                                    hipStream_t st);
+hipError_t launch_collide_stream_batched(int q, int precision, const RunDev *runs, const int *blk_start,
+                                         int nbatch, int sflip, bool odd, int block, int grid,
+                                         hipStream_t st);
 hipError_t launch_reduce(int q, int precision, const RunDev *runs, int nbatch, int what,
                          bool odd, double *scratch, hipStream_t st);
 

@@ -106,7 +106,7 @@ __device__ __forceinline__ void block_tile(const TileGeom &g, int &bx, int &by, 
 }
 
 template <typename T, int D, int SCHEME, int STAGE, int TX, int TY>
-__global__ void __launch_bounds__(TX *TY) k_stage_tiled(RunDev r, TileGeom g) {
+__device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, int bx, int by, int bz) {
     constexpr int NT = TX * TY;
     constexpr int AX = TX + 6;                  // a plane row length (x halo 3 + 3)
     constexpr int AY = (D == 3) ? TY + 6 : 1;   // a plane rows
@@ -116,8 +116,6 @@ __global__ void __launch_bounds__(TX *TY) k_stage_tiled(RunDev r, TileGeom g) {
     __shared__ T sFx[TY * (TX + 1)];
     __shared__ T sFy[(D == 3) ? (TY + 1) * TX : 1];
 
-    int bx, by, bz;
-    block_tile(g, bx, by, bz);
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
     const int x0 = bx * TX, y0 = by * TY;
@@ -314,8 +312,15 @@ __global__ void __launch_bounds__(TX *TY) k_stage_tiled(RunDev r, TileGeom g) {
     }
 }
 
-template <typename T, int D, int SCHEME, int TX, int TY>
-hipError_t stages(const RunDev &r, int chunk, hipStream_t st) {
+template <typename T, int D, int SCHEME, int STAGE, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY) k_stage_tiled(RunDev r, TileGeom g) {
+    int bx, by, bz;
+    block_tile(g, bx, by, bz);
+    stage_tile<T, D, SCHEME, STAGE, TX, TY>(r, g, bx, by, bz);
+}
+
+template <int D>
+__host__ __device__ inline TileGeom make_geom(const RunDev &r, int chunk, int TX, int TY) {
     TileGeom g;
     g.nx = r.nx;
     g.ny = (D == 3) ? r.ny : 1;
@@ -323,10 +328,41 @@ hipError_t stages(const RunDev &r, int chunk, hipStream_t st) {
     g.sv = (D == 3) ? (int64_t)r.nx * r.ny : (int64_t)r.nx;
     g.N = r.N;
     g.vper = r.vper;
-    g.chunk = chunk;
+    g.chunk = chunk < g.nv ? chunk : g.nv;
     g.gx = (r.nx + TX - 1) / TX;
     g.gy = (D == 3) ? (r.ny + TY - 1) / TY : 1;
-    g.gz = (g.nv + chunk - 1) / chunk;
+    g.gz = (g.nv + g.chunk - 1) / g.chunk;
+    return g;
+}
+
+// Batched form: one persistent grid walks the tiles of every run.  Each XCD
+// takes a contiguous range of the global tile list (runs in order, tiles of
+// a run x-fastest), so neighbouring tiles share an L2.  tile_start[b] is the
+// first global tile of run b (prefix sum, nbatch + 1 entries).
+template <typename T, int D, int SCHEME, int STAGE, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY) k_stage_batched(const RunDev *__restrict__ runs,
+                                                          const int *__restrict__ tile_start,
+                                                          int nbatch, int chunk, int sflip) {
+    const int total = tile_start[nbatch];
+    const int G = gridDim.x;
+    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+    const int per_xcd = (G + 7 - xcd) >> 3;               // blocks on this XCD
+    const int lo = (int)((int64_t)total * xcd / 8), hi = (int)((int64_t)total * (xcd + 1) / 8);
+    for (int w = lo + slot; w < hi; w += per_xcd) {
+        int b = 0;
+        while (tile_start[b + 1] <= w) ++b;                // runs are few; linear scan
+        RunDev r = runs[b];
+        if (sflip) { void *t = r.s; r.s = r.s2; r.s2 = t; }
+        const TileGeom g = make_geom<D>(r, chunk, TX, TY);
+        const int t = w - tile_start[b];
+        const int bx = t % g.gx, rest = t / g.gx;
+        stage_tile<T, D, SCHEME, STAGE, TX, TY>(r, g, bx, rest % g.gy, rest / g.gy);
+    }
+}
+
+template <typename T, int D, int SCHEME, int TX, int TY>
+hipError_t stages(const RunDev &r, int chunk, hipStream_t st) {
+    const TileGeom g = make_geom<D>(r, chunk, TX, TY);
     const int64_t nb = (int64_t)g.gx * g.gy * g.gz;
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
     k_stage_tiled<T, D, SCHEME, 1, TX, TY><<<(unsigned)nb, TX * TY, 0, st>>>(r, g);
@@ -341,43 +377,93 @@ hipError_t stages(const RunDev &r, int chunk, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <typename T, int D, int SCHEME, int TX, int TY>
+hipError_t stages_batched(const BatchArgs &a, hipStream_t st) {
+    k_stage_batched<T, D, SCHEME, 1, TX, TY><<<a.grid, TX * TY, 0, st>>>(a.runs, a.tile_start, a.nbatch, a.chunk, a.sflip);
+    k_stage_batched<T, D, SCHEME, 2, TX, TY><<<a.grid, TX * TY, 0, st>>>(a.runs, a.tile_start, a.nbatch, a.chunk, a.sflip);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (a.host_runs[0].has_s) {
+        for (int b = 0; b < a.nbatch; ++b) {
+            RunDev r = a.host_runs[b];
+            if (a.sflip) { void *t = r.s; r.s = r.s2; r.s2 = t; }
+            e = launch_s_update(D, sizeof(T) == 4 ? LBW_FP32_SHIFTED : LBW_FP64, r, st);
+            if (e != hipSuccess) return e;
+        }
+    }
+    k_stage_batched<T, D, SCHEME, 3, TX, TY><<<a.grid, TX * TY, 0, st>>>(a.runs, a.tile_start, a.nbatch, a.chunk, a.sflip);
+    return hipGetLastError();
+}
+
 template <typename T, int D, int SCHEME>
-hipError_t stages_shape(const RunDev &r, const lbw_launch &l, hipStream_t st) {
-    const int nv = (D == 3) ? r.nz : r.ny;
-    int chunk = l.tile_y > 0 ? l.tile_y : (D == 3 ? 64 : 32);
-    chunk = chunk > nv ? nv : chunk;
+hipError_t stages_shape(const RunDev &r, const lbw_launch &l, hipStream_t st, const BatchArgs *batch) {
+    const TileShape sh = resolve_tile_shape(D, l);
+    if (batch) {
+        if constexpr (D == 3) {
+            if (sh.tx == 64) return stages_batched<T, D, SCHEME, 64, 4>(*batch, st);
+            if (sh.tx == 128) return stages_batched<T, D, SCHEME, 128, 2>(*batch, st);
+            return stages_batched<T, D, SCHEME, 32, 8>(*batch, st);
+        } else {
+            if (sh.tx == 64) return stages_batched<T, D, SCHEME, 64, 1>(*batch, st);
+            if (sh.tx == 128) return stages_batched<T, D, SCHEME, 128, 1>(*batch, st);
+            return stages_batched<T, D, SCHEME, 256, 1>(*batch, st);
+        }
+    }
     if constexpr (D == 3) {
-        switch (l.tile_x) {
-            case 64: return stages<T, D, SCHEME, 64, 4>(r, chunk, st);
-            case 128: return stages<T, D, SCHEME, 128, 2>(r, chunk, st);
-            default: return stages<T, D, SCHEME, 32, 8>(r, chunk, st);
-        }
+        if (sh.tx == 64) return stages<T, D, SCHEME, 64, 4>(r, sh.chunk, st);
+        if (sh.tx == 128) return stages<T, D, SCHEME, 128, 2>(r, sh.chunk, st);
+        return stages<T, D, SCHEME, 32, 8>(r, sh.chunk, st);
     } else {
-        switch (l.tile_x) {
-            case 64: return stages<T, D, SCHEME, 64, 1>(r, chunk, st);
-            case 128: return stages<T, D, SCHEME, 128, 1>(r, chunk, st);
-            default: return stages<T, D, SCHEME, 256, 1>(r, chunk, st);
-        }
+        if (sh.tx == 64) return stages<T, D, SCHEME, 64, 1>(r, sh.chunk, st);
+        if (sh.tx == 128) return stages<T, D, SCHEME, 128, 1>(r, sh.chunk, st);
+        return stages<T, D, SCHEME, 256, 1>(r, sh.chunk, st);
     }
 }
 
 template <typename T, int D>
-hipError_t tiled_d(const RunDev &r, const lbw_launch &l, hipStream_t st) {
+hipError_t tiled_d(const RunDev &r, const lbw_launch &l, hipStream_t st, const BatchArgs *b) {
     switch (r.scheme) {
-        case LBW_WENO5: return stages_shape<T, D, LBW_WENO5>(r, l, st);
-        case LBW_WENO3: return stages_shape<T, D, LBW_WENO3>(r, l, st);
-        case LBW_UPWIND1: return stages_shape<T, D, LBW_UPWIND1>(r, l, st);
+        case LBW_WENO5: return stages_shape<T, D, LBW_WENO5>(r, l, st, b);
+        case LBW_WENO3: return stages_shape<T, D, LBW_WENO3>(r, l, st, b);
+        case LBW_UPWIND1: return stages_shape<T, D, LBW_UPWIND1>(r, l, st, b);
     }
     return hipErrorInvalidValue;
 }
 
 }  // namespace
 
+TileShape resolve_tile_shape(int dim, const lbw_launch &l) {
+    TileShape s;
+    if (dim == 3) {
+        s.tx = (l.tile_x == 64 || l.tile_x == 128) ? l.tile_x : 32;
+        s.ty = 256 / s.tx;
+    } else {
+        s.tx = (l.tile_x == 64 || l.tile_x == 128) ? l.tile_x : 256;
+        s.ty = 1;
+    }
+    s.chunk = l.tile_y > 0 ? l.tile_y : (dim == 3 ? 64 : 32);
+    return s;
+}
+
+int64_t transport_tiles(int dim, const RunDev &r, const lbw_launch &l) {
+    const TileShape s = resolve_tile_shape(dim, l);
+    const TileGeom g = dim == 3 ? make_geom<3>(r, s.chunk, s.tx, s.ty) : make_geom<2>(r, s.chunk, s.tx, s.ty);
+    return (int64_t)g.gx * g.gy * g.gz;
+}
+
 hipError_t launch_transport_tiled(int dim, int precision, const RunDev &r, const lbw_launch &l,
                                   hipStream_t st) {
     if (precision == LBW_FP32_SHIFTED)
-        return dim == 2 ? tiled_d<float, 2>(r, l, st) : tiled_d<float, 3>(r, l, st);
-    return dim == 2 ? tiled_d<double, 2>(r, l, st) : tiled_d<double, 3>(r, l, st);
+        return dim == 2 ? tiled_d<float, 2>(r, l, st, nullptr) : tiled_d<float, 3>(r, l, st, nullptr);
+    return dim == 2 ? tiled_d<double, 2>(r, l, st, nullptr) : tiled_d<double, 3>(r, l, st, nullptr);
+}
+
+hipError_t launch_transport_batched(int dim, int precision, const BatchArgs &b, const lbw_launch &l,
+                                    hipStream_t st) {
+    const RunDev &r = b.host_runs[0];
+    if (precision == LBW_FP32_SHIFTED)
+        return dim == 2 ? tiled_d<float, 2>(r, l, st, &b) : tiled_d<float, 3>(r, l, st, &b);
+    return dim == 2 ? tiled_d<double, 2>(r, l, st, &b) : tiled_d<double, 3>(r, l, st, &b);
 }
 
 }  // namespace lbw

@@ -64,7 +64,8 @@ class CBuffers(ctypes.Structure):
 
 class CLaunch(ctypes.Structure):
     _fields_ = [("lbm_block", ctypes.c_int32), ("tile_x", ctypes.c_int32),
-                ("tile_y", ctypes.c_int32), ("variant", ctypes.c_int32)]
+                ("tile_y", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("graph", ctypes.c_int32)]
 
 
 _lib = None
@@ -184,11 +185,25 @@ class Solver:
         c0 = self.cfgs[0]
         self.dtype = torch.float32 if c0.precision == "fp32_shifted" else torch.float64
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._torch = torch
         self._ccfg = (CConfig * self.nbatch)(*[c.to_c() for c in self.cfgs])
         nbytes = ctypes.c_size_t(0)
         check(lib.lbw_scratch_bytes(self._ccfg, self.nbatch, ctypes.byref(nbytes)))
         self.tensors = []
         cbufs = []
+        torch.cuda.current_stream(self.device).synchronize()
+        with torch.cuda.stream(self.stream):
+            self._alloc(cbufs, nbytes.value)
+        self.stream.synchronize()
+        self._cbuf = (CBuffers * self.nbatch)(*cbufs)
+        h = ctypes.c_void_p()
+        check(lib.lbw_create(self._ccfg, self._cbuf, self.nbatch,
+                             ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self._lib = lib
+
+    def _alloc(self, cbufs, scratch_bytes):
+        torch = self._torch
         for i, c in enumerate(self.cfgs):
             z = lambda *shape, dt=self.dtype: torch.zeros(shape, dtype=dt, device=self.device)
             t = {
@@ -198,20 +213,14 @@ class Solver:
                 "s_tmp": z(*c.shape) if c.has_s else None,
                 "u": z(c.dim, *c.shape),
                 "deposit": z(c.ncol, dt=torch.float64),
-                "scratch": z(nbytes.value // 8, dt=torch.float64) if i == 0 else None,
+                "scratch": z((scratch_bytes + 7) // 8, dt=torch.float64) if i == 0 else None,
             }
             self.tensors.append(t)
             b = CBuffers()
             for k in ("f", "c", "c_s1", "c_s2", "s", "s_tmp", "u", "deposit", "scratch"):
                 setattr(b, k, t[k].data_ptr() if t[k] is not None else None)
-            b.scratch_bytes = nbytes.value if i == 0 else 0
+            b.scratch_bytes = scratch_bytes if i == 0 else 0
             cbufs.append(b)
-        self._cbuf = (CBuffers * self.nbatch)(*cbufs)
-        h = ctypes.c_void_p()
-        check(lib.lbw_create(self._ccfg, self._cbuf, self.nbatch,
-                             ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
-        self._h = h
-        self._lib = lib
 
     # -- lifetime --------------------------------------------------------
     def close(self):
@@ -227,11 +236,15 @@ class Solver:
 
     # -- state -----------------------------------------------------------
     def _dev(self, x, dtype=None):
-        import torch
+        """Device copy of x made on the solver's stream (and finished)."""
+        torch = self._torch
         dt = self.dtype if dtype is None else dtype
         if isinstance(x, np.ndarray):
             x = torch.from_numpy(np.ascontiguousarray(x))
-        return x.to(device=self.device, dtype=dt).contiguous()
+        with torch.cuda.stream(self.stream):
+            y = x.to(device=self.device, dtype=dt).contiguous()
+        self.stream.synchronize()
+        return y
 
     def init_equilibrium(self, run=0, rho=None, u=None):
         keep = [self._dev(rho) if rho is not None else None, self._dev(u) if u is not None else None]
@@ -256,7 +269,8 @@ class Solver:
                   "deposit": (c.ncol,)}
         fid = {"f": FIELD_F, "c": FIELD_C, "s": FIELD_S, "u": FIELD_U, "deposit": FIELD_DEPOSIT}[name]
         dt = torch.float64 if name == "deposit" else self.dtype
-        out = torch.empty(shapes[name], dtype=dt, device=self.device)
+        with torch.cuda.stream(self.stream):
+            out = torch.empty(shapes[name], dtype=dt, device=self.device)
         check(self._lib.lbw_export(self._h, run, fid, out.data_ptr()))
         self.stream.synchronize()
         return out
@@ -269,15 +283,15 @@ class Solver:
         check(self._lib.lbw_steps_done(self._h, ctypes.byref(v)))
         return v.value
 
-    def set_launch(self, lbm_block=0, tile_x=0, tile_y=0, variant=0):
-        lc = CLaunch(lbm_block, tile_x, tile_y, variant)
+    def set_launch(self, lbm_block=0, tile_x=0, tile_y=0, variant=0, graph=0):
+        lc = CLaunch(lbm_block, tile_x, tile_y, variant, graph)
         check(self._lib.lbw_set_launch(self._h, ctypes.byref(lc)))
 
     def get_launch(self) -> dict:
         lc = CLaunch()
         check(self._lib.lbw_get_launch(self._h, ctypes.byref(lc)))
         return {"lbm_block": lc.lbm_block, "tile_x": lc.tile_x, "tile_y": lc.tile_y,
-                "variant": lc.variant}
+                "variant": lc.variant, "graph": lc.graph}
 
     def reduce(self, what) -> np.ndarray:
         out = (ctypes.c_double * self.nbatch)()
