@@ -15,4 +15,5 @@ from .oracle import (  # noqa: F401
     run,
     sums,
     library_path,
+    adjoint_step,
 )

@@ -525,6 +525,260 @@ int orc_run(const orc_cfg *cfg, double *f, double *c, double *s, double *dep,
     return 0;
 }
 
+/* ----------------------------------------------------------------------- */
+/* Adjoint (reverse mode) of one step.  Plain scatter loops, sequential.     */
+/* ----------------------------------------------------------------------- */
+
+/* Reverse of weno5(): given gbar = dJ/d(face value), accumulate dJ/dh and the
+ * part of dJ/da that flows through the smoothness indicators. */
+static void weno5_reverse(const double h[5], const double a[5], double eps, double gbar,
+                          double hbar[5], double abar[5])
+{
+    const double d[3] = {0.1, 0.6, 0.3};
+    double q[3], t[3], s[3], b[3], e[3], al[3], S = 0.0, g = 0.0;
+    double qbar[3], bbar[3];
+    int k;
+    q[0] = (2.0 * h[0] - 7.0 * h[1] + 11.0 * h[2]) / 6.0;
+    q[1] = (-h[1] + 5.0 * h[2] + 2.0 * h[3]) / 6.0;
+    q[2] = (2.0 * h[2] + 5.0 * h[3] - h[4]) / 6.0;
+    t[0] = a[0] - 2.0 * a[1] + a[2];
+    s[0] = a[0] - 4.0 * a[1] + 3.0 * a[2];
+    t[1] = a[1] - 2.0 * a[2] + a[3];
+    s[1] = a[1] - a[3];
+    t[2] = a[2] - 2.0 * a[3] + a[4];
+    s[2] = 3.0 * a[2] - 4.0 * a[3] + a[4];
+    for (k = 0; k < 3; k++) {
+        b[k] = 13.0 / 12.0 * t[k] * t[k] + 0.25 * s[k] * s[k];
+        e[k] = eps + b[k];
+        al[k] = d[k] / (e[k] * e[k]);
+        S += al[k];
+    }
+    for (k = 0; k < 3; k++) g += al[k] * q[k];
+    g /= S;
+    /* g = sum al q / sum al:  dg/dq_k = al_k/S,  dg/dal_k = (q_k - g)/S,
+       dal_k/db_k = -2 al_k / e_k */
+    for (k = 0; k < 3; k++) {
+        qbar[k] = gbar * al[k] / S;
+        bbar[k] = gbar * (q[k] - g) / S * (-2.0 * al[k] / e[k]);
+    }
+    hbar[0] += 2.0 / 6.0 * qbar[0];
+    hbar[1] += -7.0 / 6.0 * qbar[0] - 1.0 / 6.0 * qbar[1];
+    hbar[2] += 11.0 / 6.0 * qbar[0] + 5.0 / 6.0 * qbar[1] + 2.0 / 6.0 * qbar[2];
+    hbar[3] += 2.0 / 6.0 * qbar[1] + 5.0 / 6.0 * qbar[2];
+    hbar[4] += -1.0 / 6.0 * qbar[2];
+    /* b = 13/12 t^2 + 1/4 s^2: db/dt = 13/6 t, db/ds = 1/2 s */
+    {
+        double tb = 13.0 / 6.0 * t[0] * bbar[0], sb = 0.5 * s[0] * bbar[0];
+        abar[0] += tb + sb;
+        abar[1] += -2.0 * tb - 4.0 * sb;
+        abar[2] += tb + 3.0 * sb;
+        tb = 13.0 / 6.0 * t[1] * bbar[1];
+        sb = 0.5 * s[1] * bbar[1];
+        abar[1] += tb + sb;
+        abar[2] += -2.0 * tb;
+        abar[3] += tb - sb;
+        tb = 13.0 / 6.0 * t[2] * bbar[2];
+        sb = 0.5 * s[2] * bbar[2];
+        abar[2] += tb + 3.0 * sb;
+        abar[3] += -2.0 * tb - 4.0 * sb;
+        abar[4] += tb + sb;
+    }
+}
+
+/* Reverse of L(a) (C equation, WENO5, absorbing bottom) for adjoint lam of
+ * the output: abar += lam^T dL/da, ubar += lam^T dL/du, *vsbar += lam^T dL/dVs. */
+static void spatial_operator_reverse(const grid_t *g, const orc_cfg *cfg, const double *a,
+                                     const double *u, const double *lam, double *abar,
+                                     double *ubar, double *vsbar)
+{
+    const double vs = cfg->vs, kappa = cfg->kappa_c;
+    long k;
+    for (k = 0; k < g->N; k++) {
+        int p[3], d, m, gh;
+        node_coords(g, k, p);
+        for (d = 0; d < g->dim; d++) {
+            long idx[6], kr;
+            int ghost[6];
+            double av[6], wv[6], hv[6], hbar[6], abar_l[6], phibar, wf;
+            if (d == g->vert && !cfg->vert_periodic && p[d] == g->n[d] - 1) continue; /* top wall */
+            /* L_k = -(Phi_{k+1/2} - Phi_{k-1/2}): Phi_{k+1/2} enters L_k with -1
+               and L_{k+e} with +1 */
+            kr = displaced(g, cfg, p, d, 1, &gh);
+            phibar = lam[kr] - lam[k];
+            for (m = 0; m < 6; m++) {
+                idx[m] = displaced(g, cfg, p, d, m - 2, &ghost[m]);
+                av[m] = a[idx[m]];
+                wv[m] = transport_velocity(g, u, idx[m], d, ghost[m], vs);
+                hv[m] = wv[m] * av[m];
+                hbar[m] = 0.0;
+                abar_l[m] = 0.0;
+            }
+            wf = 0.5 * (wv[2] + wv[3]);
+            {
+                double hh[5], aa[5], hb[5] = {0, 0, 0, 0, 0}, ab[5] = {0, 0, 0, 0, 0};
+                int map[5];
+                for (m = 0; m < 5; m++) map[m] = (wf >= 0.0) ? m : 5 - m;
+                for (m = 0; m < 5; m++) { hh[m] = hv[map[m]]; aa[m] = av[map[m]]; }
+                weno5_reverse(hh, aa, cfg->weno_eps, phibar, hb, ab);
+                for (m = 0; m < 5; m++) { hbar[map[m]] += hb[m]; abar_l[map[m]] += ab[m]; }
+            }
+            /* diffusion part -kappa (a_{j+1} - a_j) */
+            abar_l[3] += -kappa * phibar;
+            abar_l[2] += kappa * phibar;
+            for (m = 0; m < 6; m++) {
+                double wbar = hbar[m] * av[m];
+                abar[idx[m]] += abar_l[m] + hbar[m] * wv[m];
+                if (d == g->vert) {
+                    /* w = u - vs directly, or -u(mirror) - vs beyond a wall */
+                    ubar[(long)d * g->N + idx[m]] += ghost[m] ? -wbar : wbar;
+                    *vsbar += -wbar;
+                } else {
+                    ubar[(long)d * g->N + idx[m]] += wbar;
+                }
+            }
+        }
+        /* bottom wall face: L_0 gains -vs a_0 */
+        if (!cfg->vert_periodic && p[g->vert] == 0) {
+            abar[k] += -vs * lam[k];
+            *vsbar += -a[k] * lam[k];
+        }
+    }
+}
+
+int orc_adjoint_step(const orc_cfg *cfg, const double *f_n, const double *c_n,
+                     const double *u_in, const double *fbar_next, const double *cbar_next,
+                     double dep_bar, double *fbar, double *cbar, double *vs_bar)
+{
+    grid_t g;
+    long k, N;
+    double *rho, *u, *F, *a1, *a2, *L, *ubar, *abar1, *abar2, *lam, vsb = 0.0;
+    const double vs = cfg->vs;
+    if (setup(cfg, &g)) return -1;
+    if (cfg->scheme_c != 0 || cfg->has_s || cfg->shifted < 0) return -1;
+    if (cfg->frozen ? !u_in : (!f_n || !fbar_next || !fbar)) return -1;
+    N = g.N;
+    rho = (double *)calloc(N, sizeof(double));
+    u = (double *)calloc((size_t)3 * N, sizeof(double));
+    F = (double *)calloc((size_t)3 * N, sizeof(double));
+    a1 = (double *)calloc(N, sizeof(double));
+    a2 = (double *)calloc(N, sizeof(double));
+    L = (double *)calloc(N, sizeof(double));
+    ubar = (double *)calloc((size_t)3 * N, sizeof(double));
+    abar1 = (double *)calloc(N, sizeof(double));
+    abar2 = (double *)calloc(N, sizeof(double));
+    lam = (double *)calloc(N, sizeof(double));
+
+    /* forward recomputation: moments (time level n) and the RK stages */
+    for (k = 0; k < N; k++) {
+        double uk[3], Fk[3];
+        int d;
+        if (cfg->frozen) {
+            for (d = 0; d < g.dim; d++) u[(long)d * N + k] = u_in[(long)d * N + k];
+        } else {
+            moments_at(&g, cfg, f_n, c_n, NULL, k, &rho[k], uk, Fk);
+            for (d = 0; d < 3; d++) { u[(long)d * N + k] = uk[d]; F[(long)d * N + k] = Fk[d]; }
+        }
+    }
+    spatial_operator(&g, cfg, 0, cfg->kappa_c, vs, 1, c_n, u, L, NULL);
+    for (k = 0; k < N; k++) a1[k] = c_n[k] + L[k];
+    spatial_operator(&g, cfg, 0, cfg->kappa_c, vs, 1, a1, u, L, NULL);
+    for (k = 0; k < N; k++) a2[k] = 0.75 * c_n[k] + 0.25 * a1[k] + 0.25 * L[k];
+
+    /* reverse of C+ = C/3 + 2/3 a2 + 2/3 L(a2) and of the deposit update */
+    for (k = 0; k < N; k++) {
+        cbar[k] = cbar_next[k] / 3.0;
+        abar2[k] = 2.0 / 3.0 * cbar_next[k];
+        lam[k] = 2.0 / 3.0 * cbar_next[k];
+    }
+    spatial_operator_reverse(&g, cfg, a2, u, lam, abar2, ubar, &vsb);
+    if (!cfg->vert_periodic) {
+        for (k = 0; k < N; k++) {
+            int p[3];
+            node_coords(&g, k, p);
+            if (p[g.vert] != 0) continue;
+            /* D+ = D + vs (C/6 + a1/6 + 2 a2/3) at the bottom cells */
+            cbar[k] += vs / 6.0 * dep_bar;
+            abar1[k] += vs / 6.0 * dep_bar;
+            abar2[k] += 2.0 * vs / 3.0 * dep_bar;
+            vsb += dep_bar * (c_n[k] / 6.0 + a1[k] / 6.0 + 2.0 / 3.0 * a2[k]);
+        }
+    }
+    /* reverse of a2 = 3/4 C + 1/4 a1 + 1/4 L(a1) */
+    for (k = 0; k < N; k++) {
+        cbar[k] += 0.75 * abar2[k];
+        abar1[k] += 0.25 * abar2[k];
+        lam[k] = 0.25 * abar2[k];
+    }
+    spatial_operator_reverse(&g, cfg, a1, u, lam, abar1, ubar, &vsb);
+    /* reverse of a1 = C + L(C) */
+    for (k = 0; k < N; k++) {
+        cbar[k] += abar1[k];
+        lam[k] = abar1[k];
+    }
+    spatial_operator_reverse(&g, cfg, c_n, u, lam, cbar, ubar, &vsb);
+
+    /* reverse of streaming, collision and moments */
+    if (!cfg->frozen) {
+        double omega = 1.0 / cfg->tau, guo = 1.0 - 0.5 / cfg->tau;
+        for (k = 0; k < N; k++) {
+            int p[3], i, d, a;
+            double fs_bar[MAXQ], uk[3], Fk[3], usq = 0.0, rb = 0.0, ub[3], Fb[3], mb[3];
+            node_coords(&g, k, p);
+            for (d = 0; d < 3; d++) {
+                uk[d] = (d < g.dim) ? u[(long)d * N + k] : 0.0;
+                Fk[d] = (d < g.dim) ? F[(long)d * N + k] : 0.0;
+                ub[d] = (d < g.dim) ? ubar[(long)d * N + k] : 0.0;
+                Fb[d] = 0.0;
+                usq += uk[d] * uk[d];
+            }
+            /* streaming sent f*_i(x) to slot i of x + c_i, or to slot opp(i)
+               of x when x + c_i lies beyond a wall: pull the adjoint back */
+            for (i = 0; i < g.q; i++) {
+                int t[3], wall = 0;
+                for (d = 0; d < 3; d++) t[d] = p[d] + g.c[i][d];
+                for (d = 0; d < g.dim; d++) {
+                    if (d != g.vert || cfg->vert_periodic)
+                        t[d] = ((t[d] % g.n[d]) + g.n[d]) % g.n[d];
+                    else if (t[d] < 0 || t[d] >= g.n[d])
+                        wall = 1;
+                }
+                fs_bar[i] = wall ? fbar_next[(long)g.opp[i] * N + k]
+                                 : fbar_next[(long)i * N + node_index(&g, t)];
+            }
+            /* f* = f - omega (f - feq(rho, u)) + G(u, F) */
+            for (i = 0; i < g.q; i++) {
+                double cu = 0.0, cF = 0.0, poly, feqb = omega * fs_bar[i], Gb = fs_bar[i];
+                for (d = 0; d < 3; d++) { cu += g.c[i][d] * uk[d]; cF += g.c[i][d] * Fk[d]; }
+                poly = 3.0 * cu + 4.5 * cu * cu - 1.5 * usq;
+                fbar[(long)i * N + k] = (1.0 - omega) * fs_bar[i];
+                rb += feqb * g.w[i] * (1.0 + poly);
+                for (a = 0; a < 3; a++) {
+                    ub[a] += feqb * g.w[i] * rho[k] * (3.0 * g.c[i][a] + 9.0 * cu * g.c[i][a] - 3.0 * uk[a]);
+                    ub[a] += Gb * guo * g.w[i] * (-3.0 * Fk[a] + 9.0 * g.c[i][a] * cF);
+                    Fb[a] += Gb * guo * g.w[i] * (3.0 * (g.c[i][a] - uk[a]) + 9.0 * cu * g.c[i][a]);
+                }
+            }
+            /* u = (m + F/2)/rho with m = sum f c and rho = sum f (+1 shifted) */
+            for (a = 0; a < 3; a++) {
+                mb[a] = ub[a] / rho[k];
+                Fb[a] += 0.5 * ub[a] / rho[k];
+                rb += -ub[a] * uk[a] / rho[k];
+            }
+            for (i = 0; i < g.q; i++) {
+                double s = rb;
+                for (a = 0; a < 3; a++) s += mb[a] * g.c[i][a];
+                fbar[(long)i * N + k] += s;
+            }
+            /* F_vert = body - gp_c C */
+            cbar[k] += -cfg->gp_c * Fb[g.vert];
+        }
+    }
+    *vs_bar += vsb;
+    free(rho); free(u); free(F); free(a1); free(a2); free(L); free(ubar);
+    free(abar1); free(abar2); free(lam);
+    return 0;
+}
+
 int orc_sums(const orc_cfg *cfg, const double *f, const double *c,
              const double *s, const double *dep, double *out)
 {

@@ -62,6 +62,17 @@ int orc_rhs_c(const orc_cfg *cfg, const double *a, const double *u,
 int orc_run(const orc_cfg *cfg, double *f, double *c, double *s, double *dep,
             const double *u_in, double *u_out, int32_t nsteps);
 
+/* Reverse-mode adjoint of one coupled step n -> n+1 (hand-written
+ * transpose of steps 1-5; WENO5 only, no S).  Inputs: the forward state at n
+ * (f_n, c_n) and the adjoints of the outputs (fbar_next of f^{n+1}, cbar_next
+ * of C^{n+1}, dep_bar of every deposit counter).  Outputs: fbar, cbar (the
+ * adjoints of f^n and C^n) and *vs_bar += dJ/dVs of this step.  In frozen
+ * mode u_in is the node velocity and fbar/fbar_next are not used.  The upwind
+ * side of every face is held at its forward choice. */
+int orc_adjoint_step(const orc_cfg *cfg, const double *f_n, const double *c_n,
+                     const double *u_in, const double *fbar_next, const double *cbar_next,
+                     double dep_bar, double *fbar, double *cbar, double *vs_bar);
+
 /* out[0..3] = sum C, sum S, sum rho, sum dep (plain sequential sums). */
 int orc_sums(const orc_cfg *cfg, const double *f, const double *c,
              const double *s, const double *dep, double *out);

@@ -113,6 +113,7 @@ def _load():
         lib.orc_rhs_c.argtypes = [cfgp, P, P, P, P]
         lib.orc_run.argtypes = [cfgp, P, P, P, P, P, P, ctypes.c_int32]
         lib.orc_sums.argtypes = [cfgp, P, P, P, P, P]
+        lib.orc_adjoint_step.argtypes = [cfgp, P, P, P, P, P, ctypes.c_double, P, P, P]
         _lib = lib
     return _lib
 
@@ -194,3 +195,19 @@ def sums(cfg: OracleConfig, f, c, s=None, dep=None):
     cc = cfg._c()
     _check(lib.orc_sums(ctypes.byref(cc), _ptr(f), _ptr(c), _ptr(s), _ptr(dep), _ptr(out)), "sums")
     return out
+
+
+def adjoint_step(cfg: OracleConfig, f_n, c_n, fbar_next, cbar_next, dep_bar=1.0, u_in=None):
+    """(fbar, cbar, vs_bar) of one step (WENO5, no S); see lbw_oracle.h."""
+    lib = _load()
+    cbar = np.zeros(cfg.shape, np.float64)
+    fbar = None if cfg.frozen else np.zeros((cfg.q,) + cfg.shape, np.float64)
+    vsb = np.zeros(1, np.float64)
+    cc = cfg._c()
+    _check(lib.orc_adjoint_step(ctypes.byref(cc), _ptr(None if f_n is None else np.ascontiguousarray(f_n)),
+                                _ptr(np.ascontiguousarray(c_n)),
+                                _ptr(None if u_in is None else np.ascontiguousarray(u_in)),
+                                _ptr(None if fbar_next is None else np.ascontiguousarray(fbar_next)),
+                                _ptr(np.ascontiguousarray(cbar_next)), float(dep_bar),
+                                _ptr(fbar), _ptr(cbar), _ptr(vsb)), "adjoint_step")
+    return fbar, cbar, float(vsb[0])
