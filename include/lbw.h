@@ -198,6 +198,30 @@ int lbw_import(lbw_handle *h, int32_t run, int32_t field, const void *src);
  * LBW_ERR_NONFINITE if any sum is NaN or Inf (the values are still written). */
 int lbw_reduce(lbw_handle *h, int32_t what, double *out_host);
 
+/* Device workspace lbw_adjoint_step needs for run `run` (bytes). */
+int lbw_adjoint_work_bytes(const lbw_handle *h, int32_t run, size_t *out_bytes);
+
+/* Reverse mode of one coupled step n -> n+1 of run `run`: the hand-written
+ * transpose of moments, RK3 transport (S21-S23, WENO5 weights differentiated
+ * through their smoothness indicators, the upwind side of each face held at
+ * its forward choice), deposit update, BGK + Guo collision and bounce-back
+ * streaming.  For J a function of the state at n+1:
+ *   f_n, c_n     forward state at n (canonical populations, as lbw_export
+ *                writes them; C), device arrays of the run's element type;
+ *   fbar_next    dJ/df^{n+1} (canonical layout); cbar_next = dJ/dC^{n+1};
+ *   dep_bar      dJ/d(deposit) of every column (1 for the total deposited
+ *                mass m_b of section 4.3);
+ *   fbar, cbar   out: dJ/df^n and dJ/dC^n (must not alias the inputs);
+ *   vs_bar_dev   device FP64 scalar: += dJ/dVs through this step;
+ *   work         device workspace of lbw_adjoint_work_bytes bytes.
+ * WENO5 without S only (LBW_ERR_UNSUPPORTED otherwise).  In frozen mode the
+ * run's u buffer is the (constant) velocity and the population arguments may
+ * be NULL.  Asynchronous on the handle's stream; independent of the handle's
+ * own state buffers apart from that velocity. */
+int lbw_adjoint_step(lbw_handle *h, int32_t run, const void *f_n, const void *c_n,
+                     const void *fbar_next, const void *cbar_next, double dep_bar, void *fbar,
+                     void *cbar, double *vs_bar_dev, void *work, size_t work_bytes);
+
 /* Per-phase GPU time of the lbw_step calls made between lbw_timing_begin and
  * lbw_timing_end: HIP events are recorded on the handle's stream around the
  * collide-stream launches and around the transport launches of every step.

@@ -1,0 +1,125 @@
+"""Gradient of the deposited mass through the coupled step.
+
+``DepositedMass.apply(c0, vs, cfg, nsteps)`` returns J = total mass deposited
+on the bottom wall after ``nsteps`` coupled steps started from the fluid at
+rest and the concentration field ``c0`` (the initial state of section 2.2);
+its backward gives dJ/dc0 and dJ/dVs through the hand-written adjoint kernels
+(``lbw_adjoint_step``).
+
+Memory follows the square-root rule: the forward keeps the state (canonical
+populations and C) every ``seg`` ~ sqrt(nsteps) steps; the backward replays
+each segment from its checkpoint, keeping that segment's per-step states, and
+runs the reverse steps back through it.  All arithmetic runs in the library's
+kernels; this module orders calls and owns tensors.
+"""
+from __future__ import annotations
+
+import math
+
+import torch
+
+from . import lbw
+
+
+def default_segment(nsteps: int) -> int:
+    return max(1, int(round(math.sqrt(nsteps))))
+
+
+def _solver(cfg: lbw.RunConfig, vs: float, launch=None) -> lbw.Solver:
+    c = lbw.RunConfig(**{**cfg.__dict__, "vs": float(vs)})
+    sol = lbw.Solver(c)
+    if launch:
+        sol.set_launch(**launch)
+    return sol
+
+
+def _state_buffers(sol, count):
+    cfg = sol.cfgs[0]
+    with torch.cuda.stream(sol.stream):
+        return [(torch.empty((cfg.lattice,) + cfg.shape, dtype=sol.dtype, device=sol.device),
+                 torch.empty(cfg.shape, dtype=sol.dtype, device=sol.device)) for _ in range(count)]
+
+
+def forward_with_checkpoints(cfg, c0: torch.Tensor, vs: float, nsteps: int, seg: int, launch=None,
+                             f0=None, u=None):
+    """Run nsteps from C = c0 and the fluid at rest (or the canonical
+    populations f0; or, for a frozen fluid, the velocity u); return
+    (J, solver, checkpoints {step: (f, c)})."""
+    sol = _solver(cfg, vs, launch)
+    sol.set_field("c", c0)
+    frozen = cfg.fluid_mode == lbw.FLUID_FROZEN
+    if frozen:
+        sol.set_field("u", u)
+    elif f0 is not None:
+        sol.set_field("f", f0)
+    else:
+        sol.init_equilibrium()
+    starts = list(range(0, nsteps, seg))
+    bufs = _state_buffers(sol, len(starts))
+    ckpt = {}
+    for s0, (fb, cb) in zip(starts, bufs):
+        if not frozen:
+            sol.export_into("f", fb)
+        sol.export_into("c", cb)
+        ckpt[s0] = (fb, cb)
+        sol.step(min(seg, nsteps - s0))
+    J = float(sol.reduce(lbw.DEPOSIT)[0])
+    return J, sol, ckpt
+
+
+def backward_from_checkpoints(sol: lbw.Solver, ckpt: dict, nsteps: int, seg: int, dep_bar: float):
+    """(dJ/dc0, dJ/dVs) given the checkpoints of a forward run."""
+    dev, dt = sol.device, sol.dtype
+    cfg = sol.cfgs[0]
+    with torch.cuda.stream(sol.stream):
+        fbar_next = torch.zeros((cfg.lattice,) + cfg.shape, dtype=dt, device=dev)
+        cbar_next = torch.zeros(cfg.shape, dtype=dt, device=dev)
+        fbar = torch.empty_like(fbar_next)
+        cbar = torch.empty_like(cbar_next)
+        vs_bar = torch.zeros(1, dtype=torch.float64, device=dev)
+    work = sol.adjoint_workspace()
+    states = _state_buffers(sol, seg)
+    frozen = cfg.fluid_mode == lbw.FLUID_FROZEN
+    for s0 in reversed(sorted(ckpt)):
+        n = min(seg, nsteps - s0)
+        f_s, c_s = ckpt[s0]
+        if not frozen:
+            sol.import_from("f", f_s)
+        sol.import_from("c", c_s)
+        for i in range(n):
+            if not frozen:
+                sol.export_into("f", states[i][0])
+            sol.export_into("c", states[i][1])
+            if i + 1 < n:
+                sol.step(1)
+        for i in reversed(range(n)):
+            f_n, c_n = states[i]
+            if frozen:
+                sol.adjoint_step(None, c_n, None, cbar_next, dep_bar, None, cbar, vs_bar, work)
+            else:
+                sol.adjoint_step(f_n, c_n, fbar_next, cbar_next, dep_bar, fbar, cbar, vs_bar, work)
+            fbar_next, fbar = fbar, fbar_next
+            cbar_next, cbar = cbar, cbar_next
+    sol.stream.synchronize()
+    return cbar_next.clone(), float(vs_bar.item())
+
+
+class DepositedMass(torch.autograd.Function):
+    """J(c0, vs) = deposited mass after nsteps; differentiable in c0 and vs."""
+
+    @staticmethod
+    def forward(ctx, c0, vs, cfg, nsteps, seg=None, launch=None, f0=None, u=None):
+        seg = seg or default_segment(nsteps)
+        J, sol, ckpt = forward_with_checkpoints(cfg, c0.detach(), float(vs), nsteps, seg, launch,
+                                                f0, u)
+        ctx.sol, ctx.ckpt, ctx.nsteps, ctx.seg = sol, ckpt, nsteps, seg
+        return torch.tensor(J, dtype=torch.float64, device=c0.device)
+
+    @staticmethod
+    def backward(ctx, gJ):
+        cbar, vsb = backward_from_checkpoints(ctx.sol, ctx.ckpt, ctx.nsteps, ctx.seg, float(gJ))
+        ctx.sol.close()
+        ctx.ckpt = None
+        gc = cbar.to(torch.float64)
+        gv = torch.tensor(vsb, dtype=torch.float64, device=gc.device)
+        return gc, gv, None, None, None, None, None, None

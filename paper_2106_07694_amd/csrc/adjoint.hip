@@ -1,0 +1,480 @@
+// adjoint.hip -- reverse mode of one coupled step (WENO5 transport, no S).
+//
+// Objective sensitivities flow backwards through the step of lbm.hip and
+// transport.hip:  J depends on the state at n+1 through (fbar_next of the
+// populations, cbar_next of C, dep_bar of every deposit counter); this step
+// returns the adjoints of the state at n (fbar, cbar) and adds dJ/dVs.
+//
+//  1. recompute, from the saved forward state at n: the node velocity u^n
+//     (moments, eq. 19-20 with the Guo shift) and the RK stages a1, a2;
+//  2. RK3 in reverse (S21-S23 transposed) with the deposit update: each stage
+//     needs lam^T dL/da and lam^T dL/du at its input.  The transpose of L is
+//     taken face by face: one kernel evaluates every interior face once,
+//     multiplies its local Jacobian (six stencil values of a and of the
+//     transport velocity, the WENO5 weights differentiated through the
+//     smoothness indicators, the upwind side held at its forward choice) by
+//     the face's adjoint lam_{j+1} - lam_j and stores the twelve products;
+//     a second kernel gathers, for every node, the products of every face
+//     stencil that reads it, including stencils that read it as a mirror
+//     image beyond a wall (where the vertical velocity enters with a sign
+//     flip and the settling speed unchanged);
+//  3. streaming in reverse (each population pulls the adjoint from where the
+//     forward step sent it), then BGK + Guo collision and the moments in
+//     reverse, adding the transport's velocity sensitivity; the force's C
+//     dependence closes the loop into cbar.
+// Every node's adjoint is written by exactly one thread; dJ/dVs is gathered
+// per node and summed in a fixed order (FP64).
+#include "lbm_device.h"
+#include "transport_device.h"
+
+namespace lbw {
+namespace {
+
+struct AdjDev {
+    RunDev r;
+    const void *f_n, *c_n, *fbar_next, *cbar_next;
+    void *fbar, *cbar;
+    void *u, *a1, *a2, *abar1, *abar2, *ubar, *faceA, *faceW;
+    double *vs_part, *partials, *vs_bar;
+    double dep_bar;
+    int frozen;
+};
+
+template <int D>
+__device__ __forceinline__ void xyz(const RunDev &r, int64_t k, int &x, int &y, int &z) {
+    x = (int)(k % r.nx);
+    const int64_t t = k / r.nx;
+    if constexpr (D == 2) { y = (int)t; z = 0; }
+    else { y = (int)(t % r.ny); z = (int)(t / r.ny); }
+}
+
+// ---------------------------------------------------------------------------
+// 1. moments of the saved populations: u^n (force-shifted)
+// ---------------------------------------------------------------------------
+template <int Q, typename T, bool SH>
+__global__ void __launch_bounds__(256) k_adj_moments(AdjDev a) {
+    using L = Lattice<Q>;
+    constexpr int D = L::D;
+    const RunDev &r = a.r;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= r.N) return;
+    const T *f = (const T *)a.f_n;
+    T rho = SH ? (T)1 : (T)0, m[3] = {0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const T v = f[(int64_t)i * r.N + k];
+        rho += v;
+        m[0] += (T)L::cx[i] * v;
+        m[1] += (T)L::cy[i] * v;
+        m[2] += (T)L::cz[i] * v;
+    }
+    T F[3] = {(T)r.body[0], (T)r.body[1], (T)r.body[2]};
+    F[D - 1] += -(T)r.gp_c * ((const T *)a.c_n)[k];
+    T *u = (T *)a.u;
+#pragma unroll
+    for (int d = 0; d < D; ++d) u[(int64_t)d * r.N + k] = (m[d] + (T)0.5 * F[d]) / rho;
+}
+
+// ---------------------------------------------------------------------------
+// 2. transpose of the spatial operator
+// ---------------------------------------------------------------------------
+
+// Reverse of the WENO5-JS face value for stencil values (upwind -> downwind)
+// h (fluxes) and a (smoothness input): gb = dJ/d(face value); adds dJ/dh and
+// the smoothness part of dJ/da.
+template <typename T>
+__device__ __forceinline__ void weno5_vjp(const T h[5], const T a[5], T eps, T gb, T hb[5], T ab[5]) {
+    const T d0 = (T)0.1, d1 = (T)0.6, d2 = (T)0.3;
+    const T q0 = ((T)2 * h[0] - (T)7 * h[1] + (T)11 * h[2]) / (T)6;
+    const T q1 = (-h[1] + (T)5 * h[2] + (T)2 * h[3]) / (T)6;
+    const T q2 = ((T)2 * h[2] + (T)5 * h[3] - h[4]) / (T)6;
+    const T t0 = a[0] - (T)2 * a[1] + a[2], s0 = a[0] - (T)4 * a[1] + (T)3 * a[2];
+    const T t1 = a[1] - (T)2 * a[2] + a[3], s1 = a[1] - a[3];
+    const T t2 = a[2] - (T)2 * a[3] + a[4], s2 = (T)3 * a[2] - (T)4 * a[3] + a[4];
+    const T e0 = eps + ((T)(13.0 / 12.0) * t0 * t0 + (T)0.25 * s0 * s0);
+    const T e1 = eps + ((T)(13.0 / 12.0) * t1 * t1 + (T)0.25 * s1 * s1);
+    const T e2 = eps + ((T)(13.0 / 12.0) * t2 * t2 + (T)0.25 * s2 * s2);
+    const T al0 = d0 / (e0 * e0), al1 = d1 / (e1 * e1), al2 = d2 / (e2 * e2);
+    const T S = al0 + al1 + al2;
+    const T g = (al0 * q0 + al1 * q1 + al2 * q2) / S;
+    // g = sum al_k q_k / S: dg/dq_k = al_k / S, dg/dal_k = (q_k - g) / S,
+    // dal_k/de_k = -2 al_k / e_k (e_k = eps + smoothness indicator k)
+    const T qb0 = gb * al0 / S, qb1 = gb * al1 / S, qb2 = gb * al2 / S;
+    const T bb0 = gb * (q0 - g) / S * ((T)-2 * al0 / e0);
+    const T bb1 = gb * (q1 - g) / S * ((T)-2 * al1 / e1);
+    const T bb2 = gb * (q2 - g) / S * ((T)-2 * al2 / e2);
+    hb[0] += (T)2 / (T)6 * qb0;
+    hb[1] += -(T)7 / (T)6 * qb0 - qb1 / (T)6;
+    hb[2] += (T)11 / (T)6 * qb0 + (T)5 / (T)6 * qb1 + (T)2 / (T)6 * qb2;
+    hb[3] += (T)2 / (T)6 * qb1 + (T)5 / (T)6 * qb2;
+    hb[4] += -qb2 / (T)6;
+    // indicator = 13/12 t^2 + 1/4 s^2
+    T tb = (T)(13.0 / 6.0) * t0 * bb0, sb = (T)0.5 * s0 * bb0;
+    ab[0] += tb + sb;
+    ab[1] += (T)-2 * tb - (T)4 * sb;
+    ab[2] += tb + (T)3 * sb;
+    tb = (T)(13.0 / 6.0) * t1 * bb1;
+    sb = (T)0.5 * s1 * bb1;
+    ab[1] += tb + sb;
+    ab[2] += (T)-2 * tb;
+    ab[3] += tb - sb;
+    tb = (T)(13.0 / 6.0) * t2 * bb2;
+    sb = (T)0.5 * s2 * bb2;
+    ab[2] += tb + (T)3 * sb;
+    ab[3] += (T)-2 * tb - (T)4 * sb;
+    ab[4] += tb + sb;
+}
+
+// For every interior face j+1/2 (stored at its lower node j) and axis d:
+//   faceA[d][s] = phibar * dPhi/da_{j-2+s},  faceW[d][s] = phibar * dPhi/dw_{j-2+s}
+// with phibar = scale * (lam_{j+1} - lam_j).  Wall faces store zeros.
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_adj_face(AdjDev A, const T *__restrict__ a,
+                                                  const T *__restrict__ lam, T scale) {
+    const RunDev &r = A.r;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= r.N) return;
+    int x, y, z;
+    xyz<D>(r, k, x, y, z);
+    const T *u = (const T *)(A.frozen ? r.u : A.u);
+    T *fa = (T *)A.faceA, *fw = (T *)A.faceW;
+    const T vs = (T)r.vs, kap = (T)r.kappa_c, eps = (T)r.eps;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const bool vert = (d == D - 1);
+        const bool walls = vert && !r.vper;
+        const int j = d == 0 ? x : (d == 1 ? y : z);
+        const int n = d == 0 ? r.nx : (d == 1 ? r.ny : r.nz);
+        const int64_t stride = d == 0 ? 1 : (d == 1 ? (int64_t)r.nx : (int64_t)r.nx * r.ny);
+        const int64_t base = ((int64_t)d * 6) * r.N + k;
+        if (walls && j == n - 1) {
+#pragma unroll
+            for (int s = 0; s < 6; ++s) { fa[base + s * r.N] = (T)0; fw[base + s * r.N] = (T)0; }
+            continue;
+        }
+        T av[6], wv[6];
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+            int jj = j + s - 2;
+            bool ghost = false;
+            if (!walls) { jj %= n; if (jj < 0) jj += n; }
+            else if (jj < 0) { jj = -1 - jj; ghost = true; }
+            else if (jj >= n) { jj = 2 * n - 1 - jj; ghost = true; }
+            const int64_t kk = k + (int64_t)(jj - j) * stride;
+            av[s] = a[kk];
+            T uu = u[(int64_t)d * r.N + kk];
+            if (ghost) uu = -uu;
+            wv[s] = vert ? uu - vs : uu;
+        }
+        int jn = j + 1;
+        if (jn >= n) jn -= n;   // periodic neighbour (walls never reach here at the top)
+        const T pb = scale * (lam[k + (int64_t)(jn - j) * stride] - lam[k]);
+        T hb[6] = {0, 0, 0, 0, 0, 0}, ab[6] = {0, 0, 0, 0, 0, 0};
+        const bool pos = (wv[2] + wv[3]) >= (T)0;
+        if (pos) {
+            T h5[5] = {wv[0] * av[0], wv[1] * av[1], wv[2] * av[2], wv[3] * av[3], wv[4] * av[4]};
+            T a5[5] = {av[0], av[1], av[2], av[3], av[4]};
+            T hb5[5] = {0, 0, 0, 0, 0}, ab5[5] = {0, 0, 0, 0, 0};
+            weno5_vjp<T>(h5, a5, eps, pb, hb5, ab5);
+#pragma unroll
+            for (int s = 0; s < 5; ++s) { hb[s] += hb5[s]; ab[s] += ab5[s]; }
+        } else {
+            T h5[5] = {wv[5] * av[5], wv[4] * av[4], wv[3] * av[3], wv[2] * av[2], wv[1] * av[1]};
+            T a5[5] = {av[5], av[4], av[3], av[2], av[1]};
+            T hb5[5] = {0, 0, 0, 0, 0}, ab5[5] = {0, 0, 0, 0, 0};
+            weno5_vjp<T>(h5, a5, eps, pb, hb5, ab5);
+#pragma unroll
+            for (int s = 0; s < 5; ++s) { hb[5 - s] += hb5[s]; ab[5 - s] += ab5[s]; }
+        }
+        ab[3] += -kap * pb;   // diffusion -kappa (a_{j+1} - a_j)
+        ab[2] += kap * pb;
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+            fa[base + s * r.N] = ab[s] + hb[s] * wv[s];   // through a directly and through h = w a
+            fw[base + s * r.N] = hb[s] * av[s];
+        }
+    }
+}
+
+// Node-wise gather of the face products.  STAGE selects the RK stage being
+// reversed (3, 2, 1 in that order) and how the result combines.
+template <typename T, int D, int STAGE>
+__global__ void __launch_bounds__(256) k_adj_gather(AdjDev A) {
+    const RunDev &r = A.r;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= r.N) return;
+    int x, y, z;
+    xyz<D>(r, k, x, y, z);
+    const T *fa = (const T *)A.faceA, *fw = (const T *)A.faceW;
+    T *ub = (T *)A.ubar;
+    double vsp = 0.0;
+    T abar = 0;
+    T ubs[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const bool vert = (d == D - 1);
+        const bool walls = vert && !r.vper;
+        const int m = d == 0 ? x : (d == 1 ? y : z);
+        const int n = d == 0 ? r.nx : (d == 1 ? r.ny : r.nz);
+        const int64_t stride = d == 0 ? 1 : (d == 1 ? (int64_t)r.nx : (int64_t)r.nx * r.ny);
+        // images of node m as seen by stencils: itself, and beyond each wall
+        const int nimg = walls ? 3 : 1;
+        for (int im = 0; im < nimg; ++im) {
+            const int p = im == 0 ? m : (im == 1 ? -1 - m : 2 * n - 1 - m);
+            const bool ghost = im != 0;
+#pragma unroll
+            for (int s = 0; s < 6; ++s) {
+                int jf = p - s + 2;              // face whose slot s reads position p
+                if (walls) {
+                    if (jf < 0 || jf > n - 2) continue;
+                } else {
+                    jf %= n;
+                    if (jf < 0) jf += n;
+                }
+                const int64_t kf = k + (int64_t)(jf - m) * stride;
+                const int64_t idx = ((int64_t)d * 6 + s) * r.N + kf;
+                abar += fa[idx];
+                const T wb = fw[idx];
+                if (vert) {
+                    ubs[d] += ghost ? -wb : wb;
+                    vsp -= (double)wb;
+                } else {
+                    ubs[d] += wb;
+                }
+            }
+        }
+    }
+    // bottom wall face: L_0 contains -vs a_0
+    const int v = (D == 2) ? y : z;
+    const bool bottom = !r.vper && v == 0;
+    const T *lam_in;
+    T lam_scale;
+    const T *a_fwd;
+    if constexpr (STAGE == 3) { lam_in = (const T *)A.cbar_next; lam_scale = (T)(2.0 / 3.0); a_fwd = (const T *)A.a2; }
+    else if constexpr (STAGE == 2) { lam_in = (const T *)A.abar2; lam_scale = (T)0.25; a_fwd = (const T *)A.a1; }
+    else { lam_in = (const T *)A.abar1; lam_scale = (T)1; a_fwd = (const T *)A.c_n; }
+    const T lam = lam_scale * lam_in[k];
+    if (bottom) {
+        abar += -(T)r.vs * lam;
+        vsp += -(double)a_fwd[k] * (double)lam;
+    }
+    const double db = A.dep_bar;
+    const T *cbn = (const T *)A.cbar_next;
+    T *cb = (T *)A.cbar;
+    if constexpr (STAGE == 3) {
+        T a2b = (T)(2.0 / 3.0) * cbn[k] + abar;
+        T cbv = cbn[k] / (T)3;
+        if (bottom) {
+            // D+ = D + vs (C/6 + a1/6 + 2 a2/3)
+            a2b += (T)(2.0 / 3.0 * r.vs * db);
+            cbv += (T)(r.vs / 6.0 * db);
+            vsp += db * ((double)((const T *)A.c_n)[k] / 6.0 + (double)((const T *)A.a1)[k] / 6.0 +
+                         2.0 / 3.0 * (double)((const T *)A.a2)[k]);
+        }
+        ((T *)A.abar2)[k] = a2b;
+        cb[k] = cbv;
+#pragma unroll
+        for (int d = 0; d < D; ++d) ub[(int64_t)d * r.N + k] = ubs[d];
+        A.vs_part[k] = vsp;
+    } else if constexpr (STAGE == 2) {
+        const T a2b = ((const T *)A.abar2)[k];
+        T a1b = (T)0.25 * a2b + abar;
+        if (bottom) a1b += (T)(r.vs / 6.0 * db);
+        ((T *)A.abar1)[k] = a1b;
+        cb[k] += (T)0.75 * a2b;
+#pragma unroll
+        for (int d = 0; d < D; ++d) ub[(int64_t)d * r.N + k] += ubs[d];
+        A.vs_part[k] += vsp;
+    } else {
+        cb[k] += ((const T *)A.abar1)[k] + abar;
+#pragma unroll
+        for (int d = 0; d < D; ++d) ub[(int64_t)d * r.N + k] += ubs[d];
+        A.vs_part[k] += vsp;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3. streaming, collision and moments in reverse
+// ---------------------------------------------------------------------------
+template <int Q, typename T, bool SH>
+__global__ void __launch_bounds__(256) k_adj_collide(AdjDev A) {
+    using L = Lattice<Q>;
+    constexpr int D = L::D;
+    const RunDev &r = A.r;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= r.N) return;
+    int x, y, z;
+    xyz<D>(r, k, x, y, z);
+    const T *f = (const T *)A.f_n;
+    const T *fbn = (const T *)A.fbar_next;
+    T fi[Q], fsb[Q];
+    T rho = SH ? (T)1 : (T)0, m[3] = {0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        fi[i] = f[(int64_t)i * r.N + k];
+        rho += fi[i];
+        m[0] += (T)L::cx[i] * fi[i];
+        m[1] += (T)L::cy[i] * fi[i];
+        m[2] += (T)L::cz[i] * fi[i];
+        // forward streaming sent f*_i(x) to slot i of x + c_i, or to slot
+        // opp(i) of x across a wall: pull the adjoint from there
+        const int64_t dst = displaced<D>(r, x, y, z, L::cx[i], L::cy[i], L::cz[i]);
+        fsb[i] = dst >= 0 ? fbn[(int64_t)i * r.N + dst] : fbn[(int64_t)L::opp[i] * r.N + k];
+    }
+    T F[3] = {(T)r.body[0], (T)r.body[1], (T)r.body[2]};
+    F[D - 1] += -(T)r.gp_c * ((const T *)A.c_n)[k];
+    T u[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < D; ++d) u[d] = (m[d] + (T)0.5 * F[d]) / rho;
+    const T usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const T omega = (T)r.omega, guo = (T)r.guo;
+    const T *ubt = (const T *)A.ubar;
+    T ub[3] = {0, 0, 0}, Fb[3] = {0, 0, 0}, rb = 0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) ub[d] = ubt[(int64_t)d * r.N + k];
+    T *fb = (T *)A.fbar;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const T w = (T)L::w[i];
+        const T c[3] = {(T)L::cx[i], (T)L::cy[i], (T)L::cz[i]};
+        const T cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
+        const T cF = c[0] * F[0] + c[1] * F[1] + c[2] * F[2];
+        const T poly = (T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * usq;
+        // f* = f - omega (f - feq(rho, u)) + G(u, F)
+        const T eb = omega * fsb[i];      // adjoint of feq_i
+        const T gb = fsb[i];              // adjoint of G_i
+        rb += eb * w * ((T)1 + poly);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            ub[d] += eb * w * rho * ((T)3 * c[d] + (T)9 * cu * c[d] - (T)3 * u[d]) +
+                     gb * guo * w * ((T)-3 * F[d] + (T)9 * c[d] * cF);
+            Fb[d] += gb * guo * w * ((T)3 * (c[d] - u[d]) + (T)9 * cu * c[d]);
+        }
+        fb[(int64_t)i * r.N + k] = ((T)1 - omega) * fsb[i];
+    }
+    // u = (m + F/2) / rho, m = sum f c, rho = sum f (+1 when shifted)
+    T mb[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        mb[d] = ub[d] / rho;
+        Fb[d] += (T)0.5 * ub[d] / rho;
+        rb -= ub[d] * u[d] / rho;
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        fb[(int64_t)i * r.N + k] += rb + mb[0] * (T)L::cx[i] + mb[1] * (T)L::cy[i] + mb[2] * (T)L::cz[i];
+    ((T *)A.cbar)[k] += -(T)r.gp_c * Fb[D - 1];
+}
+
+// ---------------------------------------------------------------------------
+// dJ/dVs: fixed-order FP64 sum of the per-node parts, added to *vs_bar
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum_adj(double acc) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    __shared__ double waves[16];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) waves[wid] = acc;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)((blockDim.x + 63) >> 6); ++i) t += waves[i];
+    return t;
+}
+
+__global__ void __launch_bounds__(256) k_adj_vs_partial(const double *__restrict__ part, int64_t n,
+                                                        double *__restrict__ out) {
+    double acc = 0.0;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        acc += part[k];
+    const double t = block_sum_adj(acc);
+    if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(256) k_adj_vs_final(const double *__restrict__ part, int n,
+                                                      double *__restrict__ vs_bar) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += part[i];
+    const double t = block_sum_adj(acc);
+    if (threadIdx.x == 0) *vs_bar += t;
+}
+
+template <int Q, typename T, bool SH>
+hipError_t adjoint_t(const AdjDev &A, hipStream_t st) {
+    constexpr int D = Lattice<Q>::D;
+    const int block = 256;
+    const dim3 grid((unsigned)((A.r.N + block - 1) / block));
+    if (!A.frozen) k_adj_moments<Q, T, SH><<<grid, block, 0, st>>>(A);
+    // forward stages 1 and 2 from the saved C^n and the recomputed u^n
+    RunDev fr = A.r;
+    fr.c = const_cast<void *>(A.c_n);
+    fr.c1 = A.a1;
+    fr.c2 = A.a2;
+    fr.u = A.frozen ? A.r.u : A.u;
+    hipError_t e = launch_rk_stages12(D, sizeof(T) == 4 ? LBW_FP32_SHIFTED : LBW_FP64, fr, st);
+    if (e != hipSuccess) return e;
+    k_adj_face<T, D><<<grid, block, 0, st>>>(A, (const T *)A.a2, (const T *)A.cbar_next, (T)(2.0 / 3.0));
+    k_adj_gather<T, D, 3><<<grid, block, 0, st>>>(A);
+    k_adj_face<T, D><<<grid, block, 0, st>>>(A, (const T *)A.a1, (const T *)A.abar2, (T)0.25);
+    k_adj_gather<T, D, 2><<<grid, block, 0, st>>>(A);
+    k_adj_face<T, D><<<grid, block, 0, st>>>(A, (const T *)A.c_n, (const T *)A.abar1, (T)1);
+    k_adj_gather<T, D, 1><<<grid, block, 0, st>>>(A);
+    if (!A.frozen) k_adj_collide<Q, T, SH><<<grid, block, 0, st>>>(A);
+    k_adj_vs_partial<<<kReduceBlocks, 256, 0, st>>>(A.vs_part, A.r.N, A.partials);
+    k_adj_vs_final<<<1, 256, 0, st>>>(A.partials, kReduceBlocks, A.vs_bar);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t adjoint_work_bytes(int dim, int precision, int64_t N) {
+    const size_t es = precision == LBW_FP32_SHIFTED ? 4 : 8;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t b = 0;
+    b += al(es * dim * N);          // u
+    b += 4 * al(es * N);            // a1, a2, abar1, abar2
+    b += al(es * dim * N);          // ubar
+    b += 2 * al(es * 6 * dim * N);  // face products
+    b += al(sizeof(double) * N);    // vs parts
+    b += al(sizeof(double) * kReduceBlocks);
+    return b;
+}
+
+hipError_t launch_adjoint(int q, int precision, const RunDev &r, bool frozen, const void *f_n,
+                          const void *c_n, const void *fbar_next, const void *cbar_next,
+                          double dep_bar, void *fbar, void *cbar, double *vs_bar, void *work,
+                          hipStream_t st) {
+    const int dim = q == 9 ? 2 : 3;
+    const size_t es = precision == LBW_FP32_SHIFTED ? 4 : 8;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    char *w = (char *)work;
+    AdjDev A;
+    A.r = r;
+    A.f_n = f_n;
+    A.c_n = c_n;
+    A.fbar_next = fbar_next;
+    A.cbar_next = cbar_next;
+    A.fbar = fbar;
+    A.cbar = cbar;
+    A.u = w; w += al(es * dim * r.N);
+    A.a1 = w; w += al(es * r.N);
+    A.a2 = w; w += al(es * r.N);
+    A.abar1 = w; w += al(es * r.N);
+    A.abar2 = w; w += al(es * r.N);
+    A.ubar = w; w += al(es * dim * r.N);
+    A.faceA = w; w += al(es * 6 * dim * r.N);
+    A.faceW = w; w += al(es * 6 * dim * r.N);
+    A.vs_part = (double *)w; w += al(sizeof(double) * r.N);
+    A.partials = (double *)w;
+    A.vs_bar = vs_bar;
+    A.dep_bar = dep_bar;
+    A.frozen = frozen ? 1 : 0;
+    switch (precision) {
+        case LBW_FP64: return q == 9 ? adjoint_t<9, double, false>(A, st) : adjoint_t<19, double, false>(A, st);
+        case LBW_FP64_SHIFTED: return q == 9 ? adjoint_t<9, double, true>(A, st) : adjoint_t<19, double, true>(A, st);
+        case LBW_FP32_SHIFTED: return q == 9 ? adjoint_t<9, float, true>(A, st) : adjoint_t<19, float, true>(A, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace lbw

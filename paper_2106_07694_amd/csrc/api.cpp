@@ -429,6 +429,36 @@ int lbw_step(lbw_handle *h, int32_t nsteps) {
     return LBW_OK;
 }
 
+int lbw_adjoint_work_bytes(const lbw_handle *h, int32_t run, size_t *out_bytes) {
+    int rc = check_run(h, run);
+    if (rc) return rc;
+    if (!out_bytes) return fail(LBW_ERR_INVAL, "out_bytes is NULL");
+    *out_bytes = lbw::adjoint_work_bytes(h->dim, h->precision, h->run[run].N);
+    return LBW_OK;
+}
+
+int lbw_adjoint_step(lbw_handle *h, int32_t run, const void *f_n, const void *c_n,
+                     const void *fbar_next, const void *cbar_next, double dep_bar, void *fbar,
+                     void *cbar, double *vs_bar_dev, void *work, size_t work_bytes) {
+    int rc = check_run(h, run);
+    if (rc) return rc;
+    if (h->scheme != LBW_WENO5 || h->has_s)
+        return fail(LBW_ERR_UNSUPPORTED, "the adjoint covers WENO5 transport without S");
+    const bool frozen = h->fluid_mode == LBW_FLUID_FROZEN;
+    if (!c_n || !cbar_next || !cbar || !vs_bar_dev || !work)
+        return fail(LBW_ERR_INVAL, "NULL required argument");
+    if (!frozen && (!f_n || !fbar_next || !fbar))
+        return fail(LBW_ERR_INVAL, "populations and their adjoints are required");
+    if (cbar == cbar_next || cbar == c_n || (!frozen && (fbar == fbar_next || fbar == f_n)))
+        return fail(LBW_ERR_INVAL, "outputs must not alias inputs");
+    if (!std::isfinite(dep_bar)) return fail(LBW_ERR_INVAL, "dep_bar must be finite");
+    const size_t need = lbw::adjoint_work_bytes(h->dim, h->precision, h->run[run].N);
+    if (work_bytes < need) return fail(LBW_ERR_INVAL, "work needs %zu bytes", need);
+    hipError_t e = lbw::launch_adjoint(h->q, h->precision, h->run[run], frozen, f_n, c_n, fbar_next,
+                                       cbar_next, dep_bar, fbar, cbar, vs_bar_dev, work, h->stream);
+    return e == hipSuccess ? LBW_OK : hip_fail(e, "adjoint launch");
+}
+
 int lbw_timing_begin(lbw_handle *h) {
     if (!h) return fail(LBW_ERR_INVAL, "NULL handle");
     for (hipEvent_t ev : h->events) (void)hipEventDestroy(ev);

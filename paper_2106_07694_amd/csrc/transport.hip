@@ -155,6 +155,29 @@ hipError_t launch_s_update(int dim, int precision, const RunDev &r, hipStream_t 
     return hipGetLastError();
 }
 
+hipError_t launch_rk_stages12(int dim, int precision, const RunDev &r, hipStream_t st) {
+    const int block = 256;
+    const dim3 grid((unsigned)((r.N + block - 1) / block));
+    if (precision == LBW_FP32_SHIFTED) {
+        if (dim == 2) {
+            k_rk_stage<float, 2, LBW_WENO5, 1><<<grid, block, 0, st>>>(r);
+            k_rk_stage<float, 2, LBW_WENO5, 2><<<grid, block, 0, st>>>(r);
+        } else {
+            k_rk_stage<float, 3, LBW_WENO5, 1><<<grid, block, 0, st>>>(r);
+            k_rk_stage<float, 3, LBW_WENO5, 2><<<grid, block, 0, st>>>(r);
+        }
+    } else {
+        if (dim == 2) {
+            k_rk_stage<double, 2, LBW_WENO5, 1><<<grid, block, 0, st>>>(r);
+            k_rk_stage<double, 2, LBW_WENO5, 2><<<grid, block, 0, st>>>(r);
+        } else {
+            k_rk_stage<double, 3, LBW_WENO5, 1><<<grid, block, 0, st>>>(r);
+            k_rk_stage<double, 3, LBW_WENO5, 2><<<grid, block, 0, st>>>(r);
+        }
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_transport(int dim, int precision, const RunDev &r, const lbw_launch &l,
                             hipStream_t st) {
     if (l.variant == 0) return launch_transport_tiled(dim, precision, r, l, st);

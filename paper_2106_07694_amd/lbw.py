@@ -30,7 +30,7 @@ SCHEMES = {"weno5": WENO5, "weno3": WENO3, "upwind1": UPWIND1}
 EXPORTED = ("lbw_version", "lbw_last_error", "lbw_scratch_bytes", "lbw_create", "lbw_destroy",
             "lbw_set_launch", "lbw_get_launch", "lbw_init_equilibrium", "lbw_step",
             "lbw_steps_done", "lbw_export", "lbw_import", "lbw_reduce", "lbw_timing_begin",
-            "lbw_timing_end")
+            "lbw_timing_end", "lbw_adjoint_work_bytes", "lbw_adjoint_step")
 
 
 class LbwError(RuntimeError):
@@ -95,6 +95,8 @@ def load() -> ctypes.CDLL:
     lib.lbw_export.argtypes = [P, I32, I32, P]
     lib.lbw_import.argtypes = [P, I32, I32, P]
     lib.lbw_reduce.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double)]
+    lib.lbw_adjoint_work_bytes.argtypes = [P, I32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.lbw_adjoint_step.argtypes = [P, I32, P, P, P, P, ctypes.c_double, P, P, P, P, ctypes.c_size_t]
     lib.lbw_timing_begin.argtypes = [P]
     lib.lbw_timing_end.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     for name in EXPORTED:
@@ -275,6 +277,18 @@ class Solver:
         self.stream.synchronize()
         return out
 
+    _FIELDS = {"f": FIELD_F, "c": FIELD_C, "s": FIELD_S, "u": FIELD_U, "deposit": FIELD_DEPOSIT}
+
+    def export_into(self, name, out, run=0):
+        """Canonical copy of a field into an existing device tensor, ordered on
+        the solver's stream (no host synchronisation)."""
+        check(self._lib.lbw_export(self._h, run, self._FIELDS[name], out.data_ptr()))
+
+    def import_from(self, name, src, run=0):
+        """Overwrite a field from a device tensor written on the solver's
+        stream (no host synchronisation)."""
+        check(self._lib.lbw_import(self._h, run, self._FIELDS[name], src.data_ptr()))
+
     def step(self, n=1):
         check(self._lib.lbw_step(self._h, int(n)))
 
@@ -306,6 +320,20 @@ class Solver:
         n = ctypes.c_int64(0)
         check(self._lib.lbw_timing_end(self._h, ms, ctypes.byref(n)))
         return {"collide_stream_ms": ms[0], "transport_ms": ms[1], "steps": n.value}
+
+    def adjoint_workspace(self, run=0):
+        """Device workspace tensor for adjoint_step (allocated by torch)."""
+        n = ctypes.c_size_t(0)
+        check(self._lib.lbw_adjoint_work_bytes(self._h, run, ctypes.byref(n)))
+        with self._torch.cuda.stream(self.stream):
+            return self._torch.empty((n.value + 7) // 8, dtype=self._torch.float64, device=self.device)
+
+    def adjoint_step(self, f_n, c_n, fbar_next, cbar_next, dep_bar, fbar, cbar, vs_bar, work, run=0):
+        """One reverse step (device tensors; see lbw_adjoint_step)."""
+        ptr = lambda t: t.data_ptr() if t is not None else None
+        check(self._lib.lbw_adjoint_step(self._h, run, ptr(f_n), ptr(c_n), ptr(fbar_next),
+                                         ptr(cbar_next), float(dep_bar), ptr(fbar), ptr(cbar),
+                                         ptr(vs_bar), ptr(work), work.numel() * 8))
 
     def setup_workload(self, wl, run=0, seed=None):
         """Initial state of a seeded workload: two-layer scalars, fluid at rest."""

@@ -1,0 +1,217 @@
+"""GPU adjoint against the oracle's adjoint and against finite differences.
+
+* one reverse step in FP64 equals the oracle's reverse step (1e-12 relative);
+* the gradient of the deposited mass through checkpointed steps equals the
+  oracle's step-by-step reverse sweep (FP64) and does not depend on the
+  checkpoint spacing (bitwise);
+* central finite differences of the FP64 forward on 16 seeded directions
+  converge to the adjoint gradient as eps^2 (eps = 1e-4, 1e-5, 1e-6): at
+  eps = 1e-4 they carry an O((eps / 1e-3)^2) truncation error, because the
+  WENO weights vary on the scale of the 1e-3 seeded noise, so the gate is the
+  quadratic convergence and the agreement at 1e-6; the FP32 adjoint's
+  gradient matches the FP64 one.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import OracleConfig
+from paper_2106_07694_amd import adjoint, lbw, workloads as W
+
+from parity import oracle_cfg, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _flowing(ocfg, rng):
+    dim = ocfg.dim
+    u0 = 0.02 * rng.standard_normal((dim,) + ocfg.shape) + np.array(
+        [0.03, 0.02, 0.01][:dim]).reshape((dim, 1, 1, 1))
+    f0 = oracle.equilibrium(ocfg, 1.0 + 0.01 * rng.standard_normal(ocfg.shape), u0)
+    c0 = rng.uniform(0.2, 1.0, ocfg.shape)
+    return f0, c0, u0
+
+
+def _dev(x, dt=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda", dt)
+
+
+@pytest.mark.parametrize("q", [9, 19])
+@pytest.mark.parametrize("frozen", [False, True])
+@pytest.mark.parametrize("vper", [False, True])
+@pytest.mark.parametrize("precision", ["fp64", "fp64_shifted"])
+def test_adjoint_step_matches_oracle(q, frozen, vper, precision):
+    rng = np.random.default_rng(31)
+    shape = dict(nx=13, ny=17) if q == 9 else dict(nx=7, ny=5, nz=11)
+    cfg = lbw.RunConfig(lattice=q, precision=precision, tau=0.7, vs=0.04, kappa_c=2e-3,
+                        gp_c=3e-3, vert_periodic=vper,
+                        fluid_mode=lbw.FLUID_FROZEN if frozen else lbw.FLUID_LBM, **shape)
+    ocfg = oracle_cfg(cfg)
+    f_n, c_n, u0 = _flowing(ocfg, rng)
+    fbar_next = rng.standard_normal((q,) + ocfg.shape)
+    cbar_next = rng.standard_normal(ocfg.shape)
+    dep_bar = 0.7
+    fo, co, vo = oracle.adjoint_step(ocfg, None if frozen else f_n, c_n,
+                                     None if frozen else fbar_next, cbar_next, dep_bar,
+                                     u0 if frozen else None)
+    sol = lbw.Solver(cfg)
+    if frozen:
+        sol.set_field("u", u0)
+    fb = torch.zeros((q,) + ocfg.shape, dtype=torch.float64, device="cuda")
+    cb = torch.zeros(ocfg.shape, dtype=torch.float64, device="cuda")
+    vs = torch.zeros(1, dtype=torch.float64, device="cuda")
+    work = sol.adjoint_workspace()
+    torch.cuda.synchronize()
+    sol.adjoint_step(None if frozen else _dev(f_n), _dev(c_n),
+                     None if frozen else _dev(fbar_next), _dev(cbar_next), dep_bar,
+                     None if frozen else fb, cb, vs, work)
+    torch.cuda.synchronize()
+    errs = {"cbar": rel(cb.cpu().numpy(), co), "vs_bar": abs(vs.item() - vo) / max(abs(vo), 1e-300)}
+    if not frozen:
+        errs["fbar"] = rel(fb.cpu().numpy(), fo)
+    print(f"\nadjoint step q={q} frozen={frozen} vper={vper} {precision}: {errs}")
+    assert max(errs.values()) < 1e-12, errs
+    sol.close()
+
+
+def _oracle_gradient(ocfg, f0, c0, n):
+    fs, cs = [], []
+    f, c = f0, c0
+    for _ in range(n):
+        fs.append(f)
+        cs.append(c)
+        f, c, _, _, _ = oracle.run(ocfg, f, c, None, None, None, 1)
+    fbar = np.zeros((ocfg.q,) + ocfg.shape)
+    cbar = np.zeros(ocfg.shape)
+    vsb = 0.0
+    for k in reversed(range(n)):
+        fbar, cbar, v = oracle.adjoint_step(ocfg, fs[k], cs[k], fbar, cbar, 1.0)
+        vsb += v
+    return cbar, vsb
+
+
+def test_checkpointed_gradient_fp64_matches_oracle():
+    wl = W.C5.replace(nx=24, ny=32, precision="fp64")
+    cfg = lbw.RunConfig.from_workload(wl)
+    c0, _ = W.initial_scalars(wl)
+    n = 12
+    c0t = _dev(c0).requires_grad_(True)
+    vst = torch.tensor(cfg.vs, dtype=torch.float64, requires_grad=True)
+    J = adjoint.DepositedMass.apply(c0t, vst, cfg, n, 5)
+    J.backward()
+    ocfg = oracle_cfg(cfg)
+    cbar_o, vsb_o = _oracle_gradient(ocfg, oracle.equilibrium(ocfg), c0, n)
+    e_c = rel(c0t.grad.cpu().numpy(), cbar_o)
+    e_v = abs(vst.grad.item() - vsb_o) / abs(vsb_o)
+    _, _, _, dep, _ = oracle.run(ocfg, oracle.equilibrium(ocfg), c0, nsteps=n)
+    print(f"\ncheckpointed FP64 gradient vs oracle: dc0 {e_c:.2e}, dvs {e_v:.2e}; "
+          f"J {J.item():.15e} vs {dep.sum():.15e}")
+    assert abs(J.item() - dep.sum()) < 1e-12 * abs(dep.sum())
+    assert e_c < 1e-11 and e_v < 1e-11
+
+
+def test_checkpoint_spacing_does_not_change_the_gradient():
+    wl = W.C5.replace(nx=32, ny=48)
+    cfg = lbw.RunConfig.from_workload(wl)
+    c0, _ = W.initial_scalars(wl)
+    n = 12
+    grads = []
+    for seg in (1, 3, 5, 12):
+        c0t = _dev(c0, torch.float32).requires_grad_(True)
+        vst = torch.tensor(cfg.vs, dtype=torch.float64, requires_grad=True)
+        adjoint.DepositedMass.apply(c0t, vst, cfg, n, seg).backward()
+        grads.append((c0t.grad.cpu().numpy(), vst.grad.item()))
+    for g in grads[1:]:
+        assert np.array_equal(g[0], grads[0][0]) and g[1] == grads[0][1]
+
+
+def _grad(cfg, c0, n, dt, **kw):
+    c0t = _dev(c0, dt).requires_grad_(True)
+    vst = torch.tensor(cfg.vs, dtype=torch.float64, requires_grad=True)
+    adjoint.DepositedMass.apply(c0t, vst, cfg, n, None, None, kw.get("f0"), kw.get("u")).backward()
+    return c0t.grad.double().cpu().numpy(), vst.grad.item()
+
+
+def _fd_errors(cfg64, c0, n, grads, ndirs=16, epss=(1e-4, 1e-5, 1e-6), **kw):
+    """Max relative error over the directions, and the dVs error, per eps."""
+    def J(c, vs=cfg64.vs):
+        J, sol, _ = adjoint.forward_with_checkpoints(cfg64, _dev(c), vs, n, n, None,
+                                                     kw.get("f0"), kw.get("u"))
+        sol.close()
+        return J
+
+    dirs = W.random_directions(ndirs, c0.shape, seed=2024)
+    g = grads["fp64"]
+    out = {}
+    for eps in epss:
+        errs = []
+        for v in dirs:
+            fd = (J(c0 + eps * v) - J(c0 - eps * v)) / (2 * eps)
+            errs.append(abs(np.sum(g[0] * v) - fd) / abs(fd))
+        fdv = (J(c0, cfg64.vs + eps) - J(c0, cfg64.vs - eps)) / (2 * eps)
+        out[eps] = (max(errs), abs(g[1] - fdv) / abs(fdv))
+    return out
+
+
+def _check_fd(out, tol, floor=1e-8):
+    """Agreement at eps = 1e-6 and second-order convergence of the central
+    differences towards the adjoint over both decades of eps."""
+    e4, e5, e6 = out[1e-4][0], out[1e-5][0], out[1e-6][0]
+    v4, v5, v6 = out[1e-4][1], out[1e-5][1], out[1e-6][1]
+    assert e6 < tol and v6 < tol, out
+    for a, b in ((e4, e5), (e5, e6), (v4, v5), (v5, v6)):
+        assert b < 0.05 * a or b < floor, out
+
+
+def test_frozen_gradient_matches_finite_differences():
+    """Transport only, smooth velocity with no sign change on any face:
+    FP64 and FP32 adjoints vs central FD (eps = 1e-4, 16 directions)."""
+    wl = W.C5.replace(nx=128, ny=256)
+    n = 300
+    base = dict(fluid_mode=lbw.FLUID_FROZEN, vs=2e-3)
+    cfg32 = lbw.RunConfig.from_workload(wl, **base)
+    cfg64 = lbw.RunConfig.from_workload(wl, precision="fp64", **base)
+    c0, _ = W.initial_scalars(wl)
+    c0 = c0.astype(np.float32).astype(np.float64)
+    y = np.arange(wl.ny)[None, :, None] / wl.ny
+    x = np.arange(wl.nx)[None, None, :] / wl.nx
+    u = np.zeros((2,) + c0.shape)
+    u[0] = 0.02 + 0.01 * np.sin(2 * np.pi * x) * np.cos(np.pi * y)
+    u[1] = 0.0005 * np.sin(2 * np.pi * x)
+    u = u.astype(np.float32).astype(np.float64)
+    g = {"fp64": _grad(cfg64, c0, n, torch.float64, u=u)}
+    g32 = _grad(cfg32, c0, n, torch.float32, u=u)
+    out = _fd_errors(cfg64, c0, n, g, u=u)
+    l2 = float(np.linalg.norm(g32[0] - g["fp64"][0]) / np.linalg.norm(g["fp64"][0]))
+    print(f"\nfrozen FD check (max rel err over 16 dirs, dVs rel err) per eps: {out}; "
+          f"FP32 vs FP64 gradient L2 {l2:.2e}")
+    _check_fd(out, 1e-5)
+    assert l2 < 1e-3 and abs(g32[1] - g["fp64"][1]) < 1e-3 * abs(g["fp64"][1])
+
+
+def test_coupled_gradient_matches_finite_differences():
+    """Coupled LBM + transport started from a plug flow (lateral velocity
+    bounded away from zero, so no face changes its upwind side): FP64 and
+    FP32 adjoints vs central FD (eps = 1e-4, 16 directions)."""
+    wl = W.C5.replace(nx=128, ny=256)
+    n = 200
+    cfg32 = lbw.RunConfig.from_workload(wl)
+    cfg64 = lbw.RunConfig.from_workload(wl, precision="fp64")
+    c0, _ = W.initial_scalars(wl)
+    c0 = c0.astype(np.float32).astype(np.float64)
+    ocfg = oracle_cfg(cfg64)
+    u0 = np.zeros((2,) + c0.shape)
+    u0[0] = 0.03
+    f0_64 = oracle.equilibrium(ocfg, None, u0)
+    f0_32 = oracle.equilibrium(oracle_cfg(cfg32), None, u0).astype(np.float32).astype(np.float64)
+    g = {"fp64": _grad(cfg64, c0, n, torch.float64, f0=f0_64)}
+    g32 = _grad(cfg32, c0, n, torch.float32, f0=f0_32)
+    out = _fd_errors(cfg64, c0, n, g, f0=f0_64)
+    l2 = float(np.linalg.norm(g32[0] - g["fp64"][0]) / np.linalg.norm(g["fp64"][0]))
+    print(f"\ncoupled FD check (max rel err over 16 dirs, dVs rel err) per eps: {out}; "
+          f"FP32 vs FP64 gradient L2 {l2:.2e}")
+    _check_fd(out, 1e-5)
+    assert l2 < 1e-3 and abs(g32[1] - g["fp64"][1]) < 1e-3 * abs(g["fp64"][1])
