@@ -160,6 +160,67 @@ def run_sweep(steps: int, warmup: int) -> dict:
             "speedup": ms_seq / ms_batched, "launch": launch}
 
 
+def run_adjoint(nsteps: int) -> dict:
+    """Gradient of the deposited mass for the 512x1024 FP32 run: the plain
+    forward, the checkpointed forward (a checkpoint every ~sqrt(N) steps) and
+    the backward (segment replay + reverse steps), each timed end to end."""
+    import torch
+    from paper_2106_07694_amd import adjoint, autotune, lbw, workloads as W
+
+    wl = W.C5
+    cfg = lbw.RunConfig.from_workload(wl)
+    launch = autotune.lookup(wl.name)
+    c0, _ = W.initial_scalars(wl)
+    sol = lbw.Solver(cfg)
+    if launch:
+        sol.set_launch(**launch)
+    sol.setup_workload(wl)
+    sol.step(10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sol.step(nsteps)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    sol.close()
+    c0t = torch.from_numpy(c0).to("cuda", torch.float32).requires_grad_(True)
+    vst = torch.tensor(cfg.vs, dtype=torch.float64, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = adjoint.DepositedMass.apply(c0t, vst, cfg, nsteps, None, launch)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    seg = adjoint.default_segment(nsteps)
+    return {"workload": wl.name, "steps": nsteps, "checkpoint_every": seg,
+            "forward_s": t_plain, "forward_checkpointed_s": t_fwd, "backward_s": t_bwd,
+            "adjoint_forward_ratio": t_bwd / t_plain,
+            "adjoint_vs_checkpointed_forward_ratio": t_bwd / t_fwd,
+            "J": float(J.item()), "dJ_dVs": float(vst.grad.item()),
+            "grad_c0_l2": float(c0t.grad.double().norm().item())}
+
+
+def calibrate_copy(mib: int = 256, reps: int = 3) -> dict:
+    """A plain copy-like kernel of known size (read mib MiB, write mib MiB),
+    run so that profiler counters can be scaled against its known bytes."""
+    import torch
+    n = mib * 1024 * 1024 // 4
+    src = torch.rand(n, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        torch.mul(src, 1.0, out=dst)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    return {"bytes_read": n * 4, "bytes_written": n * 4, "ms": ms,
+            "gbs": 2 * n * 4 / (ms * 1e-3) / 1e9}
+
+
 def cpu_baseline(wl, nz_crop: int, ny_crop: int, steps: int) -> dict:
     """The FP64 oracle as it stands, timed on the host cores on a crop of
     the workload (vertical extent cut), reported as MLUPS."""
@@ -192,6 +253,10 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-also", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=5000)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a known-size copy kernel (profiler counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path "
@@ -226,6 +291,12 @@ def main() -> int:
         print(f"[bench] sweep: batched {sweep['batched_mlups']:.0f} MLUPS, one at a time "
               f"{sweep['sequential_mlups']:.0f} MLUPS ({sweep['speedup']:.1f}x)", file=sys.stderr,
               flush=True)
+    adj = None
+    if not args.no_adjoint:
+        adj = run_adjoint(args.adjoint_steps)
+        print(f"[bench] adjoint: forward {adj['forward_s']:.3f} s, backward {adj['backward_s']:.3f} s "
+              f"(ratio {adj['adjoint_forward_ratio']:.2f})", file=sys.stderr, flush=True)
+    copy = calibrate_copy() if args.calibrate_copy else None
     cpu = None
     if not args.no_cpu_baseline:
         cpu = (cpu_baseline(main_wl, nz_crop=128, ny_crop=0, steps=20) if main_wl.dim == 3
@@ -256,6 +327,8 @@ def main() -> int:
         "cpu_baseline": cpu,
         "also": also,
         "sweep": sweep,
+        "adjoint": adj,
+        "copy_calibration": copy,
     }
     print(json.dumps(line))
     return 0
