@@ -126,11 +126,18 @@ typedef struct {
     int32_t tile_x;        /* transport tile width: 32, 64, 128 (3D) or
                               64, 128, 256 (2D) columns */
     int32_t tile_y;        /* transport chunk: vertical planes per block */
-    int32_t variant;       /* transport kernels: 0 tiled (LDS, marching),
-                              1 plain (one thread per node, no LDS) */
+    int32_t variant;       /* 0 tiled transport (LDS, marching) after the
+                              collide-stream kernel; 1 plain transport (one
+                              thread per node, no LDS); 2 pipelined: the
+                              vertical axis is cut into slabs and the
+                              collide-stream of step n+1 on a slab runs on a
+                              second stream, overlapping the transport of step
+                              n on the slabs above it (single run with walls;
+                              a periodic vertical axis takes variant 0) */
     int32_t graph;         /* 1: lbw_step replays a captured HIP graph of two
                               steps (needs a non-null stream; the graph is
                               runtime-owned and rebuilt after lbw_set_launch) */
+    int32_t slabs;         /* pipelined variant: number of vertical slabs */
 } lbw_launch;
 
 /* Library ABI version (LBW_ABI_VERSION). */
@@ -192,7 +199,7 @@ int lbw_import(lbw_handle *h, int32_t run, int32_t field, const void *src);
 
 /* FP64 sums per run into out_host[nbatch]: LBW_MASS_C (sum C), LBW_MASS_S
  * (sum S), LBW_MASS_FLUID (sum rho), LBW_DEPOSIT (sum of the deposit
- * counters), the particle mass and deposited mass m_b of section 4.3.
+ * counters), the particle mass and deposited mass m_b of section 4.2.3.
  * Wavefront shuffles, per-block partials, then a fixed-order final pass:
  * the result is bitwise reproducible.  Synchronises the stream.  Returns
  * LBW_ERR_NONFINITE if any sum is NaN or Inf (the values are still written). */
@@ -210,7 +217,7 @@ int lbw_adjoint_work_bytes(const lbw_handle *h, int32_t run, size_t *out_bytes);
  *                writes them; C), device arrays of the run's element type;
  *   fbar_next    dJ/df^{n+1} (canonical layout); cbar_next = dJ/dC^{n+1};
  *   dep_bar      dJ/d(deposit) of every column (1 for the total deposited
- *                mass m_b of section 4.3);
+ *                mass m_b of section 4.2.3);
  *   fbar, cbar   out: dJ/df^n and dJ/dC^n (must not alias the inputs);
  *   vs_bar_dev   device FP64 scalar: += dJ/dVs through this step;
  *   work         device workspace of lbw_adjoint_work_bytes bytes.
@@ -223,12 +230,14 @@ int lbw_adjoint_step(lbw_handle *h, int32_t run, const void *f_n, const void *c_
                      void *cbar, double *vs_bar_dev, void *work, size_t work_bytes);
 
 /* Per-phase GPU time of the lbw_step calls made between lbw_timing_begin and
- * lbw_timing_end: HIP events are recorded on the handle's stream around the
- * collide-stream launches and around the transport launches of every step.
- * lbw_timing_end waits for the last event and writes the summed milliseconds
- * per phase to ms_out[LBW_NPHASES] and the number of steps timed to *steps.
- * The events are host-side objects created by the runtime (no device memory
- * is allocated); timing adds two event records per phase and step. */
+ * lbw_timing_end: HIP events are recorded on the stream each launch goes to,
+ * around every collide-stream launch and around the transport launches of
+ * every step (around each slab's kernels in the pipelined variant, where
+ * the phases overlap in time and each span includes the slow-down from the
+ * kernels running beside it).  lbw_timing_end waits for the events and writes
+ * the summed milliseconds per phase to ms_out[LBW_NPHASES] and the number of
+ * steps timed to *steps.  Events are host-side runtime objects, pooled in the
+ * handle; graph replay is not used while timing. */
 int lbw_timing_begin(lbw_handle *h);
 int lbw_timing_end(lbw_handle *h, double *ms_out, int64_t *steps);
 

@@ -14,6 +14,11 @@
  * The vertical axis (gravity, walls) is y in 2D and z in 3D.
  *
  * Every routine returns 0 on success and a negative value on bad arguments.
+ *
+ * Pins (tests/test_oracle_*.py): closed forms and invariants for every part,
+ * except the ghost values the WENO stencils see beyond a wall (mirrored
+ * scalar, sign-flipped vertical fluid velocity): parity unpinned beyond the
+ * particle budget and the uniform-layer deposit, which they must satisfy.
  */
 #ifndef LBW_ORACLE_H
 #define LBW_ORACLE_H

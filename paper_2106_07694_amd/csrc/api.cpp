@@ -23,9 +23,21 @@ struct lbw_handle {
     std::vector<lbw::RunDev> run;
     int64_t steps = 0;
     bool odd = false;  // next collide-stream kernel is the odd one of the pair
-    lbw_launch launch{256, 0, 0, 0, 0};
+    lbw_launch launch{256, 0, 0, 0, 0, 0};
+    // timing: spans (phase, start, end) drawn from a pool of events
     bool timing = false;
-    std::vector<hipEvent_t> events;  // 2 per phase per timed step
+    struct Span {
+        int phase;
+        hipEvent_t a, b;
+    };
+    std::vector<Span> spans;
+    std::vector<hipEvent_t> pool;
+    size_t pool_used = 0;
+    int64_t timed_steps = 0;
+    // pipelined variant: second stream and the slab events
+    hipStream_t side = nullptr;
+    std::vector<hipEvent_t> ev_lbm, ev_tr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool sflip = false;              // S currently lives in s_tmp
     int num_cu = 256;
     // batched mode (nbatch > 1): tables in run 0's scratch
@@ -275,7 +287,15 @@ int lbw_create(const lbw_config *cfgs, const lbw_buffers *bufs, int32_t nbatch, 
 
 void lbw_destroy(lbw_handle *h) {
     if (!h) return;
-    for (hipEvent_t ev : h->events) (void)hipEventDestroy(ev);
+    for (hipEvent_t ev : h->pool) (void)hipEventDestroy(ev);
+    for (hipEvent_t ev : h->ev_lbm) (void)hipEventDestroy(ev);
+    for (hipEvent_t ev : h->ev_tr) (void)hipEventDestroy(ev);
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    if (h->side) {
+        (void)hipStreamSynchronize(h->side);
+        (void)hipStreamDestroy(h->side);
+    }
     release_graph(h);
     delete h;
 }
@@ -298,8 +318,12 @@ int lbw_set_launch(lbw_handle *h, const lbw_launch *l) {
         if (l->tile_y < 1 || l->tile_y > 4096) return fail(LBW_ERR_INVAL, "tile_y must lie in [1, 4096]");
         n.tile_y = l->tile_y;
     }
-    if (l->variant < 0 || l->variant > 1) return fail(LBW_ERR_INVAL, "variant must be 0 or 1");
+    if (l->variant < 0 || l->variant > 2) return fail(LBW_ERR_INVAL, "variant must be 0, 1 or 2");
+    if (l->variant == 2 && h->nbatch > 1)
+        return fail(LBW_ERR_UNSUPPORTED, "the pipelined variant drives a single run");
     n.variant = l->variant;
+    if (l->slabs < 0 || l->slabs > 64) return fail(LBW_ERR_INVAL, "slabs must lie in [0, 64]");
+    n.slabs = l->slabs;
     if (l->graph < 0 || l->graph > 1) return fail(LBW_ERR_INVAL, "graph must be 0 or 1");
     n.graph = l->graph;
     h->launch = n;
@@ -322,14 +346,29 @@ int lbw_init_equilibrium(lbw_handle *h, int32_t run, const void *rho, const void
 }
 
 namespace {
-// Record one timing event on the handle's stream (timing mode only).
-int mark(lbw_handle *h) {
-    if (!h->timing) return LBW_OK;
-    hipEvent_t ev;
-    hipError_t e = hipEventCreate(&ev);
-    if (e != hipSuccess) return hip_fail(e, "event create");
-    h->events.push_back(ev);
-    e = hipEventRecord(ev, h->stream);
+hipEvent_t pooled_event(lbw_handle *h) {
+    if (h->pool_used < h->pool.size()) return h->pool[h->pool_used++];
+    hipEvent_t ev = nullptr;
+    if (hipEventCreate(&ev) != hipSuccess) return nullptr;
+    h->pool.push_back(ev);
+    ++h->pool_used;
+    return ev;
+}
+
+// Open a timing span of `phase` on stream st (timing mode only); returns its
+// index or -1.
+int span_open(lbw_handle *h, int phase, hipStream_t st) {
+    if (!h->timing) return -1;
+    lbw_handle::Span sp{phase, pooled_event(h), pooled_event(h)};
+    if (!sp.a || !sp.b || hipEventRecord(sp.a, st) != hipSuccess) return -2;
+    h->spans.push_back(sp);
+    return (int)h->spans.size() - 1;
+}
+
+int span_close(lbw_handle *h, int idx, hipStream_t st) {
+    if (idx == -1) return LBW_OK;
+    if (idx < 0) return fail(LBW_ERR_HIP, "timing event unavailable");
+    hipError_t e = hipEventRecord(h->spans[idx].b, st);
     return e == hipSuccess ? LBW_OK : hip_fail(e, "event record");
 }
 }  // namespace
@@ -339,7 +378,7 @@ namespace {
 // state (streaming parity, S buffer roles, step count).
 int enqueue_step(lbw_handle *h) {
     int rc;
-    if ((rc = mark(h))) return rc;
+    int sp = span_open(h, LBW_PHASE_COLLIDE_STREAM, h->stream);
     if (h->fluid_mode == LBW_FLUID_LBM) {
         hipError_t e;
         if (h->nbatch > 1)
@@ -351,8 +390,8 @@ int enqueue_step(lbw_handle *h) {
                                            h->launch.lbm_block, h->stream);
         if (e != hipSuccess) return hip_fail(e, "collide-stream launch");
     }
-    if ((rc = mark(h))) return rc;
-    if ((rc = mark(h))) return rc;
+    if ((rc = span_close(h, sp, h->stream))) return rc;
+    sp = span_open(h, LBW_PHASE_TRANSPORT, h->stream);
     if (h->nbatch > 1 && h->launch.variant == 0) {
         lbw::BatchArgs a;
         a.runs = h->d_runs;
@@ -370,7 +409,100 @@ int enqueue_step(lbw_handle *h) {
             if (e != hipSuccess) return hip_fail(e, "transport launch");
         }
     }
-    if ((rc = mark(h))) return rc;
+    if ((rc = span_close(h, sp, h->stream))) return rc;
+    if (h->timing) ++h->timed_steps;
+    if (h->has_s) h->sflip = !h->sflip;
+    if (h->fluid_mode == LBW_FLUID_LBM) h->odd = !h->odd;
+    ++h->steps;
+    return LBW_OK;
+}
+
+// Vertical slabs of the pipelined variant: chunk-aligned plane ranges.
+void slab_planes(const lbw_handle *h, int nslab, std::vector<int> &lo, std::vector<int> &hi) {
+    const lbw::RunDev &r = h->run[0];
+    const int nv = h->dim == 3 ? r.nz : r.ny;
+    int chunk = lbw::resolve_tile_shape(h->dim, h->launch).chunk;
+    if (chunk > nv) chunk = nv;
+    const int nch = (nv + chunk - 1) / chunk;
+    const int P = std::max(1, std::min(nslab, nch));
+    lo.resize(P);
+    hi.resize(P);
+    for (int p = 0; p < P; ++p) {
+        lo[p] = (int)((int64_t)nch * p / P) * chunk;
+        hi[p] = std::min(nv, (int)((int64_t)nch * (p + 1) / P) * chunk);
+    }
+}
+
+int ensure_pipeline(lbw_handle *h, int P) {
+    hipError_t e = hipSuccess;
+    if (!h->side) e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
+    if (e == hipSuccess && !h->ev_fork) e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess && !h->ev_join) e = hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming);
+    while (e == hipSuccess && (int)h->ev_lbm.size() < P) {
+        hipEvent_t a = nullptr, b = nullptr;
+        e = hipEventCreateWithFlags(&a, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b, hipEventDisableTiming);
+        if (a) h->ev_lbm.push_back(a);
+        if (b) h->ev_tr.push_back(b);
+    }
+    return e == hipSuccess ? LBW_OK : hip_fail(e, "pipeline stream/events");
+}
+
+// One step of the pipelined variant.  Stream A (the handle's) runs the
+// collide-stream kernel slab by slab; stream B runs the three RK stages in a
+// wavefront over the slabs.  Slab p of stage 1 waits for the collide-stream of
+// slabs up to p+1 (its velocity halo); stages 2 and 3 follow stage 1 on B; the
+// collide-stream of the next step on slab p waits for stage 3 (and S) on
+// slabs up to p+1, which also retires every reader of this step's velocity
+// and concentration in slab p.  `primed` says whether B's events of the
+// previous step are pending in this call.
+int enqueue_step_pipelined(lbw_handle *h, bool primed) {
+    std::vector<int> lo, hi;
+    slab_planes(h, h->launch.slabs > 0 ? h->launch.slabs : 8, lo, hi);
+    const int P = (int)lo.size();
+    int rc = ensure_pipeline(h, P);
+    if (rc) return rc;
+    hipStream_t A = h->stream, B = h->side;
+    const lbw::RunDev r = current(h, 0);
+    const int64_t sv = h->dim == 3 ? (int64_t)r.nx * r.ny : (int64_t)r.nx;
+    hipError_t e;
+    for (int p = 0; p < P; ++p) {
+        if (primed) {
+            e = hipStreamWaitEvent(A, h->ev_tr[std::min(p + 1, P - 1)], 0);
+            if (e != hipSuccess) return hip_fail(e, "stream wait");
+        }
+        if (h->fluid_mode == LBW_FLUID_LBM) {
+            const int sp = span_open(h, LBW_PHASE_COLLIDE_STREAM, A);
+            e = lbw::launch_collide_stream(h->q, h->precision, r, h->odd, h->launch.lbm_block, A,
+                                           lo[p] * sv, hi[p] * sv);
+            if (e != hipSuccess) return hip_fail(e, "collide-stream launch");
+            if ((rc = span_close(h, sp, A))) return rc;
+        }
+        e = hipEventRecord(h->ev_lbm[p], A);
+        if (e != hipSuccess) return hip_fail(e, "event record");
+    }
+    for (int i = 0; i < P + 2; ++i) {
+        const int sp = span_open(h, LBW_PHASE_TRANSPORT, B);
+        if (i < P) {
+            e = hipStreamWaitEvent(B, h->ev_lbm[std::min(i + 1, P - 1)], 0);
+            if (e == hipSuccess) e = lbw::launch_stage_slab(h->dim, h->precision, r, h->launch, 1, lo[i], hi[i], B);
+            if (e != hipSuccess) return hip_fail(e, "stage 1 launch");
+        }
+        if (i >= 1 && i <= P) {
+            e = lbw::launch_stage_slab(h->dim, h->precision, r, h->launch, 2, lo[i - 1], hi[i - 1], B);
+            if (e != hipSuccess) return hip_fail(e, "stage 2 launch");
+        }
+        if (i >= 2) {
+            const int q = i - 2;
+            e = lbw::launch_stage_slab(h->dim, h->precision, r, h->launch, 3, lo[q], hi[q], B);
+            if (e == hipSuccess && h->has_s) e = lbw::launch_s_update(h->dim, h->precision, r, B, lo[q] * sv, hi[q] * sv);
+            if (e != hipSuccess) return hip_fail(e, "stage 3 launch");
+            e = hipEventRecord(h->ev_tr[q], B);
+            if (e != hipSuccess) return hip_fail(e, "event record");
+        }
+        if ((rc = span_close(h, sp, B))) return rc;
+    }
+    if (h->timing) ++h->timed_steps;
     if (h->has_s) h->sflip = !h->sflip;
     if (h->fluid_mode == LBW_FLUID_LBM) h->odd = !h->odd;
     ++h->steps;
@@ -413,7 +545,21 @@ int lbw_step(lbw_handle *h, int32_t nsteps) {
     if (!h) return fail(LBW_ERR_INVAL, "NULL handle");
     if (nsteps < 0) return fail(LBW_ERR_INVAL, "nsteps must be >= 0");
     int rc;
-    if (h->launch.graph && !h->timing && nsteps >= 2) {
+    // the slab order assumes walls: a periodic vertical axis couples the first
+    // and last slabs, so such runs take the sequential order
+    if (h->launch.variant == 2 && !h->run[0].vper && nsteps > 0) {
+        if ((rc = ensure_pipeline(h, 1))) return rc;
+        // B starts after everything already queued on A, A ends after B
+        hipError_t e = hipEventRecord(h->ev_fork, h->stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(h->side, h->ev_fork, 0);
+        if (e != hipSuccess) return hip_fail(e, "pipeline fork");
+        for (int32_t s = 0; s < nsteps; ++s)
+            if ((rc = enqueue_step_pipelined(h, s > 0))) return rc;
+        e = hipEventRecord(h->ev_join, h->side);
+        if (e == hipSuccess) e = hipStreamWaitEvent(h->stream, h->ev_join, 0);
+        return e == hipSuccess ? LBW_OK : hip_fail(e, "pipeline join");
+    }
+    if (h->launch.graph && h->launch.variant != 2 && !h->timing && nsteps >= 2) {  // never pipelined
         if (!h->stream) return fail(LBW_ERR_UNSUPPORTED, "graph replay needs a non-null stream");
         if (!h->gexec || h->graph_odd != h->odd || h->graph_sflip != h->sflip)
             if ((rc = build_graph(h))) return rc;
@@ -461,8 +607,9 @@ int lbw_adjoint_step(lbw_handle *h, int32_t run, const void *f_n, const void *c_
 
 int lbw_timing_begin(lbw_handle *h) {
     if (!h) return fail(LBW_ERR_INVAL, "NULL handle");
-    for (hipEvent_t ev : h->events) (void)hipEventDestroy(ev);
-    h->events.clear();
+    h->spans.clear();
+    h->pool_used = 0;
+    h->timed_steps = 0;
     h->timing = true;
     return LBW_OK;
 }
@@ -471,22 +618,20 @@ int lbw_timing_end(lbw_handle *h, double *ms_out, int64_t *steps) {
     if (!h || !ms_out || !steps) return fail(LBW_ERR_INVAL, "NULL argument");
     h->timing = false;
     for (int p = 0; p < LBW_NPHASES; ++p) ms_out[p] = 0.0;
-    *steps = (int64_t)(h->events.size() / 4);
+    *steps = h->timed_steps;
     int rc = LBW_OK;
-    if (!h->events.empty()) {
-        hipError_t e = hipEventSynchronize(h->events.back());
-        if (e != hipSuccess) rc = hip_fail(e, "event sync");
-        for (size_t i = 0; rc == LBW_OK && i + 3 < h->events.size(); i += 4) {
-            float a = 0.f, b = 0.f;
-            e = hipEventElapsedTime(&a, h->events[i], h->events[i + 1]);
-            if (e == hipSuccess) e = hipEventElapsedTime(&b, h->events[i + 2], h->events[i + 3]);
-            if (e != hipSuccess) rc = hip_fail(e, "event elapsed");
-            ms_out[LBW_PHASE_COLLIDE_STREAM] += a;
-            ms_out[LBW_PHASE_TRANSPORT] += b;
+    for (const auto &sp : h->spans) {
+        hipError_t e = hipEventSynchronize(sp.b);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, sp.a, sp.b);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "event elapsed");
+            break;
         }
+        ms_out[sp.phase] += ms;
     }
-    for (hipEvent_t ev : h->events) (void)hipEventDestroy(ev);
-    h->events.clear();
+    h->spans.clear();
+    h->pool_used = 0;
     return rc;
 }
 

@@ -1,5 +1,5 @@
 // reduce.hip -- FP64 global sums of a run: particle mass sum C, sugar sum S,
-// fluid mass sum rho and the deposited mass m_b (section 4.3: mass of
+// fluid mass sum rho and the deposited mass m_b (section 4.2.3: mass of
 // particles per cell and mass accumulated at the bottom).  Each block
 // accumulates a grid-stride slice in double, reduces it across the wavefront
 // with shuffles and across waves through LDS, and writes one partial; a

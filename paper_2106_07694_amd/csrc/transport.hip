@@ -108,9 +108,9 @@ __global__ void __launch_bounds__(256) k_rk_stage(RunDev r) {
 }
 
 template <typename T, int D>
-__global__ void __launch_bounds__(256) k_s_euler(RunDev r) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= r.N) return;
+__global__ void __launch_bounds__(256) k_s_euler(RunDev r, int64_t k0, int64_t k1) {
+    const int64_t k = k0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= k1) return;
     int x, y, z;
     node_coords<D>(r, k, x, y, z);
     const T *__restrict__ s = (const T *)r.s;
@@ -125,7 +125,7 @@ hipError_t transport_t(const RunDev &r, hipStream_t st) {
     const dim3 grid((unsigned)((r.N + block - 1) / block));
     k_rk_stage<T, D, SCHEME, 1><<<grid, block, 0, st>>>(r);
     k_rk_stage<T, D, SCHEME, 2><<<grid, block, 0, st>>>(r);
-    if (r.has_s) k_s_euler<T, D><<<grid, block, 0, st>>>(r);
+    if (r.has_s) k_s_euler<T, D><<<grid, block, 0, st>>>(r, 0, r.N);
     k_rk_stage<T, D, SCHEME, 3><<<grid, block, 0, st>>>(r);
     return hipGetLastError();
 }
@@ -142,15 +142,18 @@ hipError_t transport_d(const RunDev &r, hipStream_t st) {
 
 }  // namespace
 
-hipError_t launch_s_update(int dim, int precision, const RunDev &r, hipStream_t st) {
+hipError_t launch_s_update(int dim, int precision, const RunDev &r, hipStream_t st, int64_t k0,
+                           int64_t k1) {
+    if (k1 < 0) k1 = r.N;
+    if (k0 >= k1) return hipSuccess;
     const int block = 256;
-    const dim3 grid((unsigned)((r.N + block - 1) / block));
+    const dim3 grid((unsigned)((k1 - k0 + block - 1) / block));
     if (precision == LBW_FP32_SHIFTED) {
-        if (dim == 2) k_s_euler<float, 2><<<grid, block, 0, st>>>(r);
-        else k_s_euler<float, 3><<<grid, block, 0, st>>>(r);
+        if (dim == 2) k_s_euler<float, 2><<<grid, block, 0, st>>>(r, k0, k1);
+        else k_s_euler<float, 3><<<grid, block, 0, st>>>(r, k0, k1);
     } else {
-        if (dim == 2) k_s_euler<double, 2><<<grid, block, 0, st>>>(r);
-        else k_s_euler<double, 3><<<grid, block, 0, st>>>(r);
+        if (dim == 2) k_s_euler<double, 2><<<grid, block, 0, st>>>(r, k0, k1);
+        else k_s_euler<double, 3><<<grid, block, 0, st>>>(r, k0, k1);
     }
     return hipGetLastError();
 }
@@ -180,7 +183,7 @@ hipError_t launch_rk_stages12(int dim, int precision, const RunDev &r, hipStream
 
 hipError_t launch_transport(int dim, int precision, const RunDev &r, const lbw_launch &l,
                             hipStream_t st) {
-    if (l.variant == 0) return launch_transport_tiled(dim, precision, r, l, st);
+    if (l.variant != 1) return launch_transport_tiled(dim, precision, r, l, st);
     if (precision == LBW_FP32_SHIFTED)
         return dim == 2 ? transport_d<float, 2>(r, st) : transport_d<float, 3>(r, st);
     return dim == 2 ? transport_d<double, 2>(r, st) : transport_d<double, 3>(r, st);

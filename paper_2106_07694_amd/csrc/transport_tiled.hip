@@ -22,8 +22,10 @@ namespace {
 template <typename T> __device__ __forceinline__ T fast_rcp(T x) { return (T)1 / x; }
 template <> __device__ __forceinline__ float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// WENO5-JS face value (same formula as weno5_face) with reciprocals in place
-// of divisions.
+// WENO5-JS face value (same formula as weno5_face) with one reciprocal:
+// alpha_k = d_k / e_k^2 (e_k = eps + indicator k) is multiplied through by
+// e_0^2 e_1^2 e_2^2, which cancels between numerator and denominator.  With
+// e_k >= eps = 1e-6 every product stays far inside the single-precision range.
 template <typename T>
 __device__ __forceinline__ T weno5_rcp(T h0, T h1, T h2, T h3, T h4, T a0, T a1, T a2, T a3, T a4,
                                        T eps) {
@@ -38,10 +40,9 @@ __device__ __forceinline__ T weno5_rcp(T h0, T h1, T h2, T h3, T h4, T a0, T a1,
     t = a2 - (T)2 * a3 + a4;
     s = (T)3 * a2 - (T)4 * a3 + a4;
     const T e2 = eps + ((T)(13.0 / 12.0) * t * t + (T)0.25 * s * s);
-    const T al0 = (T)0.1 * fast_rcp<T>(e0 * e0);
-    const T al1 = (T)0.6 * fast_rcp<T>(e1 * e1);
-    const T al2 = (T)0.3 * fast_rcp<T>(e2 * e2);
-    return (al0 * q0 + al1 * q1 + al2 * q2) * fast_rcp<T>((T)6 * (al0 + al1 + al2));
+    const T s0 = e0 * e0, s1 = e1 * e1, s2 = e2 * e2;
+    const T b0 = (T)0.1 * (s1 * s2), b1 = (T)0.6 * (s0 * s2), b2 = (T)0.3 * (s0 * s1);
+    return (b0 * q0 + b1 * q1 + b2 * q2) * fast_rcp<T>((T)6 * (b0 + b1 + b2));
 }
 
 template <typename T>
@@ -85,7 +86,8 @@ struct TileGeom {
     int64_t N;
     int vper;
     int chunk;          // vertical planes per block
-    int gx, gy, gz;     // tiles along x, y and vertical chunks
+    int gx, gy, gz;     // tiles along x, y and vertical chunks launched
+    int bz0;            // first vertical chunk launched
 };
 
 // Position of the block: blocks are dealt round-robin to the 8 XCDs, so the
@@ -102,7 +104,7 @@ __device__ __forceinline__ void block_tile(const TileGeom &g, int &bx, int &by, 
     bx = logical % g.gx;
     const int t = logical / g.gx;
     by = t % g.gy;
-    bz = t / g.gy;
+    bz = g.bz0 + t / g.gy;
 }
 
 template <typename T, int D, int SCHEME, int STAGE, int TX, int TY>
@@ -332,6 +334,7 @@ __host__ __device__ inline TileGeom make_geom(const RunDev &r, int chunk, int TX
     g.gx = (r.nx + TX - 1) / TX;
     g.gy = (D == 3) ? (r.ny + TY - 1) / TY : 1;
     g.gz = (g.nv + g.chunk - 1) / g.chunk;
+    g.bz0 = 0;
     return g;
 }
 
@@ -375,6 +378,46 @@ hipError_t stages(const RunDev &r, int chunk, hipStream_t st) {
     }
     k_stage_tiled<T, D, SCHEME, 3, TX, TY><<<(unsigned)nb, TX * TY, 0, st>>>(r, g);
     return hipGetLastError();
+}
+
+template <typename T, int D, int SCHEME, int TX, int TY>
+hipError_t stage_slab_t(const RunDev &r, int chunk, int stage, int v_lo, int v_hi, hipStream_t st) {
+    TileGeom g = make_geom<D>(r, chunk, TX, TY);
+    const int c0 = v_lo / g.chunk, c1 = (v_hi + g.chunk - 1) / g.chunk;
+    if (v_lo % g.chunk || c1 > g.gz || c0 >= c1) return hipErrorInvalidValue;
+    g.bz0 = c0;
+    g.gz = c1 - c0;
+    const int64_t nb = (int64_t)g.gx * g.gy * g.gz;
+    if (stage == 1) k_stage_tiled<T, D, SCHEME, 1, TX, TY><<<(unsigned)nb, TX * TY, 0, st>>>(r, g);
+    else if (stage == 2) k_stage_tiled<T, D, SCHEME, 2, TX, TY><<<(unsigned)nb, TX * TY, 0, st>>>(r, g);
+    else k_stage_tiled<T, D, SCHEME, 3, TX, TY><<<(unsigned)nb, TX * TY, 0, st>>>(r, g);
+    return hipGetLastError();
+}
+
+template <typename T, int D, int SCHEME>
+hipError_t stage_slab_shape(const RunDev &r, const lbw_launch &l, int stage, int v_lo, int v_hi,
+                            hipStream_t st) {
+    const TileShape sh = resolve_tile_shape(D, l);
+    if constexpr (D == 3) {
+        if (sh.tx == 64) return stage_slab_t<T, D, SCHEME, 64, 4>(r, sh.chunk, stage, v_lo, v_hi, st);
+        if (sh.tx == 128) return stage_slab_t<T, D, SCHEME, 128, 2>(r, sh.chunk, stage, v_lo, v_hi, st);
+        return stage_slab_t<T, D, SCHEME, 32, 8>(r, sh.chunk, stage, v_lo, v_hi, st);
+    } else {
+        if (sh.tx == 64) return stage_slab_t<T, D, SCHEME, 64, 1>(r, sh.chunk, stage, v_lo, v_hi, st);
+        if (sh.tx == 128) return stage_slab_t<T, D, SCHEME, 128, 1>(r, sh.chunk, stage, v_lo, v_hi, st);
+        return stage_slab_t<T, D, SCHEME, 256, 1>(r, sh.chunk, stage, v_lo, v_hi, st);
+    }
+}
+
+template <typename T, int D>
+hipError_t stage_slab_d(const RunDev &r, const lbw_launch &l, int stage, int v_lo, int v_hi,
+                        hipStream_t st) {
+    switch (r.scheme) {
+        case LBW_WENO5: return stage_slab_shape<T, D, LBW_WENO5>(r, l, stage, v_lo, v_hi, st);
+        case LBW_WENO3: return stage_slab_shape<T, D, LBW_WENO3>(r, l, stage, v_lo, v_hi, st);
+        case LBW_UPWIND1: return stage_slab_shape<T, D, LBW_UPWIND1>(r, l, stage, v_lo, v_hi, st);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <typename T, int D, int SCHEME, int TX, int TY>
@@ -456,6 +499,15 @@ hipError_t launch_transport_tiled(int dim, int precision, const RunDev &r, const
     if (precision == LBW_FP32_SHIFTED)
         return dim == 2 ? tiled_d<float, 2>(r, l, st, nullptr) : tiled_d<float, 3>(r, l, st, nullptr);
     return dim == 2 ? tiled_d<double, 2>(r, l, st, nullptr) : tiled_d<double, 3>(r, l, st, nullptr);
+}
+
+hipError_t launch_stage_slab(int dim, int precision, const RunDev &r, const lbw_launch &l,
+                             int stage, int v_lo, int v_hi, hipStream_t st) {
+    if (precision == LBW_FP32_SHIFTED)
+        return dim == 2 ? stage_slab_d<float, 2>(r, l, stage, v_lo, v_hi, st)
+                        : stage_slab_d<float, 3>(r, l, stage, v_lo, v_hi, st);
+    return dim == 2 ? stage_slab_d<double, 2>(r, l, stage, v_lo, v_hi, st)
+                    : stage_slab_d<double, 3>(r, l, stage, v_lo, v_hi, st);
 }
 
 hipError_t launch_transport_batched(int dim, int precision, const BatchArgs &b, const lbw_launch &l,

@@ -65,7 +65,7 @@ class CBuffers(ctypes.Structure):
 class CLaunch(ctypes.Structure):
     _fields_ = [("lbm_block", ctypes.c_int32), ("tile_x", ctypes.c_int32),
                 ("tile_y", ctypes.c_int32), ("variant", ctypes.c_int32),
-                ("graph", ctypes.c_int32)]
+                ("graph", ctypes.c_int32), ("slabs", ctypes.c_int32)]
 
 
 _lib = None
@@ -297,15 +297,15 @@ class Solver:
         check(self._lib.lbw_steps_done(self._h, ctypes.byref(v)))
         return v.value
 
-    def set_launch(self, lbm_block=0, tile_x=0, tile_y=0, variant=0, graph=0):
-        lc = CLaunch(lbm_block, tile_x, tile_y, variant, graph)
+    def set_launch(self, lbm_block=0, tile_x=0, tile_y=0, variant=0, graph=0, slabs=0):
+        lc = CLaunch(lbm_block, tile_x, tile_y, variant, graph, slabs)
         check(self._lib.lbw_set_launch(self._h, ctypes.byref(lc)))
 
     def get_launch(self) -> dict:
         lc = CLaunch()
         check(self._lib.lbw_get_launch(self._h, ctypes.byref(lc)))
         return {"lbm_block": lc.lbm_block, "tile_x": lc.tile_x, "tile_y": lc.tile_y,
-                "variant": lc.variant, "graph": lc.graph}
+                "variant": lc.variant, "graph": lc.graph, "slabs": lc.slabs}
 
     def reduce(self, what) -> np.ndarray:
         out = (ctypes.c_double * self.nbatch)()

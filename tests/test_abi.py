@@ -116,14 +116,18 @@ def test_launch_shape_validation():
     h = ctypes.c_void_p()
     assert lib.lbw_create(ctypes.byref(c), ctypes.byref(b), 1, None, ctypes.byref(h)) == 0
     try:
-        ok = lbw.CLaunch(512, 128, 16, 1, 1)
+        ok = lbw.CLaunch(512, 128, 16, 1, 1, 0)
         assert lib.lbw_set_launch(h, ctypes.byref(ok)) == 0
         got = lbw.CLaunch()
         assert lib.lbw_get_launch(h, ctypes.byref(got)) == 0
         assert (got.lbm_block, got.tile_x, got.tile_y, got.variant, got.graph) == (512, 128, 16, 1, 1)
-        for bad in (lbw.CLaunch(100, 0, 0, 0, 0), lbw.CLaunch(2048, 0, 0, 0, 0),
-                    lbw.CLaunch(0, 96, 0, 0, 0), lbw.CLaunch(0, 32, 0, 0, 0),
-                    lbw.CLaunch(0, 0, 0, 2, 0), lbw.CLaunch(0, 0, 0, 0, 3)):
+        assert lib.lbw_set_launch(h, ctypes.byref(lbw.CLaunch(0, 0, 0, 2, 0, 6))) == 0
+        lib.lbw_get_launch(h, ctypes.byref(got))
+        assert (got.variant, got.slabs) == (2, 6)
+        for bad in (lbw.CLaunch(100, 0, 0, 0, 0, 0), lbw.CLaunch(2048, 0, 0, 0, 0, 0),
+                    lbw.CLaunch(0, 96, 0, 0, 0, 0), lbw.CLaunch(0, 32, 0, 0, 0, 0),
+                    lbw.CLaunch(0, 0, 0, 3, 0, 0), lbw.CLaunch(0, 0, 0, 0, 3, 0),
+                    lbw.CLaunch(0, 0, 0, 2, 0, 65)):
             assert lib.lbw_set_launch(h, ctypes.byref(bad)) == lbw.ERR_INVAL
         assert lib.lbw_step(h, -1) == lbw.ERR_INVAL
         v = ctypes.c_int64(-1)
