@@ -7,7 +7,7 @@ transport tile (width, vertical chunk) with the least transport time.  The
 winners are cached in ``tuned.json`` beside this file, keyed by workload
 name, with the device architecture, grid and precision they were taken on.
 
-    python -m paper_2106_07694_amd.autotune [3d|2d|sweep|all]
+    python -m paper_2106_07694_amd.autotune [3d|2d|adjoint|sweep|all]
 """
 from __future__ import annotations
 
@@ -97,6 +97,8 @@ def main(which: str = "all") -> int:
         jobs.append((W.C3.name, [lbw.RunConfig.from_workload(W.C3)], [W.C3], False))
     if which in ("2d", "all"):
         jobs.append((W.C2.name, [lbw.RunConfig.from_workload(W.C2)], [W.C2], False))
+    if which in ("adjoint", "all"):
+        jobs.append((W.C5.name, [lbw.RunConfig.from_workload(W.C5)], [W.C5], False))
     if which in ("sweep", "all"):
         runs = W.sweep_runs()
         jobs.append(("sweep_64", [lbw.RunConfig.from_workload(w) for w in runs], runs, True))

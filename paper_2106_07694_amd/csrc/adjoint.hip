@@ -400,7 +400,7 @@ __global__ void __launch_bounds__(256) k_adj_vs_final(const double *__restrict__
 }
 
 template <int Q, typename T, bool SH>
-hipError_t adjoint_t(const AdjDev &A, hipStream_t st) {
+hipError_t adjoint_t(const AdjDev &A, const lbw_launch &l, hipStream_t st) {
     constexpr int D = Lattice<Q>::D;
     const int block = 256;
     const dim3 grid((unsigned)((A.r.N + block - 1) / block));
@@ -411,7 +411,14 @@ hipError_t adjoint_t(const AdjDev &A, hipStream_t st) {
     fr.c1 = A.a1;
     fr.c2 = A.a2;
     fr.u = A.frozen ? A.r.u : A.u;
-    hipError_t e = launch_rk_stages12(D, sizeof(T) == 4 ? LBW_FP32_SHIFTED : LBW_FP64, fr, st);
+    // the same tiled stage kernels as the forward step, so a1 and a2 are the
+    // forward's own values
+    const int prec = sizeof(T) == 4 ? LBW_FP32_SHIFTED : LBW_FP64;
+    const int nv = D == 3 ? A.r.nz : A.r.ny;
+    lbw_launch lt = l;
+    lt.variant = 0;
+    hipError_t e = launch_stage_slab(D, prec, fr, lt, 1, 0, nv, st);
+    if (e == hipSuccess) e = launch_stage_slab(D, prec, fr, lt, 2, 0, nv, st);
     if (e != hipSuccess) return e;
     k_adj_face<T, D><<<grid, block, 0, st>>>(A, (const T *)A.a2, (const T *)A.cbar_next, (T)(2.0 / 3.0));
     k_adj_gather<T, D, 3><<<grid, block, 0, st>>>(A);
@@ -443,7 +450,7 @@ size_t adjoint_work_bytes(int dim, int precision, int64_t N) {
 hipError_t launch_adjoint(int q, int precision, const RunDev &r, bool frozen, const void *f_n,
                           const void *c_n, const void *fbar_next, const void *cbar_next,
                           double dep_bar, void *fbar, void *cbar, double *vs_bar, void *work,
-                          hipStream_t st) {
+                          const lbw_launch &l, hipStream_t st) {
     const int dim = q == 9 ? 2 : 3;
     const size_t es = precision == LBW_FP32_SHIFTED ? 4 : 8;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -470,9 +477,9 @@ hipError_t launch_adjoint(int q, int precision, const RunDev &r, bool frozen, co
     A.dep_bar = dep_bar;
     A.frozen = frozen ? 1 : 0;
     switch (precision) {
-        case LBW_FP64: return q == 9 ? adjoint_t<9, double, false>(A, st) : adjoint_t<19, double, false>(A, st);
-        case LBW_FP64_SHIFTED: return q == 9 ? adjoint_t<9, double, true>(A, st) : adjoint_t<19, double, true>(A, st);
-        case LBW_FP32_SHIFTED: return q == 9 ? adjoint_t<9, float, true>(A, st) : adjoint_t<19, float, true>(A, st);
+        case LBW_FP64: return q == 9 ? adjoint_t<9, double, false>(A, l, st) : adjoint_t<19, double, false>(A, l, st);
+        case LBW_FP64_SHIFTED: return q == 9 ? adjoint_t<9, double, true>(A, l, st) : adjoint_t<19, double, true>(A, l, st);
+        case LBW_FP32_SHIFTED: return q == 9 ? adjoint_t<9, float, true>(A, l, st) : adjoint_t<19, float, true>(A, l, st);
     }
     return hipErrorInvalidValue;
 }

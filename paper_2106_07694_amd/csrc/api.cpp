@@ -601,7 +601,8 @@ int lbw_adjoint_step(lbw_handle *h, int32_t run, const void *f_n, const void *c_
     const size_t need = lbw::adjoint_work_bytes(h->dim, h->precision, h->run[run].N);
     if (work_bytes < need) return fail(LBW_ERR_INVAL, "work needs %zu bytes", need);
     hipError_t e = lbw::launch_adjoint(h->q, h->precision, h->run[run], frozen, f_n, c_n, fbar_next,
-                                       cbar_next, dep_bar, fbar, cbar, vs_bar_dev, work, h->stream);
+                                       cbar_next, dep_bar, fbar, cbar, vs_bar_dev, work, h->launch,
+                                       h->stream);
     return e == hipSuccess ? LBW_OK : hip_fail(e, "adjoint launch");
 }
 

@@ -107,7 +107,7 @@ size_t adjoint_work_bytes(int dim, int precision, int64_t N);
 hipError_t launch_adjoint(int q, int precision, const RunDev &r, bool frozen, const void *f_n,
                           const void *c_n, const void *fbar_next, const void *cbar_next,
                           double dep_bar, void *fbar, void *cbar, double *vs_bar, void *work,
-                          hipStream_t st);
+                          const lbw_launch &l, hipStream_t st);
 hipError_t launch_reduce(int q, int precision, const RunDev *runs, int nbatch, int what,
                          bool odd, double *scratch, hipStream_t st);
 
