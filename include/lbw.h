@@ -79,7 +79,7 @@ enum { LBW_FP64 = 0, LBW_FP32_SHIFTED = 1, LBW_FP64_SHIFTED = 2 };
 enum { LBW_FLUID_LBM = 0, LBW_FLUID_FROZEN = 1 };
 enum { LBW_WENO5 = 0, LBW_WENO3 = 1, LBW_UPWIND1 = 2 };
 enum { LBW_FIELD_F = 0, LBW_FIELD_C = 1, LBW_FIELD_S = 2, LBW_FIELD_U = 3,
-       LBW_FIELD_DEPOSIT = 4 };
+       LBW_FIELD_DEPOSIT = 4, LBW_FIELD_STAGE1 = 5, LBW_FIELD_STAGE2 = 6 };
 enum { LBW_MASS_C = 0, LBW_MASS_S = 1, LBW_MASS_FLUID = 2, LBW_DEPOSIT = 3 };
 enum { LBW_PHASE_COLLIDE_STREAM = 0, LBW_PHASE_TRANSPORT = 1, LBW_NPHASES = 2 };
 
@@ -188,7 +188,8 @@ int lbw_steps_done(const lbw_handle *h, int64_t *out);
 
 /* Copy field `field` of run `run` in canonical layout into the device buffer
  * dst (populations: pre-collision f_i(x, t) -- or g_i for the shifted forms --
- * in f[q][k] order; u: the last step's node velocity; deposit: FP64 ncol).
+ * in f[q][k] order; u: the last step's node velocity; STAGE1, STAGE2: the
+ * last step's first and second RK stages of C; deposit: FP64 ncol).
  * Asynchronous on the handle's stream. */
 int lbw_export(lbw_handle *h, int32_t run, int32_t field, void *dst);
 
@@ -215,17 +216,25 @@ int lbw_adjoint_work_bytes(const lbw_handle *h, int32_t run, size_t *out_bytes);
  * streaming.  For J a function of the state at n+1:
  *   f_n, c_n     forward state at n (canonical populations, as lbw_export
  *                writes them; C), device arrays of the run's element type;
+ *   u_n, a1_n, a2_n  optional forward intermediates of step n (its node
+ *                velocity and first two RK stages, as lbw_export gives
+ *                LBW_FIELD_U, LBW_FIELD_STAGE1, LBW_FIELD_STAGE2 right after
+ *                that step); NULL: recomputed from f_n and c_n;
  *   fbar_next    dJ/df^{n+1} (canonical layout); cbar_next = dJ/dC^{n+1};
  *   dep_bar      dJ/d(deposit) of every column (1 for the total deposited
  *                mass m_b of section 4.2.3);
  *   fbar, cbar   out: dJ/df^n and dJ/dC^n (must not alias the inputs);
- *   vs_bar_dev   device FP64 scalar: += dJ/dVs through this step;
- *   work         device workspace of lbw_adjoint_work_bytes bytes.
+ *   work         device workspace of lbw_adjoint_work_bytes bytes, zero-filled
+ *                by the caller before the first step of a sweep; it carries an
+ *                FP64 per-node accumulator of dJ/dVs across steps;
+ *   vs_bar_dev   NULL, or a device FP64 scalar: the accumulator is then
+ *                summed in a fixed order, added to *vs_bar_dev and cleared.
  * WENO5 without S only (LBW_ERR_UNSUPPORTED otherwise).  In frozen mode the
  * run's u buffer is the (constant) velocity and the population arguments may
  * be NULL.  Asynchronous on the handle's stream; independent of the handle's
  * own state buffers apart from that velocity. */
 int lbw_adjoint_step(lbw_handle *h, int32_t run, const void *f_n, const void *c_n,
+                     const void *u_n, const void *a1_n, const void *a2_n,
                      const void *fbar_next, const void *cbar_next, double dep_bar, void *fbar,
                      void *cbar, double *vs_bar_dev, void *work, size_t work_bytes);
 

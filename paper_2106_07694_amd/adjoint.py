@@ -40,6 +40,15 @@ def _state_buffers(sol, count):
                  torch.empty(cfg.shape, dtype=sol.dtype, device=sol.device)) for _ in range(count)]
 
 
+def _step_buffers(sol, count):
+    """Per-step forward intermediates (velocity, RK stages 1 and 2)."""
+    cfg = sol.cfgs[0]
+    with torch.cuda.stream(sol.stream):
+        return [(torch.empty((cfg.dim,) + cfg.shape, dtype=sol.dtype, device=sol.device),
+                 torch.empty(cfg.shape, dtype=sol.dtype, device=sol.device),
+                 torch.empty(cfg.shape, dtype=sol.dtype, device=sol.device)) for _ in range(count)]
+
+
 def forward_with_checkpoints(cfg, c0: torch.Tensor, vs: float, nsteps: int, seg: int, launch=None,
                              f0=None, u=None):
     """Run nsteps from C = c0 and the fluid at rest (or the canonical
@@ -79,25 +88,36 @@ def backward_from_checkpoints(sol: lbw.Solver, ckpt: dict, nsteps: int, seg: int
         vs_bar = torch.zeros(1, dtype=torch.float64, device=dev)
     work = sol.adjoint_workspace()
     states = _state_buffers(sol, seg)
+    inter = _step_buffers(sol, seg)
     frozen = cfg.fluid_mode == lbw.FLUID_FROZEN
+    last = min(ckpt)
     for s0 in reversed(sorted(ckpt)):
         n = min(seg, nsteps - s0)
         f_s, c_s = ckpt[s0]
         if not frozen:
             sol.import_from("f", f_s)
         sol.import_from("c", c_s)
+        # replay the segment: the state before each step, and the step's own
+        # velocity and RK stages right after it
         for i in range(n):
             if not frozen:
                 sol.export_into("f", states[i][0])
             sol.export_into("c", states[i][1])
-            if i + 1 < n:
-                sol.step(1)
+            sol.step(1)
+            if not frozen:
+                sol.export_into("u", inter[i][0])
+            sol.export_into("stage1", inter[i][1])
+            sol.export_into("stage2", inter[i][2])
         for i in reversed(range(n)):
             f_n, c_n = states[i]
+            u_n, a1, a2 = inter[i]
+            vs_out = vs_bar if (s0 == last and i == 0) else None
             if frozen:
-                sol.adjoint_step(None, c_n, None, cbar_next, dep_bar, None, cbar, vs_bar, work)
+                sol.adjoint_step(None, c_n, None, cbar_next, dep_bar, None, cbar, vs_out, work,
+                                 a1_n=a1, a2_n=a2)
             else:
-                sol.adjoint_step(f_n, c_n, fbar_next, cbar_next, dep_bar, fbar, cbar, vs_bar, work)
+                sol.adjoint_step(f_n, c_n, fbar_next, cbar_next, dep_bar, fbar, cbar, vs_out, work,
+                                 u_n=u_n, a1_n=a1, a2_n=a2)
             fbar_next, fbar = fbar, fbar_next
             cbar_next, cbar = cbar, cbar_next
     sol.stream.synchronize()

@@ -21,7 +21,8 @@
 //  3. streaming in reverse (each population pulls the adjoint from where the
 //     forward step sent it), then BGK + Guo collision and the moments in
 //     reverse, adding the transport's velocity sensitivity; the force's C
-//     dependence closes the loop into cbar.
+//     dependence closes the loop into cbar.  This runs in the gather kernel
+//     of the last reversed stage, once the node's velocity adjoint is whole.
 // Every node's adjoint is written by exactly one thread; dJ/dVs is gathered
 // per node and summed in a fixed order (FP64).
 #include "lbm_device.h"
@@ -38,6 +39,7 @@ struct AdjDev {
     double *vs_part, *partials, *vs_bar;
     double dep_bar;
     int frozen;
+    int have_u, have_stages;   // forward intermediates supplied by the caller
 };
 
 template <int D>
@@ -59,20 +61,15 @@ __global__ void __launch_bounds__(256) k_adj_moments(AdjDev a) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= r.N) return;
     const T *f = (const T *)a.f_n;
-    T rho = SH ? (T)1 : (T)0, m[3] = {0, 0, 0};
+    T fi[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const T v = f[(int64_t)i * r.N + k];
-        rho += v;
-        m[0] += (T)L::cx[i] * v;
-        m[1] += (T)L::cy[i] * v;
-        m[2] += (T)L::cz[i] * v;
-    }
-    T F[3] = {(T)r.body[0], (T)r.body[1], (T)r.body[2]};
-    F[D - 1] += -(T)r.gp_c * ((const T *)a.c_n)[k];
-    T *u = (T *)a.u;
+    for (int i = 0; i < Q; ++i) fi[i] = f[(int64_t)i * r.N + k];
+    T F[3], u[3], rho, drho;
+    lbm_force<D, T>(r, (const T *)a.c_n, nullptr, k, F);
+    lbm_rho_u<Q, T, SH>(fi, F, rho, drho, u);
+    T *uo = (T *)a.u;
 #pragma unroll
-    for (int d = 0; d < D; ++d) u[(int64_t)d * r.N + k] = (m[d] + (T)0.5 * F[d]) / rho;
+    for (int d = 0; d < D; ++d) uo[(int64_t)d * r.N + k] = u[d];
 }
 
 // ---------------------------------------------------------------------------
@@ -125,6 +122,39 @@ __device__ __forceinline__ void weno5_vjp(const T h[5], const T a[5], T eps, T g
     ab[4] += tb + sb;
 }
 
+// Products of one face's local Jacobian with its adjoint pb, for the six
+// stencil nodes j-2..j+3 (values av, transport velocities wv):
+//   A[s] = pb * dPhi/da_s (WENO5 through h = w a and the indicators, plus the
+//          central diffusion), W[s] = pb * dPhi/dw_s.
+template <typename T>
+__device__ __forceinline__ void face_vjp(const T av[6], const T wv[6], T pb, T kap, T eps, T A[6],
+                                         T W[6]) {
+    T hb[6] = {0, 0, 0, 0, 0, 0}, ab[6] = {0, 0, 0, 0, 0, 0};
+    const bool pos = (wv[2] + wv[3]) >= (T)0;
+    if (pos) {
+        T h5[5] = {wv[0] * av[0], wv[1] * av[1], wv[2] * av[2], wv[3] * av[3], wv[4] * av[4]};
+        T a5[5] = {av[0], av[1], av[2], av[3], av[4]};
+        T hb5[5] = {0, 0, 0, 0, 0}, ab5[5] = {0, 0, 0, 0, 0};
+        weno5_vjp<T>(h5, a5, eps, pb, hb5, ab5);
+#pragma unroll
+        for (int s = 0; s < 5; ++s) { hb[s] += hb5[s]; ab[s] += ab5[s]; }
+    } else {
+        T h5[5] = {wv[5] * av[5], wv[4] * av[4], wv[3] * av[3], wv[2] * av[2], wv[1] * av[1]};
+        T a5[5] = {av[5], av[4], av[3], av[2], av[1]};
+        T hb5[5] = {0, 0, 0, 0, 0}, ab5[5] = {0, 0, 0, 0, 0};
+        weno5_vjp<T>(h5, a5, eps, pb, hb5, ab5);
+#pragma unroll
+        for (int s = 0; s < 5; ++s) { hb[5 - s] += hb5[s]; ab[5 - s] += ab5[s]; }
+    }
+    ab[3] += -kap * pb;   // diffusion -kappa (a_{j+1} - a_j)
+    ab[2] += kap * pb;
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        A[s] = ab[s] + hb[s] * wv[s];   // through a directly and through h = w a
+        W[s] = hb[s] * av[s];
+    }
+}
+
 // For every interior face j+1/2 (stored at its lower node j) and axis d:
 //   faceA[d][s] = phibar * dPhi/da_{j-2+s},  faceW[d][s] = phibar * dPhi/dw_{j-2+s}
 // with phibar = scale * (lam_{j+1} - lam_j).  Wall faces store zeros.
@@ -169,37 +199,88 @@ __global__ void __launch_bounds__(256) k_adj_face(AdjDev A, const T *__restrict_
         int jn = j + 1;
         if (jn >= n) jn -= n;   // periodic neighbour (walls never reach here at the top)
         const T pb = scale * (lam[k + (int64_t)(jn - j) * stride] - lam[k]);
-        T hb[6] = {0, 0, 0, 0, 0, 0}, ab[6] = {0, 0, 0, 0, 0, 0};
-        const bool pos = (wv[2] + wv[3]) >= (T)0;
-        if (pos) {
-            T h5[5] = {wv[0] * av[0], wv[1] * av[1], wv[2] * av[2], wv[3] * av[3], wv[4] * av[4]};
-            T a5[5] = {av[0], av[1], av[2], av[3], av[4]};
-            T hb5[5] = {0, 0, 0, 0, 0}, ab5[5] = {0, 0, 0, 0, 0};
-            weno5_vjp<T>(h5, a5, eps, pb, hb5, ab5);
-#pragma unroll
-            for (int s = 0; s < 5; ++s) { hb[s] += hb5[s]; ab[s] += ab5[s]; }
-        } else {
-            T h5[5] = {wv[5] * av[5], wv[4] * av[4], wv[3] * av[3], wv[2] * av[2], wv[1] * av[1]};
-            T a5[5] = {av[5], av[4], av[3], av[2], av[1]};
-            T hb5[5] = {0, 0, 0, 0, 0}, ab5[5] = {0, 0, 0, 0, 0};
-            weno5_vjp<T>(h5, a5, eps, pb, hb5, ab5);
-#pragma unroll
-            for (int s = 0; s < 5; ++s) { hb[5 - s] += hb5[s]; ab[5 - s] += ab5[s]; }
-        }
-        ab[3] += -kap * pb;   // diffusion -kappa (a_{j+1} - a_j)
-        ab[2] += kap * pb;
+        T fa6[6], fw6[6];
+        face_vjp<T>(av, wv, pb, kap, eps, fa6, fw6);
 #pragma unroll
         for (int s = 0; s < 6; ++s) {
-            fa[base + s * r.N] = ab[s] + hb[s] * wv[s];   // through a directly and through h = w a
-            fw[base + s * r.N] = hb[s] * av[s];
+            fa[base + s * r.N] = fa6[s];
+            fw[base + s * r.N] = fw6[s];
         }
     }
 }
 
+// ---------------------------------------------------------------------------
+// 3. streaming, collision and moments in reverse
+// ---------------------------------------------------------------------------
+// Reverse of streaming, collision and moments at node k given the node's
+// total velocity adjoint ub (transport part included); writes fbar and
+// returns the node's contribution to cbar through the force.
+template <int Q, typename T, bool SH>
+__device__ __forceinline__ T collide_reverse_node(const AdjDev &A, int64_t k, int x, int y, int z,
+                                                  const T ubt[3]) {
+    using L = Lattice<Q>;
+    constexpr int D = L::D;
+    const RunDev &r = A.r;
+    const T *f = (const T *)A.f_n;
+    const T *fbn = (const T *)A.fbar_next;
+    T fi[Q], fsb[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        fi[i] = f[(int64_t)i * r.N + k];
+        // forward streaming sent f*_i(x) to slot i of x + c_i, or to slot
+        // opp(i) of x across a wall: pull the adjoint from there
+        const int64_t dst = displaced<D>(r, x, y, z, L::cx[i], L::cy[i], L::cz[i]);
+        fsb[i] = dst >= 0 ? fbn[(int64_t)i * r.N + dst] : fbn[(int64_t)L::opp[i] * r.N + k];
+    }
+    T F[3], u[3], rho, drho;
+    lbm_force<D, T>(r, (const T *)A.c_n, nullptr, k, F);
+    lbm_rho_u<Q, T, SH>(fi, F, rho, drho, u);
+    const T usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const T omega = (T)r.omega, guo = (T)r.guo;
+    T ub[3] = {ubt[0], ubt[1], ubt[2]}, Fb[3] = {0, 0, 0}, rb = 0;
+    T *fb = (T *)A.fbar;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const T w = (T)L::w[i];
+        const T c[3] = {(T)L::cx[i], (T)L::cy[i], (T)L::cz[i]};
+        const T cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
+        const T cF = c[0] * F[0] + c[1] * F[1] + c[2] * F[2];
+        const T poly = (T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * usq;
+        // f* = f - omega (f - feq(rho, u)) + G(u, F)
+        const T eb = omega * fsb[i];      // adjoint of feq_i
+        const T gb = fsb[i];              // adjoint of G_i
+        rb += eb * w * ((T)1 + poly);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            ub[d] += eb * w * rho * ((T)3 * c[d] + (T)9 * cu * c[d] - (T)3 * u[d]) +
+                     gb * guo * w * ((T)-3 * F[d] + (T)9 * c[d] * cF);
+            Fb[d] += gb * guo * w * ((T)3 * (c[d] - u[d]) + (T)9 * cu * c[d]);
+        }
+        fi[i] = ((T)1 - omega) * fsb[i];
+    }
+    // u = (m + F/2) / rho, m = sum f c, rho = sum f (+1 when shifted)
+    T mb[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        mb[d] = ub[d] / rho;
+        Fb[d] += (T)0.5 * ub[d] / rho;
+        rb -= ub[d] * u[d] / rho;
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        fb[(int64_t)i * r.N + k] = fi[i] + (rb + mb[0] * (T)L::cx[i] + mb[1] * (T)L::cy[i] + mb[2] * (T)L::cz[i]);
+    return -(T)r.gp_c * Fb[D - 1];
+}
+
+// ---------------------------------------------------------------------------
+// gather of the transport transpose (the last reversed stage also reverses
+// the collision at the node)
+// ---------------------------------------------------------------------------
 // Node-wise gather of the face products.  STAGE selects the RK stage being
 // reversed (3, 2, 1 in that order) and how the result combines.
-template <typename T, int D, int STAGE>
+template <int Q, typename T, bool SH, int STAGE>
 __global__ void __launch_bounds__(256) k_adj_gather(AdjDev A) {
+    constexpr int D = Lattice<Q>::D;
     const RunDev &r = A.r;
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= r.N) return;
@@ -275,7 +356,7 @@ __global__ void __launch_bounds__(256) k_adj_gather(AdjDev A) {
         cb[k] = cbv;
 #pragma unroll
         for (int d = 0; d < D; ++d) ub[(int64_t)d * r.N + k] = ubs[d];
-        A.vs_part[k] = vsp;
+        A.vs_part[k] += vsp;      // accumulates across steps until summed
     } else if constexpr (STAGE == 2) {
         const T a2b = ((const T *)A.abar2)[k];
         T a1b = (T)0.25 * a2b + abar;
@@ -286,84 +367,19 @@ __global__ void __launch_bounds__(256) k_adj_gather(AdjDev A) {
         for (int d = 0; d < D; ++d) ub[(int64_t)d * r.N + k] += ubs[d];
         A.vs_part[k] += vsp;
     } else {
-        cb[k] += ((const T *)A.abar1)[k] + abar;
-#pragma unroll
-        for (int d = 0; d < D; ++d) ub[(int64_t)d * r.N + k] += ubs[d];
+        T cbv = cb[k] + ((const T *)A.abar1)[k] + abar;
         A.vs_part[k] += vsp;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// 3. streaming, collision and moments in reverse
-// ---------------------------------------------------------------------------
-template <int Q, typename T, bool SH>
-__global__ void __launch_bounds__(256) k_adj_collide(AdjDev A) {
-    using L = Lattice<Q>;
-    constexpr int D = L::D;
-    const RunDev &r = A.r;
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= r.N) return;
-    int x, y, z;
-    xyz<D>(r, k, x, y, z);
-    const T *f = (const T *)A.f_n;
-    const T *fbn = (const T *)A.fbar_next;
-    T fi[Q], fsb[Q];
-    T rho = SH ? (T)1 : (T)0, m[3] = {0, 0, 0};
+        if (A.frozen) {
+            cb[k] = cbv;
+        } else {
+            // last stage reversed: the node's velocity adjoint is complete, so
+            // the collision and moments are reversed here as well
+            T ut[3] = {0, 0, 0};
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        fi[i] = f[(int64_t)i * r.N + k];
-        rho += fi[i];
-        m[0] += (T)L::cx[i] * fi[i];
-        m[1] += (T)L::cy[i] * fi[i];
-        m[2] += (T)L::cz[i] * fi[i];
-        // forward streaming sent f*_i(x) to slot i of x + c_i, or to slot
-        // opp(i) of x across a wall: pull the adjoint from there
-        const int64_t dst = displaced<D>(r, x, y, z, L::cx[i], L::cy[i], L::cz[i]);
-        fsb[i] = dst >= 0 ? fbn[(int64_t)i * r.N + dst] : fbn[(int64_t)L::opp[i] * r.N + k];
-    }
-    T F[3] = {(T)r.body[0], (T)r.body[1], (T)r.body[2]};
-    F[D - 1] += -(T)r.gp_c * ((const T *)A.c_n)[k];
-    T u[3] = {0, 0, 0};
-#pragma unroll
-    for (int d = 0; d < D; ++d) u[d] = (m[d] + (T)0.5 * F[d]) / rho;
-    const T usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    const T omega = (T)r.omega, guo = (T)r.guo;
-    const T *ubt = (const T *)A.ubar;
-    T ub[3] = {0, 0, 0}, Fb[3] = {0, 0, 0}, rb = 0;
-#pragma unroll
-    for (int d = 0; d < D; ++d) ub[d] = ubt[(int64_t)d * r.N + k];
-    T *fb = (T *)A.fbar;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const T w = (T)L::w[i];
-        const T c[3] = {(T)L::cx[i], (T)L::cy[i], (T)L::cz[i]};
-        const T cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
-        const T cF = c[0] * F[0] + c[1] * F[1] + c[2] * F[2];
-        const T poly = (T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * usq;
-        // f* = f - omega (f - feq(rho, u)) + G(u, F)
-        const T eb = omega * fsb[i];      // adjoint of feq_i
-        const T gb = fsb[i];              // adjoint of G_i
-        rb += eb * w * ((T)1 + poly);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            ub[d] += eb * w * rho * ((T)3 * c[d] + (T)9 * cu * c[d] - (T)3 * u[d]) +
-                     gb * guo * w * ((T)-3 * F[d] + (T)9 * c[d] * cF);
-            Fb[d] += gb * guo * w * ((T)3 * (c[d] - u[d]) + (T)9 * cu * c[d]);
+            for (int d = 0; d < D; ++d) ut[d] = ub[(int64_t)d * r.N + k] + ubs[d];
+            cb[k] = cbv + collide_reverse_node<Q, T, SH>(A, k, x, y, z, ut);
         }
-        fb[(int64_t)i * r.N + k] = ((T)1 - omega) * fsb[i];
     }
-    // u = (m + F/2) / rho, m = sum f c, rho = sum f (+1 when shifted)
-    T mb[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        mb[d] = ub[d] / rho;
-        Fb[d] += (T)0.5 * ub[d] / rho;
-        rb -= ub[d] * u[d] / rho;
-    }
-#pragma unroll
-    for (int i = 0; i < Q; ++i)
-        fb[(int64_t)i * r.N + k] += rb + mb[0] * (T)L::cx[i] + mb[1] * (T)L::cy[i] + mb[2] * (T)L::cz[i];
-    ((T *)A.cbar)[k] += -(T)r.gp_c * Fb[D - 1];
 }
 
 // ---------------------------------------------------------------------------
@@ -382,11 +398,13 @@ __device__ __forceinline__ double block_sum_adj(double acc) {
     return t;
 }
 
-__global__ void __launch_bounds__(256) k_adj_vs_partial(const double *__restrict__ part, int64_t n,
+__global__ void __launch_bounds__(256) k_adj_vs_partial(double *__restrict__ part, int64_t n,
                                                         double *__restrict__ out) {
     double acc = 0.0;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
         acc += part[k];
+        part[k] = 0.0;            // the accumulator starts over
+    }
     const double t = block_sum_adj(acc);
     if (threadIdx.x == 0) out[blockIdx.x] = t;
 }
@@ -404,31 +422,34 @@ hipError_t adjoint_t(const AdjDev &A, const lbw_launch &l, hipStream_t st) {
     constexpr int D = Lattice<Q>::D;
     const int block = 256;
     const dim3 grid((unsigned)((A.r.N + block - 1) / block));
-    if (!A.frozen) k_adj_moments<Q, T, SH><<<grid, block, 0, st>>>(A);
-    // forward stages 1 and 2 from the saved C^n and the recomputed u^n
-    RunDev fr = A.r;
-    fr.c = const_cast<void *>(A.c_n);
-    fr.c1 = A.a1;
-    fr.c2 = A.a2;
-    fr.u = A.frozen ? A.r.u : A.u;
-    // the same tiled stage kernels as the forward step, so a1 and a2 are the
-    // forward's own values
-    const int prec = sizeof(T) == 4 ? LBW_FP32_SHIFTED : LBW_FP64;
-    const int nv = D == 3 ? A.r.nz : A.r.ny;
-    lbw_launch lt = l;
-    lt.variant = 0;
-    hipError_t e = launch_stage_slab(D, prec, fr, lt, 1, 0, nv, st);
-    if (e == hipSuccess) e = launch_stage_slab(D, prec, fr, lt, 2, 0, nv, st);
-    if (e != hipSuccess) return e;
+    if (!A.frozen && !A.have_u) k_adj_moments<Q, T, SH><<<grid, block, 0, st>>>(A);
+    hipError_t e = hipSuccess;
+    if (!A.have_stages) {
+        // forward stages 1 and 2 from the saved C^n and u^n, with the same
+        // tiled kernels as the forward step (a1, a2 are its own values)
+        RunDev fr = A.r;
+        fr.c = const_cast<void *>(A.c_n);
+        fr.c1 = A.a1;
+        fr.c2 = A.a2;
+        fr.u = A.frozen ? A.r.u : A.u;
+        const int prec = sizeof(T) == 4 ? LBW_FP32_SHIFTED : LBW_FP64;
+        const int nv = D == 3 ? A.r.nz : A.r.ny;
+        lbw_launch lt = l;
+        lt.variant = 0;
+        e = launch_stage_slab(D, prec, fr, lt, 1, 0, nv, st);
+        if (e == hipSuccess) e = launch_stage_slab(D, prec, fr, lt, 2, 0, nv, st);
+        if (e != hipSuccess) return e;
+    }
     k_adj_face<T, D><<<grid, block, 0, st>>>(A, (const T *)A.a2, (const T *)A.cbar_next, (T)(2.0 / 3.0));
-    k_adj_gather<T, D, 3><<<grid, block, 0, st>>>(A);
+    k_adj_gather<Q, T, SH, 3><<<grid, block, 0, st>>>(A);
     k_adj_face<T, D><<<grid, block, 0, st>>>(A, (const T *)A.a1, (const T *)A.abar2, (T)0.25);
-    k_adj_gather<T, D, 2><<<grid, block, 0, st>>>(A);
+    k_adj_gather<Q, T, SH, 2><<<grid, block, 0, st>>>(A);
     k_adj_face<T, D><<<grid, block, 0, st>>>(A, (const T *)A.c_n, (const T *)A.abar1, (T)1);
-    k_adj_gather<T, D, 1><<<grid, block, 0, st>>>(A);
-    if (!A.frozen) k_adj_collide<Q, T, SH><<<grid, block, 0, st>>>(A);
-    k_adj_vs_partial<<<kReduceBlocks, 256, 0, st>>>(A.vs_part, A.r.N, A.partials);
-    k_adj_vs_final<<<1, 256, 0, st>>>(A.partials, kReduceBlocks, A.vs_bar);
+    k_adj_gather<Q, T, SH, 1><<<grid, block, 0, st>>>(A);
+    if (A.vs_bar) {
+        k_adj_vs_partial<<<kReduceBlocks, 256, 0, st>>>(A.vs_part, A.r.N, A.partials);
+        k_adj_vs_final<<<1, 256, 0, st>>>(A.partials, kReduceBlocks, A.vs_bar);
+    }
     return hipGetLastError();
 }
 
@@ -448,7 +469,8 @@ size_t adjoint_work_bytes(int dim, int precision, int64_t N) {
 }
 
 hipError_t launch_adjoint(int q, int precision, const RunDev &r, bool frozen, const void *f_n,
-                          const void *c_n, const void *fbar_next, const void *cbar_next,
+                          const void *c_n, const void *u_n, const void *a1_n, const void *a2_n,
+                          const void *fbar_next, const void *cbar_next,
                           double dep_bar, void *fbar, void *cbar, double *vs_bar, void *work,
                           const lbw_launch &l, hipStream_t st) {
     const int dim = q == 9 ? 2 : 3;
@@ -476,6 +498,13 @@ hipError_t launch_adjoint(int q, int precision, const RunDev &r, bool frozen, co
     A.vs_bar = vs_bar;
     A.dep_bar = dep_bar;
     A.frozen = frozen ? 1 : 0;
+    A.have_u = (u_n != nullptr && !frozen) ? 1 : 0;
+    A.have_stages = (a1_n != nullptr && a2_n != nullptr) ? 1 : 0;
+    if (A.have_u) A.u = const_cast<void *>(u_n);
+    if (A.have_stages) {
+        A.a1 = const_cast<void *>(a1_n);
+        A.a2 = const_cast<void *>(a2_n);
+    }
     switch (precision) {
         case LBW_FP64: return q == 9 ? adjoint_t<9, double, false>(A, l, st) : adjoint_t<19, double, false>(A, l, st);
         case LBW_FP64_SHIFTED: return q == 9 ? adjoint_t<9, double, true>(A, l, st) : adjoint_t<19, double, true>(A, l, st);

@@ -584,6 +584,7 @@ int lbw_adjoint_work_bytes(const lbw_handle *h, int32_t run, size_t *out_bytes) 
 }
 
 int lbw_adjoint_step(lbw_handle *h, int32_t run, const void *f_n, const void *c_n,
+                     const void *u_n, const void *a1_n, const void *a2_n,
                      const void *fbar_next, const void *cbar_next, double dep_bar, void *fbar,
                      void *cbar, double *vs_bar_dev, void *work, size_t work_bytes) {
     int rc = check_run(h, run);
@@ -591,8 +592,9 @@ int lbw_adjoint_step(lbw_handle *h, int32_t run, const void *f_n, const void *c_
     if (h->scheme != LBW_WENO5 || h->has_s)
         return fail(LBW_ERR_UNSUPPORTED, "the adjoint covers WENO5 transport without S");
     const bool frozen = h->fluid_mode == LBW_FLUID_FROZEN;
-    if (!c_n || !cbar_next || !cbar || !vs_bar_dev || !work)
-        return fail(LBW_ERR_INVAL, "NULL required argument");
+    if (!c_n || !cbar_next || !cbar || !work) return fail(LBW_ERR_INVAL, "NULL required argument");
+    if ((a1_n == nullptr) != (a2_n == nullptr))
+        return fail(LBW_ERR_INVAL, "give both RK stages or neither");
     if (!frozen && (!f_n || !fbar_next || !fbar))
         return fail(LBW_ERR_INVAL, "populations and their adjoints are required");
     if (cbar == cbar_next || cbar == c_n || (!frozen && (fbar == fbar_next || fbar == f_n)))
@@ -600,9 +602,9 @@ int lbw_adjoint_step(lbw_handle *h, int32_t run, const void *f_n, const void *c_
     if (!std::isfinite(dep_bar)) return fail(LBW_ERR_INVAL, "dep_bar must be finite");
     const size_t need = lbw::adjoint_work_bytes(h->dim, h->precision, h->run[run].N);
     if (work_bytes < need) return fail(LBW_ERR_INVAL, "work needs %zu bytes", need);
-    hipError_t e = lbw::launch_adjoint(h->q, h->precision, h->run[run], frozen, f_n, c_n, fbar_next,
-                                       cbar_next, dep_bar, fbar, cbar, vs_bar_dev, work, h->launch,
-                                       h->stream);
+    hipError_t e = lbw::launch_adjoint(h->q, h->precision, h->run[run], frozen, f_n, c_n, u_n, a1_n,
+                                       a2_n, fbar_next, cbar_next, dep_bar, fbar, cbar, vs_bar_dev,
+                                       work, h->launch, h->stream);
     return e == hipSuccess ? LBW_OK : hip_fail(e, "adjoint launch");
 }
 
@@ -665,6 +667,8 @@ int lbw_export(lbw_handle *h, int32_t run, int32_t field, void *dst) {
         case LBW_FIELD_DEPOSIT:
             e = hipMemcpyAsync(dst, r.dep, r.ncol * sizeof(double), hipMemcpyDeviceToDevice, h->stream);
             break;
+        case LBW_FIELD_STAGE1: e = hipMemcpyAsync(dst, r.c1, r.N * es, hipMemcpyDeviceToDevice, h->stream); break;
+        case LBW_FIELD_STAGE2: e = hipMemcpyAsync(dst, r.c2, r.N * es, hipMemcpyDeviceToDevice, h->stream); break;
         default: return fail(LBW_ERR_INVAL, "unknown field %d", field);
     }
     return e == hipSuccess ? LBW_OK : hip_fail(e, "export");

@@ -33,31 +33,12 @@ __device__ __forceinline__ void collide_stream_node(const RunDev &r, int64_t k) 
 #pragma unroll
     for (int i = 0; i < Q; ++i) fi[i] = load_canonical<Q, T>(r, f, i, k, x, y, z, ODD);
 
-    // moments (eq. 19-20); shifted storage holds f_i - w_i
-    T rho = 0, mx = 0, my = 0, mz = 0;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        rho += fi[i];
-        if (L::cx[i]) mx += L::cx[i] > 0 ? fi[i] : -fi[i];
-        if (L::cy[i]) my += L::cy[i] > 0 ? fi[i] : -fi[i];
-        if (D == 3 && L::cz[i]) mz += L::cz[i] > 0 ? fi[i] : -fi[i];
-    }
-    const T drho = SH ? rho : rho - (T)1;
-    if (SH) rho = (T)1 + rho;
-
-    // buoyancy (eq. 10 linearised): vertical force -gp_c C - gp_s S
-    const T *__restrict__ cc = (const T *)r.c;
-    T fv = -(T)r.gp_c * cc[k];
-    if (r.has_s) fv -= (T)r.gp_s * ((const T *)r.s)[k];
-    const T Fx = (T)r.body[0];
-    const T Fy = (T)r.body[1] + (D == 2 ? fv : (T)0);
-    const T Fz = (T)r.body[2] + (D == 3 ? fv : (T)0);
-
-    // force-shifted velocity rho u = sum f c + F/2 (eq. 22)
-    const T inv = (T)1 / rho;
-    const T ux = (mx + (T)0.5 * Fx) * inv;
-    const T uy = (my + (T)0.5 * Fy) * inv;
-    const T uz = (D == 3) ? (mz + (T)0.5 * Fz) * inv : (T)0;
+    // moments (eq. 19-20) with the Guo shift and the buoyancy force (eq. 10)
+    T F[3], uu[3], rho, drho;
+    lbm_force<D, T>(r, (const T *)r.c, (const T *)r.s, k, F);
+    lbm_rho_u<Q, T, SH>(fi, F, rho, drho, uu);
+    const T Fx = F[0], Fy = F[1], Fz = F[2];
+    const T ux = uu[0], uy = uu[1], uz = uu[2];
     T *__restrict__ uo = (T *)r.u;
     uo[k] = ux;
     uo[r.N + k] = uy;

@@ -95,6 +95,41 @@ __device__ __forceinline__ void store_canonical(const RunDev &r, T *__restrict__
     }
 }
 
+// Density and force-shifted velocity of one node's populations (eq. 19-20
+// with rho u = sum f c + F/2, eq. 22); shifted storage holds f_i - w_i.  The
+// forward step and its adjoint both use this, so they agree bit for bit.
+template <int Q, typename T, bool SH>
+__device__ __forceinline__ void lbm_rho_u(const T (&fi)[Q], const T F[3], T &rho, T &drho,
+                                          T u[3]) {
+    using L = Lattice<Q>;
+    T r = 0, mx = 0, my = 0, mz = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        r += fi[i];
+        if (L::cx[i]) mx += L::cx[i] > 0 ? fi[i] : -fi[i];
+        if (L::cy[i]) my += L::cy[i] > 0 ? fi[i] : -fi[i];
+        if (L::D == 3 && L::cz[i]) mz += L::cz[i] > 0 ? fi[i] : -fi[i];
+    }
+    drho = SH ? r : r - (T)1;
+    rho = SH ? (T)1 + r : r;
+    const T inv = (T)1 / rho;
+    u[0] = (mx + (T)0.5 * F[0]) * inv;
+    u[1] = (my + (T)0.5 * F[1]) * inv;
+    u[2] = (L::D == 3) ? (mz + (T)0.5 * F[2]) * inv : (T)0;
+}
+
+// Force density at node k: body force plus the linear buoyancy of C (and S)
+// on the vertical axis (eq. 10 linearised).
+template <int D, typename T>
+__device__ __forceinline__ void lbm_force(const RunDev &r, const T *__restrict__ c,
+                                          const T *__restrict__ s, int64_t k, T F[3]) {
+    T fv = -(T)r.gp_c * c[k];
+    if (r.has_s) fv -= (T)r.gp_s * s[k];
+    F[0] = (T)r.body[0];
+    F[1] = (T)r.body[1] + (D == 2 ? fv : (T)0);
+    F[2] = (T)r.body[2] + (D == 3 ? fv : (T)0);
+}
+
 // Canonical density at node k (shifted storage adds back rho0 = 1).
 template <int Q, typename T>
 __device__ __forceinline__ T node_density(const RunDev &r, const T *__restrict__ f, int64_t k,

@@ -105,7 +105,8 @@ hipError_t launch_collide_stream_batched(int q, int precision, const RunDev *run
 hipError_t launch_rk_stages12(int dim, int precision, const RunDev &r, hipStream_t st);
 size_t adjoint_work_bytes(int dim, int precision, int64_t N);
 hipError_t launch_adjoint(int q, int precision, const RunDev &r, bool frozen, const void *f_n,
-                          const void *c_n, const void *fbar_next, const void *cbar_next,
+                          const void *c_n, const void *u_n, const void *a1_n, const void *a2_n,
+                          const void *fbar_next, const void *cbar_next,
                           double dep_bar, void *fbar, void *cbar, double *vs_bar, void *work,
                           const lbw_launch &l, hipStream_t st);
 hipError_t launch_reduce(int q, int precision, const RunDev *runs, int nbatch, int what,

@@ -20,7 +20,7 @@ D2Q9, D3Q19 = 9, 19
 FP64, FP32_SHIFTED, FP64_SHIFTED = 0, 1, 2
 FLUID_LBM, FLUID_FROZEN = 0, 1
 WENO5, WENO3, UPWIND1 = 0, 1, 2
-FIELD_F, FIELD_C, FIELD_S, FIELD_U, FIELD_DEPOSIT = 0, 1, 2, 3, 4
+FIELD_F, FIELD_C, FIELD_S, FIELD_U, FIELD_DEPOSIT, FIELD_STAGE1, FIELD_STAGE2 = 0, 1, 2, 3, 4, 5, 6
 MASS_C, MASS_S, MASS_FLUID, DEPOSIT = 0, 1, 2, 3
 ERR_INVAL, ERR_UNSUPPORTED, ERR_HIP, ERR_NONFINITE = -1, -2, -3, -4
 
@@ -96,7 +96,8 @@ def load() -> ctypes.CDLL:
     lib.lbw_import.argtypes = [P, I32, I32, P]
     lib.lbw_reduce.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double)]
     lib.lbw_adjoint_work_bytes.argtypes = [P, I32, ctypes.POINTER(ctypes.c_size_t)]
-    lib.lbw_adjoint_step.argtypes = [P, I32, P, P, P, P, ctypes.c_double, P, P, P, P, ctypes.c_size_t]
+    lib.lbw_adjoint_step.argtypes = [P, I32, P, P, P, P, P, P, P, ctypes.c_double, P, P, P, P,
+                                     ctypes.c_size_t]
     lib.lbw_timing_begin.argtypes = [P]
     lib.lbw_timing_end.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     for name in EXPORTED:
@@ -256,7 +257,7 @@ class Solver:
         self.stream.synchronize()
 
     def set_field(self, name, value, run=0):
-        fid = {"f": FIELD_F, "c": FIELD_C, "s": FIELD_S, "u": FIELD_U, "deposit": FIELD_DEPOSIT}[name]
+        fid = self._FIELDS[name]
         import torch
         dt = torch.float64 if name == "deposit" else None
         src = self._dev(value, dt)
@@ -268,8 +269,8 @@ class Solver:
         import torch
         c = self.cfgs[run]
         shapes = {"f": (c.lattice, *c.shape), "c": c.shape, "s": c.shape, "u": (c.dim, *c.shape),
-                  "deposit": (c.ncol,)}
-        fid = {"f": FIELD_F, "c": FIELD_C, "s": FIELD_S, "u": FIELD_U, "deposit": FIELD_DEPOSIT}[name]
+                  "deposit": (c.ncol,), "stage1": c.shape, "stage2": c.shape}
+        fid = self._FIELDS[name]
         dt = torch.float64 if name == "deposit" else self.dtype
         with torch.cuda.stream(self.stream):
             out = torch.empty(shapes[name], dtype=dt, device=self.device)
@@ -277,7 +278,8 @@ class Solver:
         self.stream.synchronize()
         return out
 
-    _FIELDS = {"f": FIELD_F, "c": FIELD_C, "s": FIELD_S, "u": FIELD_U, "deposit": FIELD_DEPOSIT}
+    _FIELDS = {"f": FIELD_F, "c": FIELD_C, "s": FIELD_S, "u": FIELD_U, "deposit": FIELD_DEPOSIT,
+               "stage1": FIELD_STAGE1, "stage2": FIELD_STAGE2}
 
     def export_into(self, name, out, run=0):
         """Canonical copy of a field into an existing device tensor, ordered on
@@ -322,18 +324,21 @@ class Solver:
         return {"collide_stream_ms": ms[0], "transport_ms": ms[1], "steps": n.value}
 
     def adjoint_workspace(self, run=0):
-        """Device workspace tensor for adjoint_step (allocated by torch)."""
+        """Zero-filled device workspace tensor for adjoint_step (torch-owned)."""
         n = ctypes.c_size_t(0)
         check(self._lib.lbw_adjoint_work_bytes(self._h, run, ctypes.byref(n)))
         with self._torch.cuda.stream(self.stream):
-            return self._torch.empty((n.value + 7) // 8, dtype=self._torch.float64, device=self.device)
+            return self._torch.zeros((n.value + 7) // 8, dtype=self._torch.float64, device=self.device)
 
-    def adjoint_step(self, f_n, c_n, fbar_next, cbar_next, dep_bar, fbar, cbar, vs_bar, work, run=0):
-        """One reverse step (device tensors; see lbw_adjoint_step)."""
+    def adjoint_step(self, f_n, c_n, fbar_next, cbar_next, dep_bar, fbar, cbar, vs_bar, work, run=0,
+                     u_n=None, a1_n=None, a2_n=None):
+        """One reverse step (device tensors; see lbw_adjoint_step).  vs_bar
+        (or None) receives the accumulated dJ/dVs when given."""
         ptr = lambda t: t.data_ptr() if t is not None else None
-        check(self._lib.lbw_adjoint_step(self._h, run, ptr(f_n), ptr(c_n), ptr(fbar_next),
-                                         ptr(cbar_next), float(dep_bar), ptr(fbar), ptr(cbar),
-                                         ptr(vs_bar), ptr(work), work.numel() * 8))
+        check(self._lib.lbw_adjoint_step(self._h, run, ptr(f_n), ptr(c_n), ptr(u_n), ptr(a1_n),
+                                         ptr(a2_n), ptr(fbar_next), ptr(cbar_next), float(dep_bar),
+                                         ptr(fbar), ptr(cbar), ptr(vs_bar), ptr(work),
+                                         work.numel() * 8))
 
     def setup_workload(self, wl, run=0, seed=None):
         """Initial state of a seeded workload: two-layer scalars, fluid at rest."""

@@ -69,6 +69,21 @@ def test_adjoint_step_matches_oracle(q, frozen, vper, precision):
                      None if frozen else _dev(fbar_next), _dev(cbar_next), dep_bar,
                      None if frozen else fb, cb, vs, work)
     torch.cuda.synchronize()
+    # the same step with the forward intermediates supplied instead of recomputed
+    if not frozen:
+        fr = lbw.Solver(cfg)
+        fr.set_field("f", f_n)
+        fr.set_field("c", c_n)
+        fr.step(1)
+        u_n, a1, a2 = fr.field("u"), fr.field("stage1"), fr.field("stage2")
+        fr.close()
+        fb2, cb2 = torch.zeros_like(fb), torch.zeros_like(cb)
+        vs2 = torch.zeros(1, dtype=torch.float64, device="cuda")
+        sol.adjoint_step(_dev(f_n), _dev(c_n), _dev(fbar_next), _dev(cbar_next), dep_bar, fb2, cb2,
+                         vs2, work, u_n=u_n, a1_n=a1, a2_n=a2)
+        torch.cuda.synchronize()
+        assert torch.equal(fb2, fb) and torch.equal(cb2, cb) and torch.equal(vs2, vs)
+    torch.cuda.synchronize()
     errs = {"cbar": rel(cb.cpu().numpy(), co), "vs_bar": abs(vs.item() - vo) / max(abs(vo), 1e-300)}
     if not frozen:
         errs["fbar"] = rel(fb.cpu().numpy(), fo)
@@ -215,3 +230,4 @@ def test_coupled_gradient_matches_finite_differences():
           f"FP32 vs FP64 gradient L2 {l2:.2e}")
     _check_fd(out, 1e-5)
     assert l2 < 1e-3 and abs(g32[1] - g["fp64"][1]) < 1e-3 * abs(g["fp64"][1])
+
