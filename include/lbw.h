@@ -198,6 +198,19 @@ int lbw_export(lbw_handle *h, int32_t run, int32_t field, void *dst);
  * parity and the step counter.  Asynchronous on the handle's stream. */
 int lbw_import(lbw_handle *h, int32_t run, int32_t field, const void *src);
 
+/* Point the buffer the step writes field `field` of run `run` into at the
+ * caller's device array ptr (same size and layout as the one given at
+ * creation; ptr NULL restores that one).  Only per-step outputs can be
+ * rebound: LBW_FIELD_U (the node velocity of eq. 20, LBW_FLUID_LBM only,
+ * since a frozen velocity is an input), LBW_FIELD_STAGE1 and
+ * LBW_FIELD_STAGE2 (the first two TVD-RK3 stages, S21-S22).  From the next
+ * step on the step writes them there, so a caller that keeps every step's
+ * intermediates (the replay of a checkpointed adjoint) copies nothing.
+ * Nothing is copied; ptr must stay valid while bound.  Drops a captured
+ * graph; for a batch it re-uploads the work lists (synchronises the
+ * stream).  Returns LBW_ERR_INVAL for any other field. */
+int lbw_rebind(lbw_handle *h, int32_t run, int32_t field, void *ptr);
+
 /* FP64 sums per run into out_host[nbatch]: LBW_MASS_C (sum C), LBW_MASS_S
  * (sum S), LBW_MASS_FLUID (sum rho), LBW_DEPOSIT (sum of the deposit
  * counters), the particle mass and deposited mass m_b of section 4.2.3.

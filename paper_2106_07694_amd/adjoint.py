@@ -97,17 +97,17 @@ def backward_from_checkpoints(sol: lbw.Solver, ckpt: dict, nsteps: int, seg: int
         if not frozen:
             sol.import_from("f", f_s)
         sol.import_from("c", c_s)
-        # replay the segment: the state before each step, and the step's own
-        # velocity and RK stages right after it
+        # replay the segment: the state before each step is exported; the
+        # step writes its own velocity and RK stages straight into that
+        # step's buffers
         for i in range(n):
             if not frozen:
                 sol.export_into("f", states[i][0])
+                sol.rebind("u", inter[i][0])
             sol.export_into("c", states[i][1])
+            sol.rebind("stage1", inter[i][1])
+            sol.rebind("stage2", inter[i][2])
             sol.step(1)
-            if not frozen:
-                sol.export_into("u", inter[i][0])
-            sol.export_into("stage1", inter[i][1])
-            sol.export_into("stage2", inter[i][2])
         for i in reversed(range(n)):
             f_n, c_n = states[i]
             u_n, a1, a2 = inter[i]
@@ -120,6 +120,9 @@ def backward_from_checkpoints(sol: lbw.Solver, ckpt: dict, nsteps: int, seg: int
                                  u_n=u_n, a1_n=a1, a2_n=a2)
             fbar_next, fbar = fbar, fbar_next
             cbar_next, cbar = cbar, cbar_next
+    for name in ("u", "stage1", "stage2"):
+        if name != "u" or not frozen:
+            sol.rebind(name, None)
     sol.stream.synchronize()
     return cbar_next.clone(), float(vs_bar.item())
 

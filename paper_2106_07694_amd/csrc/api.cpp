@@ -674,6 +674,25 @@ int lbw_export(lbw_handle *h, int32_t run, int32_t field, void *dst) {
     return e == hipSuccess ? LBW_OK : hip_fail(e, "export");
 }
 
+int lbw_rebind(lbw_handle *h, int32_t run, int32_t field, void *ptr) {
+    int rc = check_run(h, run);
+    if (rc) return rc;
+    lbw::RunDev &r = h->run[run];
+    const lbw_buffers &b = h->buf[run];
+    switch (field) {
+        case LBW_FIELD_U:
+            if (h->fluid_mode != LBW_FLUID_LBM)
+                return fail(LBW_ERR_INVAL, "a frozen velocity is an input: import it instead");
+            r.u = ptr ? ptr : b.u;
+            break;
+        case LBW_FIELD_STAGE1: r.c1 = ptr ? ptr : b.c_s1; break;
+        case LBW_FIELD_STAGE2: r.c2 = ptr ? ptr : b.c_s2; break;
+        default: return fail(LBW_ERR_INVAL, "only U, STAGE1 and STAGE2 can be rebound (field %d)", field);
+    }
+    release_graph(h);
+    return upload_tables(h);
+}
+
 int lbw_import(lbw_handle *h, int32_t run, int32_t field, const void *src) {
     int rc = check_run(h, run);
     if (rc) return rc;

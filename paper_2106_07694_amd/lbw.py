@@ -29,7 +29,7 @@ SCHEMES = {"weno5": WENO5, "weno3": WENO3, "upwind1": UPWIND1}
 
 EXPORTED = ("lbw_version", "lbw_last_error", "lbw_scratch_bytes", "lbw_create", "lbw_destroy",
             "lbw_set_launch", "lbw_get_launch", "lbw_init_equilibrium", "lbw_step",
-            "lbw_steps_done", "lbw_export", "lbw_import", "lbw_reduce", "lbw_timing_begin",
+            "lbw_steps_done", "lbw_export", "lbw_import", "lbw_rebind", "lbw_reduce", "lbw_timing_begin",
             "lbw_timing_end", "lbw_adjoint_work_bytes", "lbw_adjoint_step")
 
 
@@ -94,6 +94,7 @@ def load() -> ctypes.CDLL:
     lib.lbw_steps_done.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
     lib.lbw_export.argtypes = [P, I32, I32, P]
     lib.lbw_import.argtypes = [P, I32, I32, P]
+    lib.lbw_rebind.argtypes = [P, I32, I32, P]
     lib.lbw_reduce.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double)]
     lib.lbw_adjoint_work_bytes.argtypes = [P, I32, ctypes.POINTER(ctypes.c_size_t)]
     lib.lbw_adjoint_step.argtypes = [P, I32, P, P, P, P, P, P, P, ctypes.c_double, P, P, P, P,
@@ -290,6 +291,19 @@ class Solver:
         """Overwrite a field from a device tensor written on the solver's
         stream (no host synchronisation)."""
         check(self._lib.lbw_import(self._h, run, self._FIELDS[name], src.data_ptr()))
+
+    def rebind(self, name, out=None, run=0):
+        """Make the next steps write the per-step field `name` ("u", "stage1"
+        or "stage2") into the device tensor `out` (None: the solver's own
+        buffer again).  The tensor is kept alive while bound."""
+        if not hasattr(self, "_bound"):
+            self._bound = {}
+        check(self._lib.lbw_rebind(self._h, run, self._FIELDS[name],
+                                   out.data_ptr() if out is not None else None))
+        if out is None:
+            self._bound.pop((run, name), None)
+        else:
+            self._bound[(run, name)] = out
 
     def step(self, n=1):
         check(self._lib.lbw_step(self._h, int(n)))

@@ -139,6 +139,28 @@ def test_launch_shape_validation():
         lib.lbw_destroy(h)
 
 
+def test_rebind_accepts_only_per_step_outputs():
+    # host-only: a single run keeps no device tables, so rebinding touches
+    # no device memory
+    lib = lbw.load()
+    for mode, u_ok in ((lbw.FLUID_LBM, True), (lbw.FLUID_FROZEN, False)):
+        cfg = lbw.RunConfig(fluid_mode=mode)
+        c, b = cfg.to_c(), _fake_buffers(cfg)
+        h = ctypes.c_void_p()
+        assert lib.lbw_create(ctypes.byref(c), ctypes.byref(b), 1, None, ctypes.byref(h)) == 0
+        try:
+            p = ctypes.c_void_p(0x7000000)
+            assert lib.lbw_rebind(h, 0, lbw.FIELD_STAGE1, p) == 0
+            assert lib.lbw_rebind(h, 0, lbw.FIELD_STAGE2, p) == 0
+            assert lib.lbw_rebind(h, 0, lbw.FIELD_STAGE1, None) == 0
+            assert (lib.lbw_rebind(h, 0, lbw.FIELD_U, p) == 0) == u_ok
+            for bad in (lbw.FIELD_F, lbw.FIELD_C, lbw.FIELD_S, lbw.FIELD_DEPOSIT, 42):
+                assert lib.lbw_rebind(h, 0, bad, p) == lbw.ERR_INVAL
+            assert lib.lbw_rebind(h, 3, lbw.FIELD_STAGE1, p) == lbw.ERR_INVAL
+        finally:
+            lib.lbw_destroy(h)
+
+
 def test_batched_needs_scratch():
     lib = lbw.load()
     cfgs = [lbw.RunConfig(precision="fp32_shifted"), lbw.RunConfig(precision="fp32_shifted")]
