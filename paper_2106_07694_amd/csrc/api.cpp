@@ -149,6 +149,9 @@ int validate(const lbw_config &c, const lbw_buffers &b, int idx) {
     const int nv = dim == 2 ? c.ny : c.nz;
     if (nv < 6) return fail(LBW_ERR_INVAL, "run %d: vertical extent %d < 6 (one WENO5 stencil)", idx, nv);
     const int64_t N = (int64_t)c.nx * c.ny * c.nz;
+    const int64_t lateral = dim == 2 ? (int64_t)c.nx : (int64_t)c.nx * c.ny;
+    if (lateral * 8 >= ((int64_t)1 << 32))
+        return fail(LBW_ERR_INVAL, "run %d: a horizontal plane must hold fewer than 2^29 cells", idx);
     if (N * (int64_t)c.lattice > (int64_t)1 << 40) return fail(LBW_ERR_INVAL, "run %d: grid too large", idx);
     if (c.fluid_mode != LBW_FLUID_LBM && c.fluid_mode != LBW_FLUID_FROZEN)
         return fail(LBW_ERR_INVAL, "run %d: unknown fluid mode", idx);

@@ -22,27 +22,36 @@ namespace {
 template <typename T> __device__ __forceinline__ T fast_rcp(T x) { return (T)1 / x; }
 template <> __device__ __forceinline__ float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// WENO5-JS face value (same formula as weno5_face) with one reciprocal:
-// alpha_k = d_k / e_k^2 (e_k = eps + indicator k) is multiplied through by
-// e_0^2 e_1^2 e_2^2, which cancels between numerator and denominator.  With
-// e_k >= eps = 1e-6 every product stays far inside the single-precision range.
+// WENO5-JS face value (the formula of weno5_face) rearranged for issue
+// count, with one reciprocal.  The normalised weights are ratios, so every
+// indicator may be scaled by one constant and every ideal weight by another:
+// with e_k = (12/13)(eps + beta_k) = t_k^2 + (3/13) s_k^2 + (12/13) eps
+// (t_k the second difference, s_k the one-sided first difference of
+// sub-stencil k, both built from the four first differences) and the
+// weights multiplied through by 10 e_0^2 e_1^2 e_2^2, the face value is
+//   (P q_0 + Q q_1' + R q_2') / (P + 6 Q + 3 R),
+//   P = e_1^2 e_2^2, Q = e_0^2 e_2^2, R = e_0^2 e_1^2,
+// where q_0 is the first candidate and q_1' = 6 q_1, q_2' = 3 q_2.
+// eps12 is (12/13) eps.  With e_k >= eps12 and concentrations of order one
+// every product stays far inside the single-precision range.
 template <typename T>
 __device__ __forceinline__ T weno5_rcp(T h0, T h1, T h2, T h3, T h4, T a0, T a1, T a2, T a3, T a4,
-                                       T eps) {
-    const T q0 = ((T)2 * h0 - (T)7 * h1 + (T)11 * h2);
-    const T q1 = (-h1 + (T)5 * h2 + (T)2 * h3);
-    const T q2 = ((T)2 * h2 + (T)5 * h3 - h4);
-    T t = a0 - (T)2 * a1 + a2, s = a0 - (T)4 * a1 + (T)3 * a2;
-    const T e0 = eps + ((T)(13.0 / 12.0) * t * t + (T)0.25 * s * s);
-    t = a1 - (T)2 * a2 + a3;
-    s = a1 - a3;
-    const T e1 = eps + ((T)(13.0 / 12.0) * t * t + (T)0.25 * s * s);
-    t = a2 - (T)2 * a3 + a4;
-    s = (T)3 * a2 - (T)4 * a3 + a4;
-    const T e2 = eps + ((T)(13.0 / 12.0) * t * t + (T)0.25 * s * s);
-    const T s0 = e0 * e0, s1 = e1 * e1, s2 = e2 * e2;
-    const T b0 = (T)0.1 * (s1 * s2), b1 = (T)0.6 * (s0 * s2), b2 = (T)0.3 * (s0 * s1);
-    return (b0 * q0 + b1 * q1 + b2 * q2) * fast_rcp<T>((T)6 * (b0 + b1 + b2));
+                                       T eps12) {
+    const T g0 = a1 - a0, g1 = a2 - a1, g2 = a3 - a2, g3 = a4 - a3;
+    const T t0 = g1 - g0, t1 = g2 - g1, t2 = g3 - g2;
+    const T s0 = t0 + (T)2 * g1;          // a0 - 4 a1 + 3 a2
+    const T s1 = g1 + g2;                 // a3 - a1
+    const T s2 = t2 - (T)2 * g2;          // 3 a2 - 4 a3 + a4
+    constexpr T k = (T)(3.0 / 13.0);
+    const T e0 = t0 * t0 + (k * s0 * s0 + eps12);
+    const T e1 = t1 * t1 + (k * s1 * s1 + eps12);
+    const T e2 = t2 * t2 + (k * s2 * s2 + eps12);
+    const T S0 = e0 * e0, S1 = e1 * e1, S2 = e2 * e2;
+    const T P = S1 * S2, Q = S0 * S2, R = S0 * S1;
+    const T q0 = (T)(1.0 / 3.0) * h0 - (T)(7.0 / 6.0) * h1 + (T)(11.0 / 6.0) * h2;
+    const T q1 = (T)5 * h2 - h1 + (T)2 * h3;
+    const T q2 = h2 + (T)2.5 * h3 - (T)0.5 * h4;
+    return (P * q0 + Q * q1 + R * q2) * fast_rcp<T>(P + (T)6 * Q + (T)3 * R);
 }
 
 template <typename T>
@@ -69,7 +78,8 @@ __device__ __forceinline__ T face6(T a0, T a1, T a2, T a3, T a4, T a5, T w0, T w
                 A4 = pos ? a4 : a1;
         const T W0 = pos ? w0 : w5, W1 = pos ? w1 : w4, W2 = pos ? w2 : w3, W3 = pos ? w3 : w2,
                 W4 = pos ? w4 : w1;
-        hh = weno5_rcp<T>(W0 * A0, W1 * A1, W2 * A2, W3 * A3, W4 * A4, A0, A1, A2, A3, A4, eps);
+        hh = weno5_rcp<T>(W0 * A0, W1 * A1, W2 * A2, W3 * A3, W4 * A4, A0, A1, A2, A3, A4,
+                          (T)(12.0 / 13.0) * eps);
     } else if constexpr (SCHEME == LBW_WENO3) {
         const T A0 = pos ? a1 : a4, A1 = pos ? a2 : a3, A2 = pos ? a3 : a2;
         const T W0 = pos ? w1 : w4, W1 = pos ? w2 : w3, W2 = pos ? w3 : w2;
@@ -107,6 +117,15 @@ __device__ __forceinline__ void block_tile(const TileGeom &g, int &bx, int &by, 
     bz = g.bz0 + t / g.gy;
 }
 
+// Addressing: a vertical plane's base pointer is the same for the whole
+// block (uniform, held in scalar registers) and each lane adds a 32-bit byte
+// offset within the plane, so the loads and stores need no 64-bit vector
+// arithmetic.  This needs nx * ny * sizeof(T) < 2^32 (checked at creation).
+template <typename T>
+__device__ __forceinline__ const T &at(const void *plane, uint32_t off) {
+    return *(const T *)((const char *)plane + off);
+}
+
 template <typename T, int D, int SCHEME, int STAGE, int TX, int TY>
 __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, int bx, int by, int bz) {
     constexpr int NT = TX * TY;
@@ -125,17 +144,23 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
     const bool active = gxl < g.nx && (D == 2 || gyl < g.ny);
     const int xw = active ? gxl : gxl % g.nx;       // wrapped column for loads
     const int yw = (D == 3) ? (active ? gyl : gyl % g.ny) : 0;
-    const int64_t col = (int64_t)xw + (int64_t)g.nx * yw;
+    const int col = xw + g.nx * yw;                 // < nx * ny
+    const uint32_t colb = (uint32_t)col * (uint32_t)sizeof(T);
     const int v0 = bz * g.chunk;
     const int v1 = min(v0 + g.chunk, g.nv);
 
-    const T *__restrict__ C = (const T *)r.c;
     const T *__restrict__ ain = (const T *)(STAGE == 1 ? r.c : (STAGE == 2 ? r.c1 : r.c2));
     const T *__restrict__ ux = (const T *)r.u;
     const T *__restrict__ uy = ux + g.N;
     const T *__restrict__ uv = ux + (int64_t)(D - 1) * g.N;
     const T vs = (T)r.vs, kap = (T)r.kappa_c, eps = (T)r.eps;
     const bool walls = !g.vper;
+    auto plane = [&](const void *base, int v) -> const void * {
+        return (const char *)base + (int64_t)v * g.sv * (int64_t)sizeof(T);
+    };
+    auto wplane = [&](void *base, int v) -> void * {
+        return (char *)base + (int64_t)v * g.sv * (int64_t)sizeof(T);
+    };
 
     // vertical index with the wall/periodic rule; sets flip for mirrored nodes
     auto vidx = [&](int v, bool &flip) -> int {
@@ -151,26 +176,27 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
     auto load_av = [&](int v, T &a, T &w) {
         bool flip;
         const int vv = vidx(v, flip);
-        const int64_t k = col + (int64_t)vv * g.sv;
-        a = ain[k];
-        const T u = uv[k];
+        a = at<T>(plane(ain, vv), colb);
+        const T u = at<T>(plane(uv, vv), colb);
         w = (flip ? -u : u) - vs;
     };
 
-    // lateral halo slots of this thread (fixed over the march)
+    // lateral halo slots of this thread (fixed over the march), as byte
+    // offsets within a plane and LDS indices (-1: no slot)
     // a-plane cross: rows ty in [0,TY) x cols [0,AX), plus (3D) y-halo rows
     constexpr int NA = (D == 3) ? AX * TY + TX * 6 : AX;
     constexpr int NUX = AX * TY;
     constexpr int NUY = (D == 3) ? TX * (TY + 6) : 0;
     constexpr int SA = (NA + NT - 1) / NT, SUX = (NUX + NT - 1) / NT, SUY = (NUY + NT - 1) / NT;
-    int64_t offA[SA];
+    uint32_t offA[SA];
     int ldsA[SA];
-    int64_t offX[SUX];
+    uint32_t offX[SUX];
     int ldsX[SUX];
-    int64_t offY[(SUY > 0) ? SUY : 1];
+    uint32_t offY[(SUY > 0) ? SUY : 1];
     int ldsY[(SUY > 0) ? SUY : 1];
     auto wrapx = [&](int x) { x %= g.nx; return x < 0 ? x + g.nx : x; };
     auto wrapy = [&](int y) { y %= g.ny; return y < 0 ? y + g.ny : y; };
+    auto lat = [&](int x, int y) { return (uint32_t)(x + g.nx * y) * (uint32_t)sizeof(T); };
 #pragma unroll
     for (int s = 0; s < SA; ++s) {
         const int i = tid + s * NT;
@@ -180,9 +206,7 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
             int lx, ly;  // plane-local coords, halo origin at (-3, -3)
             if (i < AX * TY) { lx = i % AX; ly = (D == 3) ? (i / AX) + 3 : 0; }
             else { const int j = i - AX * TY; lx = (j % TX) + 3; ly = (j / TX) < 3 ? (j / TX) : (j / TX) + TY; }
-            const int gxx = wrapx(x0 + lx - 3);
-            const int gyy = (D == 3) ? wrapy(y0 + ly - 3) : 0;
-            offA[s] = (int64_t)gxx + (int64_t)g.nx * gyy;
+            offA[s] = lat(wrapx(x0 + lx - 3), (D == 3) ? wrapy(y0 + ly - 3) : 0);
             ldsA[s] = ly * AX + lx;
         }
     }
@@ -193,9 +217,7 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
         offX[s] = 0;
         if (i < NUX) {
             const int lx = i % AX, ly = i / AX;
-            const int gxx = wrapx(x0 + lx - 3);
-            const int gyy = (D == 3) ? wrapy(y0 + ly) : 0;
-            offX[s] = (int64_t)gxx + (int64_t)g.nx * gyy;
+            offX[s] = lat(wrapx(x0 + lx - 3), (D == 3) ? wrapy(y0 + ly) : 0);
             ldsX[s] = ly * AX + lx;
         }
     }
@@ -206,12 +228,15 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
         offY[s] = 0;
         if (i < NUY) {
             const int lx = i % TX, ly = i / TX;
-            const int gxx = wrapx(x0 + lx);
-            const int gyy = wrapy(y0 + ly - 3);
-            offY[s] = (int64_t)gxx + (int64_t)g.nx * gyy;
+            offY[s] = lat(wrapx(x0 + lx), wrapy(y0 + ly - 3));
             ldsY[s] = ly * TX + lx;
         }
     }
+
+    // faces on the far edges of the tile (x faces of column TX, y faces of
+    // row TY), taken by the first lanes in one extra pass with strided LDS
+    // reads, so that the main passes are exactly one face per thread
+    constexpr int NEX = (D == 3) ? TY + TX : 1;
 
     // vertical windows: a and w at v-2 .. v+3 for the face above v
     T aw[6], ww[6];
@@ -233,13 +258,13 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
     auto prefetch = [&](int v) {
         bool flip;
         const int vv = vidx(v, flip);
-        const int64_t base = (int64_t)vv * g.sv;
+        const void *pa = plane(ain, vv), *px = plane(ux, vv), *py = plane(uy, vv);
 #pragma unroll
-        for (int s = 0; s < SA; ++s) pA[s] = ldsA[s] >= 0 ? ain[base + offA[s]] : (T)0;
+        for (int s = 0; s < SA; ++s) pA[s] = ldsA[s] >= 0 ? at<T>(pa, offA[s]) : (T)0;
 #pragma unroll
-        for (int s = 0; s < SUX; ++s) pX[s] = ldsX[s] >= 0 ? ux[base + offX[s]] : (T)0;
+        for (int s = 0; s < SUX; ++s) pX[s] = ldsX[s] >= 0 ? at<T>(px, offX[s]) : (T)0;
 #pragma unroll
-        for (int s = 0; s < SUY; ++s) pY[s] = ldsY[s] >= 0 ? uy[base + offY[s]] : (T)0;
+        for (int s = 0; s < SUY; ++s) pY[s] = ldsY[s] >= 0 ? at<T>(py, offY[s]) : (T)0;
     };
     prefetch(v0);
 
@@ -256,27 +281,38 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
         if (v + 1 < v1) prefetch(v + 1);
         T anext, wnext;
         load_av(v + 4, anext, wnext);
-        const int64_t kc = col + (int64_t)v * g.sv;
         T cown = (T)0;
-        if (STAGE != 1) cown = C[kc];
+        if (STAGE != 1) cown = at<T>(plane(r.c, v), colb);
 
-        // lateral faces: x faces (TX+1 per row), then y faces (TY+1 per column)
-        for (int i = tid; i < TY * (TX + 1); i += NT) {
-            const int fx = i % (TX + 1), fy = i / (TX + 1);  // face between local fx-1 and fx
-            const T *ar = sA + ((D == 3) ? (fy + 3) : 0) * AX + fx;   // node fx-3 .. fx+2 -> +0..+5
-            const T *ur = sUx + fy * AX + fx;
-            sFx[fy * (TX + 1) + fx] = face6<T, SCHEME>(ar[0], ar[1], ar[2], ar[3], ar[4], ar[5], ur[0],
+        // lateral faces: each thread the x face on the left of its cell and
+        // (3D) the y face below it
+        {
+            const T *ar = sA + ((D == 3) ? (ty + 3) : 0) * AX + tx;   // nodes tx-3 .. tx+2
+            const T *ur = sUx + ty * AX + tx;
+            sFx[ty * (TX + 1) + tx] = face6<T, SCHEME>(ar[0], ar[1], ar[2], ar[3], ar[4], ar[5], ur[0],
                                                         ur[1], ur[2], ur[3], ur[4], ur[5], kap, eps);
         }
         if constexpr (D == 3) {
-            for (int i = tid; i < (TY + 1) * TX; i += NT) {
-                const int fx = i % TX, fy = i / TX;   // face between local rows fy-1 and fy
-                const T *ac = sA + fy * AX + fx + 3;   // rows fy-3+3 .. : column fx
-                const T *uc = sUy + fy * TX + fx;
-                sFy[fy * TX + fx] = face6<T, SCHEME>(ac[0], ac[AX], ac[2 * AX], ac[3 * AX], ac[4 * AX],
-                                                     ac[5 * AX], uc[0], uc[TX], uc[2 * TX], uc[3 * TX],
-                                                     uc[4 * TX], uc[5 * TX], kap, eps);
+            const T *ac = sA + ty * AX + tx + 3;      // rows ty-3+3 .. ty+2+3 of column tx
+            const T *uc = sUy + ty * TX + tx;
+            sFy[ty * TX + tx] = face6<T, SCHEME>(ac[0], ac[AX], ac[2 * AX], ac[3 * AX], ac[4 * AX],
+                                                 ac[5 * AX], uc[0], uc[TX], uc[2 * TX], uc[3 * TX],
+                                                 uc[4 * TX], uc[5 * TX], kap, eps);
+        }
+        for (int e = tid; e < NEX; e += NT) {
+            const bool xf = e < TY;                   // x face of column TX, row e
+            const int fy = xf ? e : TY, fx = xf ? TX : e - TY;
+            const T *ar = xf ? sA + ((D == 3) ? (fy + 3) : 0) * AX + fx : sA + fx + 3;
+            const T *ur = xf ? sUx + fy * AX + fx : sUy + fx;
+            const int sa = xf ? 1 : AX, su = xf ? 1 : TX;
+            if constexpr (D == 3) {
+                if (!xf) { ar += fy * AX; ur += fy * TX; }
             }
+            const T f = face6<T, SCHEME>(ar[0], ar[sa], ar[2 * sa], ar[3 * sa], ar[4 * sa], ar[5 * sa],
+                                         ur[0], ur[su], ur[2 * su], ur[3 * su], ur[4 * su], ur[5 * su],
+                                         kap, eps);
+            if (xf) sFx[fy * (TX + 1) + fx] = f;
+            else if constexpr (D == 3) sFy[fy * TX + fx] = f;
         }
         // vertical face above this cell
         T fabove;
@@ -292,17 +328,17 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
         const T a = aw[2];
         if (active) {
             if constexpr (STAGE == 1) {
-                ((T *)r.c1)[kc] = a + L;
+                *(T *)((char *)wplane(r.c1, v) + colb) = a + L;
             } else if constexpr (STAGE == 2) {
-                ((T *)r.c2)[kc] = (T)0.75 * cown + (T)0.25 * a + (T)0.25 * L;
+                *(T *)((char *)wplane(r.c2, v) + colb) = (T)0.75 * cown + (T)0.25 * a + (T)0.25 * L;
             } else {
                 if (walls && v == 0) {
                     const double o0 = r.vs * (double)cown;
-                    const double o1 = r.vs * (double)((const T *)r.c1)[kc];
+                    const double o1 = r.vs * (double)at<T>(plane(r.c1, 0), colb);
                     const double o2 = r.vs * (double)a;
                     r.dep[col] += o0 / 6.0 + o1 / 6.0 + 2.0 / 3.0 * o2;
                 }
-                ((T *)r.c)[kc] = cown / (T)3 + (T)(2.0 / 3.0) * a + (T)(2.0 / 3.0) * L;
+                *(T *)((char *)wplane(r.c, v) + colb) = cown / (T)3 + (T)(2.0 / 3.0) * a + (T)(2.0 / 3.0) * L;
             }
         }
         fbelow = fabove;
