@@ -79,7 +79,8 @@ enum { LBW_FP64 = 0, LBW_FP32_SHIFTED = 1, LBW_FP64_SHIFTED = 2 };
 enum { LBW_FLUID_LBM = 0, LBW_FLUID_FROZEN = 1 };
 enum { LBW_WENO5 = 0, LBW_WENO3 = 1, LBW_UPWIND1 = 2 };
 enum { LBW_FIELD_F = 0, LBW_FIELD_C = 1, LBW_FIELD_S = 2, LBW_FIELD_U = 3,
-       LBW_FIELD_DEPOSIT = 4, LBW_FIELD_STAGE1 = 5, LBW_FIELD_STAGE2 = 6 };
+       LBW_FIELD_DEPOSIT = 4, LBW_FIELD_STAGE1 = 5, LBW_FIELD_STAGE2 = 6,
+       LBW_FIELD_RHO = 7 };
 enum { LBW_MASS_C = 0, LBW_MASS_S = 1, LBW_MASS_FLUID = 2, LBW_DEPOSIT = 3 };
 enum { LBW_PHASE_COLLIDE_STREAM = 0, LBW_PHASE_TRANSPORT = 1, LBW_NPHASES = 2 };
 
@@ -203,8 +204,11 @@ int lbw_import(lbw_handle *h, int32_t run, int32_t field, const void *src);
  * creation; ptr NULL restores that one).  Only per-step outputs can be
  * rebound: LBW_FIELD_U (the node velocity of eq. 20, LBW_FLUID_LBM only,
  * since a frozen velocity is an input), LBW_FIELD_STAGE1 and
- * LBW_FIELD_STAGE2 (the first two TVD-RK3 stages, S21-S22).  From the next
- * step on the step writes them there, so a caller that keeps every step's
+ * LBW_FIELD_STAGE2 (the first two TVD-RK3 stages, S21-S22), and
+ * LBW_FIELD_RHO (the node density of eq. 19, LBW_FLUID_LBM only; N values of
+ * the run's element type): the density has no buffer of its own and is
+ * written only while bound (ptr NULL stops it).  From the next step on the
+ * step writes them there, so a caller that keeps every step's
  * intermediates (the replay of a checkpointed adjoint) copies nothing.
  * Nothing is copied; ptr must stay valid while bound.  Drops a captured
  * graph; for a batch it re-uploads the work lists (synchronises the
@@ -229,10 +233,13 @@ int lbw_adjoint_work_bytes(const lbw_handle *h, int32_t run, size_t *out_bytes);
  * streaming.  For J a function of the state at n+1:
  *   f_n, c_n     forward state at n (canonical populations, as lbw_export
  *                writes them; C), device arrays of the run's element type;
- *   u_n, a1_n, a2_n  optional forward intermediates of step n (its node
- *                velocity and first two RK stages, as lbw_export gives
- *                LBW_FIELD_U, LBW_FIELD_STAGE1, LBW_FIELD_STAGE2 right after
- *                that step); NULL: recomputed from f_n and c_n;
+ *                f_n may be NULL when u_n and rho_n are given;
+ *   u_n, rho_n, a1_n, a2_n  optional forward intermediates of step n (its
+ *                node velocity and density and first two RK stages, as the
+ *                step writes them into buffers bound with lbw_rebind, or as
+ *                lbw_export gives U, STAGE1, STAGE2 right after that step);
+ *                NULL: recomputed from f_n and c_n (rho_n is used only
+ *                together with u_n);
  *   fbar_next    dJ/df^{n+1} (canonical layout); cbar_next = dJ/dC^{n+1};
  *   dep_bar      dJ/d(deposit) of every column (1 for the total deposited
  *                mass m_b of section 4.2.3);
@@ -247,7 +254,7 @@ int lbw_adjoint_work_bytes(const lbw_handle *h, int32_t run, size_t *out_bytes);
  * be NULL.  Asynchronous on the handle's stream; independent of the handle's
  * own state buffers apart from that velocity. */
 int lbw_adjoint_step(lbw_handle *h, int32_t run, const void *f_n, const void *c_n,
-                     const void *u_n, const void *a1_n, const void *a2_n,
+                     const void *u_n, const void *rho_n, const void *a1_n, const void *a2_n,
                      const void *fbar_next, const void *cbar_next, double dep_bar, void *fbar,
                      void *cbar, double *vs_bar_dev, void *work, size_t work_bytes);
 

@@ -33,20 +33,22 @@ def _solver(cfg: lbw.RunConfig, vs: float, launch=None) -> lbw.Solver:
     return sol
 
 
-def _state_buffers(sol, count):
+def _state_buffers(sol, count, populations=True):
     cfg = sol.cfgs[0]
     with torch.cuda.stream(sol.stream):
-        return [(torch.empty((cfg.lattice,) + cfg.shape, dtype=sol.dtype, device=sol.device),
+        return [(torch.empty((cfg.lattice,) + cfg.shape, dtype=sol.dtype, device=sol.device)
+                 if populations else None,
                  torch.empty(cfg.shape, dtype=sol.dtype, device=sol.device)) for _ in range(count)]
 
 
-def _step_buffers(sol, count):
-    """Per-step forward intermediates (velocity, RK stages 1 and 2)."""
+def _step_buffers(sol, count, moments=True):
+    """Per-step forward intermediates: node velocity and density (LBM mode),
+    RK stages 1 and 2."""
     cfg = sol.cfgs[0]
+    e = lambda *shape: torch.empty(shape, dtype=sol.dtype, device=sol.device)
     with torch.cuda.stream(sol.stream):
-        return [(torch.empty((cfg.dim,) + cfg.shape, dtype=sol.dtype, device=sol.device),
-                 torch.empty(cfg.shape, dtype=sol.dtype, device=sol.device),
-                 torch.empty(cfg.shape, dtype=sol.dtype, device=sol.device)) for _ in range(count)]
+        return [(e(cfg.dim, *cfg.shape) if moments else None, e(*cfg.shape) if moments else None,
+                 e(*cfg.shape), e(*cfg.shape)) for _ in range(count)]
 
 
 def forward_with_checkpoints(cfg, c0: torch.Tensor, vs: float, nsteps: int, seg: int, launch=None,
@@ -87,9 +89,12 @@ def backward_from_checkpoints(sol: lbw.Solver, ckpt: dict, nsteps: int, seg: int
         cbar = torch.empty_like(cbar_next)
         vs_bar = torch.zeros(1, dtype=torch.float64, device=dev)
     work = sol.adjoint_workspace()
-    states = _state_buffers(sol, seg)
-    inter = _step_buffers(sol, seg)
     frozen = cfg.fluid_mode == lbw.FLUID_FROZEN
+    # per replayed step: C before the step, and the step's own velocity,
+    # density and RK stages (the populations are not needed: the reverse
+    # collision uses only their moments)
+    states = _state_buffers(sol, seg, populations=False)
+    inter = _step_buffers(sol, seg, moments=not frozen)
     last = min(ckpt)
     for s0 in reversed(sorted(ckpt)):
         n = min(seg, nsteps - s0)
@@ -97,31 +102,31 @@ def backward_from_checkpoints(sol: lbw.Solver, ckpt: dict, nsteps: int, seg: int
         if not frozen:
             sol.import_from("f", f_s)
         sol.import_from("c", c_s)
-        # replay the segment: the state before each step is exported; the
-        # step writes its own velocity and RK stages straight into that
-        # step's buffers
+        # replay the segment: the step writes its intermediates straight
+        # into that step's buffers
         for i in range(n):
+            u_n, rho_n, a1, a2 = inter[i]
             if not frozen:
-                sol.export_into("f", states[i][0])
-                sol.rebind("u", inter[i][0])
+                sol.rebind("u", u_n)
+                sol.rebind("rho", rho_n)
             sol.export_into("c", states[i][1])
-            sol.rebind("stage1", inter[i][1])
-            sol.rebind("stage2", inter[i][2])
+            sol.rebind("stage1", a1)
+            sol.rebind("stage2", a2)
             sol.step(1)
         for i in reversed(range(n)):
-            f_n, c_n = states[i]
-            u_n, a1, a2 = inter[i]
+            c_n = states[i][1]
+            u_n, rho_n, a1, a2 = inter[i]
             vs_out = vs_bar if (s0 == last and i == 0) else None
             if frozen:
                 sol.adjoint_step(None, c_n, None, cbar_next, dep_bar, None, cbar, vs_out, work,
                                  a1_n=a1, a2_n=a2)
             else:
-                sol.adjoint_step(f_n, c_n, fbar_next, cbar_next, dep_bar, fbar, cbar, vs_out, work,
-                                 u_n=u_n, a1_n=a1, a2_n=a2)
+                sol.adjoint_step(None, c_n, fbar_next, cbar_next, dep_bar, fbar, cbar, vs_out, work,
+                                 u_n=u_n, rho_n=rho_n, a1_n=a1, a2_n=a2)
             fbar_next, fbar = fbar, fbar_next
             cbar_next, cbar = cbar, cbar_next
-    for name in ("u", "stage1", "stage2"):
-        if name != "u" or not frozen:
+    for name in ("u", "rho", "stage1", "stage2"):
+        if name in ("stage1", "stage2") or not frozen:
             sol.rebind(name, None)
     sol.stream.synchronize()
     return cbar_next.clone(), float(vs_bar.item())

@@ -33,13 +33,13 @@ namespace {
 
 struct AdjDev {
     RunDev r;
-    const void *f_n, *c_n, *fbar_next, *cbar_next;
+    const void *f_n, *c_n, *rho_n, *fbar_next, *cbar_next;
     void *fbar, *cbar;
     void *u, *a1, *a2, *abar1, *abar2, *ubar, *faceA, *faceW;
     double *vs_part, *partials, *vs_bar;
     double dep_bar;
     int frozen;
-    int have_u, have_stages;   // forward intermediates supplied by the caller
+    int have_u, have_rho, have_stages;   // forward intermediates supplied by the caller
 };
 
 template <int D>
@@ -221,20 +221,31 @@ __device__ __forceinline__ T collide_reverse_node(const AdjDev &A, int64_t k, in
     using L = Lattice<Q>;
     constexpr int D = L::D;
     const RunDev &r = A.r;
-    const T *f = (const T *)A.f_n;
     const T *fbn = (const T *)A.fbar_next;
     T fi[Q], fsb[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        fi[i] = f[(int64_t)i * r.N + k];
         // forward streaming sent f*_i(x) to slot i of x + c_i, or to slot
         // opp(i) of x across a wall: pull the adjoint from there
         const int64_t dst = displaced<D>(r, x, y, z, L::cx[i], L::cy[i], L::cz[i]);
         fsb[i] = dst >= 0 ? fbn[(int64_t)i * r.N + dst] : fbn[(int64_t)L::opp[i] * r.N + k];
     }
-    T F[3], u[3], rho, drho;
+    T F[3], u[3] = {0, 0, 0}, rho;
     lbm_force<D, T>(r, (const T *)A.c_n, nullptr, k, F);
-    lbm_rho_u<Q, T, SH>(fi, F, rho, drho, u);
+    if (A.have_rho) {
+        // the forward step's own moments (what lbm_rho_u gives from f^n, bit
+        // for bit): the populations themselves are not needed
+        const T *uu = (const T *)A.u;
+#pragma unroll
+        for (int d = 0; d < D; ++d) u[d] = uu[(int64_t)d * r.N + k];
+        rho = ((const T *)A.rho_n)[k];
+    } else {
+        const T *f = (const T *)A.f_n;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) fi[i] = f[(int64_t)i * r.N + k];
+        T drho;
+        lbm_rho_u<Q, T, SH>(fi, F, rho, drho, u);
+    }
     const T usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     const T omega = (T)r.omega, guo = (T)r.guo;
     T ub[3] = {ubt[0], ubt[1], ubt[2]}, Fb[3] = {0, 0, 0}, rb = 0;
@@ -469,7 +480,8 @@ size_t adjoint_work_bytes(int dim, int precision, int64_t N) {
 }
 
 hipError_t launch_adjoint(int q, int precision, const RunDev &r, bool frozen, const void *f_n,
-                          const void *c_n, const void *u_n, const void *a1_n, const void *a2_n,
+                          const void *c_n, const void *u_n, const void *rho_n, const void *a1_n,
+                          const void *a2_n,
                           const void *fbar_next, const void *cbar_next,
                           double dep_bar, void *fbar, void *cbar, double *vs_bar, void *work,
                           const lbw_launch &l, hipStream_t st) {
@@ -481,6 +493,7 @@ hipError_t launch_adjoint(int q, int precision, const RunDev &r, bool frozen, co
     A.r = r;
     A.f_n = f_n;
     A.c_n = c_n;
+    A.rho_n = rho_n;
     A.fbar_next = fbar_next;
     A.cbar_next = cbar_next;
     A.fbar = fbar;
@@ -499,6 +512,7 @@ hipError_t launch_adjoint(int q, int precision, const RunDev &r, bool frozen, co
     A.dep_bar = dep_bar;
     A.frozen = frozen ? 1 : 0;
     A.have_u = (u_n != nullptr && !frozen) ? 1 : 0;
+    A.have_rho = (A.have_u && rho_n != nullptr) ? 1 : 0;
     A.have_stages = (a1_n != nullptr && a2_n != nullptr) ? 1 : 0;
     if (A.have_u) A.u = const_cast<void *>(u_n);
     if (A.have_stages) {

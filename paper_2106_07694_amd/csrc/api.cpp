@@ -189,6 +189,7 @@ lbw::RunDev make_run(const lbw_config &c, const lbw_buffers &b) {
     r.s = b.s;
     r.s2 = b.s_tmp;
     r.u = b.u;
+    r.rho = nullptr;
     r.dep = b.deposit;
     r.nx = c.nx;
     r.ny = c.ny;
@@ -587,7 +588,7 @@ int lbw_adjoint_work_bytes(const lbw_handle *h, int32_t run, size_t *out_bytes) 
 }
 
 int lbw_adjoint_step(lbw_handle *h, int32_t run, const void *f_n, const void *c_n,
-                     const void *u_n, const void *a1_n, const void *a2_n,
+                     const void *u_n, const void *rho_n, const void *a1_n, const void *a2_n,
                      const void *fbar_next, const void *cbar_next, double dep_bar, void *fbar,
                      void *cbar, double *vs_bar_dev, void *work, size_t work_bytes) {
     int rc = check_run(h, run);
@@ -598,15 +599,17 @@ int lbw_adjoint_step(lbw_handle *h, int32_t run, const void *f_n, const void *c_
     if (!c_n || !cbar_next || !cbar || !work) return fail(LBW_ERR_INVAL, "NULL required argument");
     if ((a1_n == nullptr) != (a2_n == nullptr))
         return fail(LBW_ERR_INVAL, "give both RK stages or neither");
-    if (!frozen && (!f_n || !fbar_next || !fbar))
-        return fail(LBW_ERR_INVAL, "populations and their adjoints are required");
+    if (!frozen && (!fbar_next || !fbar))
+        return fail(LBW_ERR_INVAL, "the population adjoints are required");
+    if (!frozen && !f_n && !(u_n && rho_n))
+        return fail(LBW_ERR_INVAL, "give the populations, or the velocity and the density");
     if (cbar == cbar_next || cbar == c_n || (!frozen && (fbar == fbar_next || fbar == f_n)))
         return fail(LBW_ERR_INVAL, "outputs must not alias inputs");
     if (!std::isfinite(dep_bar)) return fail(LBW_ERR_INVAL, "dep_bar must be finite");
     const size_t need = lbw::adjoint_work_bytes(h->dim, h->precision, h->run[run].N);
     if (work_bytes < need) return fail(LBW_ERR_INVAL, "work needs %zu bytes", need);
-    hipError_t e = lbw::launch_adjoint(h->q, h->precision, h->run[run], frozen, f_n, c_n, u_n, a1_n,
-                                       a2_n, fbar_next, cbar_next, dep_bar, fbar, cbar, vs_bar_dev,
+    hipError_t e = lbw::launch_adjoint(h->q, h->precision, h->run[run], frozen, f_n, c_n, u_n, rho_n,
+                                       a1_n, a2_n, fbar_next, cbar_next, dep_bar, fbar, cbar, vs_bar_dev,
                                        work, h->launch, h->stream);
     return e == hipSuccess ? LBW_OK : hip_fail(e, "adjoint launch");
 }
@@ -688,9 +691,13 @@ int lbw_rebind(lbw_handle *h, int32_t run, int32_t field, void *ptr) {
                 return fail(LBW_ERR_INVAL, "a frozen velocity is an input: import it instead");
             r.u = ptr ? ptr : b.u;
             break;
+        case LBW_FIELD_RHO:
+            if (h->fluid_mode != LBW_FLUID_LBM) return fail(LBW_ERR_INVAL, "a frozen fluid has no density");
+            r.rho = ptr;
+            break;
         case LBW_FIELD_STAGE1: r.c1 = ptr ? ptr : b.c_s1; break;
         case LBW_FIELD_STAGE2: r.c2 = ptr ? ptr : b.c_s2; break;
-        default: return fail(LBW_ERR_INVAL, "only U, STAGE1 and STAGE2 can be rebound (field %d)", field);
+        default: return fail(LBW_ERR_INVAL, "only U, RHO, STAGE1 and STAGE2 can be rebound (field %d)", field);
     }
     release_graph(h);
     return upload_tables(h);

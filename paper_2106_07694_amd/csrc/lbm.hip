@@ -43,6 +43,7 @@ __device__ __forceinline__ void collide_stream_node(const RunDev &r, int64_t k) 
     uo[k] = ux;
     uo[r.N + k] = uy;
     if (D == 3) uo[2 * r.N + k] = uz;
+    if (r.rho) ((T *)r.rho)[k] = rho;
 
     // BGK + Guo collision (eq. 18, 22)
     const T omega = (T)r.omega, guo = (T)r.guo;

@@ -47,6 +47,7 @@ struct RunDev {
     void *c, *c1, *c2;   // C and the two RK stage buffers
     void *s, *s2;        // S and its work buffer (current S is `s`)
     void *u;             // dim*N node velocity
+    void *rho;           // N node density, written only when non-NULL
     double *dep;         // per-column deposit
     int32_t nx, ny, nz;  // grid
     int32_t vper;        // vertical axis periodic
@@ -105,7 +106,8 @@ hipError_t launch_collide_stream_batched(int q, int precision, const RunDev *run
 hipError_t launch_rk_stages12(int dim, int precision, const RunDev &r, hipStream_t st);
 size_t adjoint_work_bytes(int dim, int precision, int64_t N);
 hipError_t launch_adjoint(int q, int precision, const RunDev &r, bool frozen, const void *f_n,
-                          const void *c_n, const void *u_n, const void *a1_n, const void *a2_n,
+                          const void *c_n, const void *u_n, const void *rho_n, const void *a1_n,
+                          const void *a2_n,
                           const void *fbar_next, const void *cbar_next,
                           double dep_bar, void *fbar, void *cbar, double *vs_bar, void *work,
                           const lbw_launch &l, hipStream_t st);

@@ -20,7 +20,7 @@ D2Q9, D3Q19 = 9, 19
 FP64, FP32_SHIFTED, FP64_SHIFTED = 0, 1, 2
 FLUID_LBM, FLUID_FROZEN = 0, 1
 WENO5, WENO3, UPWIND1 = 0, 1, 2
-FIELD_F, FIELD_C, FIELD_S, FIELD_U, FIELD_DEPOSIT, FIELD_STAGE1, FIELD_STAGE2 = 0, 1, 2, 3, 4, 5, 6
+FIELD_F, FIELD_C, FIELD_S, FIELD_U, FIELD_DEPOSIT, FIELD_STAGE1, FIELD_STAGE2, FIELD_RHO = range(8)
 MASS_C, MASS_S, MASS_FLUID, DEPOSIT = 0, 1, 2, 3
 ERR_INVAL, ERR_UNSUPPORTED, ERR_HIP, ERR_NONFINITE = -1, -2, -3, -4
 
@@ -97,7 +97,7 @@ def load() -> ctypes.CDLL:
     lib.lbw_rebind.argtypes = [P, I32, I32, P]
     lib.lbw_reduce.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double)]
     lib.lbw_adjoint_work_bytes.argtypes = [P, I32, ctypes.POINTER(ctypes.c_size_t)]
-    lib.lbw_adjoint_step.argtypes = [P, I32, P, P, P, P, P, P, P, ctypes.c_double, P, P, P, P,
+    lib.lbw_adjoint_step.argtypes = [P, I32, P, P, P, P, P, P, P, P, ctypes.c_double, P, P, P, P,
                                      ctypes.c_size_t]
     lib.lbw_timing_begin.argtypes = [P]
     lib.lbw_timing_end.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
@@ -280,7 +280,7 @@ class Solver:
         return out
 
     _FIELDS = {"f": FIELD_F, "c": FIELD_C, "s": FIELD_S, "u": FIELD_U, "deposit": FIELD_DEPOSIT,
-               "stage1": FIELD_STAGE1, "stage2": FIELD_STAGE2}
+               "stage1": FIELD_STAGE1, "stage2": FIELD_STAGE2, "rho": FIELD_RHO}
 
     def export_into(self, name, out, run=0):
         """Canonical copy of a field into an existing device tensor, ordered on
@@ -293,9 +293,10 @@ class Solver:
         check(self._lib.lbw_import(self._h, run, self._FIELDS[name], src.data_ptr()))
 
     def rebind(self, name, out=None, run=0):
-        """Make the next steps write the per-step field `name` ("u", "stage1"
-        or "stage2") into the device tensor `out` (None: the solver's own
-        buffer again).  The tensor is kept alive while bound."""
+        """Make the next steps write the per-step field `name` ("u", "rho",
+        "stage1" or "stage2") into the device tensor `out` (None: the
+        solver's own buffer again; for "rho", no density is written).  The
+        tensor is kept alive while bound."""
         if not hasattr(self, "_bound"):
             self._bound = {}
         check(self._lib.lbw_rebind(self._h, run, self._FIELDS[name],
@@ -345,11 +346,12 @@ class Solver:
             return self._torch.zeros((n.value + 7) // 8, dtype=self._torch.float64, device=self.device)
 
     def adjoint_step(self, f_n, c_n, fbar_next, cbar_next, dep_bar, fbar, cbar, vs_bar, work, run=0,
-                     u_n=None, a1_n=None, a2_n=None):
+                     u_n=None, a1_n=None, a2_n=None, rho_n=None):
         """One reverse step (device tensors; see lbw_adjoint_step).  vs_bar
         (or None) receives the accumulated dJ/dVs when given."""
         ptr = lambda t: t.data_ptr() if t is not None else None
-        check(self._lib.lbw_adjoint_step(self._h, run, ptr(f_n), ptr(c_n), ptr(u_n), ptr(a1_n),
+        check(self._lib.lbw_adjoint_step(self._h, run, ptr(f_n), ptr(c_n), ptr(u_n), ptr(rho_n),
+                                         ptr(a1_n),
                                          ptr(a2_n), ptr(fbar_next), ptr(cbar_next), float(dep_bar),
                                          ptr(fbar), ptr(cbar), ptr(vs_bar), ptr(work),
                                          work.numel() * 8))

@@ -154,6 +154,8 @@ def test_rebind_accepts_only_per_step_outputs():
             assert lib.lbw_rebind(h, 0, lbw.FIELD_STAGE2, p) == 0
             assert lib.lbw_rebind(h, 0, lbw.FIELD_STAGE1, None) == 0
             assert (lib.lbw_rebind(h, 0, lbw.FIELD_U, p) == 0) == u_ok
+            assert (lib.lbw_rebind(h, 0, lbw.FIELD_RHO, p) == 0) == u_ok
+            assert (lib.lbw_rebind(h, 0, lbw.FIELD_RHO, None) == 0) == u_ok
             for bad in (lbw.FIELD_F, lbw.FIELD_C, lbw.FIELD_S, lbw.FIELD_DEPOSIT, 42):
                 assert lib.lbw_rebind(h, 0, bad, p) == lbw.ERR_INVAL
             assert lib.lbw_rebind(h, 3, lbw.FIELD_STAGE1, p) == lbw.ERR_INVAL

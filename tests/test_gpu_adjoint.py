@@ -74,15 +74,28 @@ def test_adjoint_step_matches_oracle(q, frozen, vper, precision):
         fr = lbw.Solver(cfg)
         fr.set_field("f", f_n)
         fr.set_field("c", c_n)
+        rho_n = torch.full(ocfg.shape, float("nan"), dtype=torch.float64, device="cuda")
+        fr.rebind("rho", rho_n)
         fr.step(1)
+        fr.rebind("rho", None)
         u_n, a1, a2 = fr.field("u"), fr.field("stage1"), fr.field("stage2")
         fr.close()
+        # the density the step wrote is the zeroth moment of f^n
+        rho_ref = f_n.sum(axis=0) + (1.0 if precision == "fp64_shifted" else 0.0)
+        assert np.max(np.abs(rho_n.cpu().numpy() - rho_ref)) < 1e-13
         fb2, cb2 = torch.zeros_like(fb), torch.zeros_like(cb)
         vs2 = torch.zeros(1, dtype=torch.float64, device="cuda")
         sol.adjoint_step(_dev(f_n), _dev(c_n), _dev(fbar_next), _dev(cbar_next), dep_bar, fb2, cb2,
                          vs2, work, u_n=u_n, a1_n=a1, a2_n=a2)
         torch.cuda.synchronize()
         assert torch.equal(fb2, fb) and torch.equal(cb2, cb) and torch.equal(vs2, vs)
+        # and with the moments supplied, no populations at all
+        fb3, cb3 = torch.zeros_like(fb), torch.zeros_like(cb)
+        vs3 = torch.zeros(1, dtype=torch.float64, device="cuda")
+        sol.adjoint_step(None, _dev(c_n), _dev(fbar_next), _dev(cbar_next), dep_bar, fb3, cb3,
+                         vs3, work, u_n=u_n, rho_n=rho_n, a1_n=a1, a2_n=a2)
+        torch.cuda.synchronize()
+        assert torch.equal(fb3, fb) and torch.equal(cb3, cb) and torch.equal(vs3, vs)
     torch.cuda.synchronize()
     errs = {"cbar": rel(cb.cpu().numpy(), co), "vs_bar": abs(vs.item() - vo) / max(abs(vo), 1e-300)}
     if not frozen:
