@@ -126,7 +126,10 @@ __device__ __forceinline__ const T &at(const void *plane, uint32_t off) {
     return *(const T *)((const char *)plane + off);
 }
 
-template <typename T, int D, int SCHEME, int STAGE, int TX, int TY>
+// FULL: the grid is a whole number of tiles, so every lane owns a cell and
+// the store needs no lane mask (a masked store on a path that may be skipped
+// would make every later wait on the load counter drain it completely).
+template <typename T, int D, int SCHEME, int STAGE, int TX, int TY, bool FULL>
 __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, int bx, int by, int bz) {
     constexpr int NT = TX * TY;
     constexpr int AX = TX + 6;                  // a plane row length (x halo 3 + 3)
@@ -141,7 +144,7 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
     const int tx = tid % TX, ty = tid / TX;
     const int x0 = bx * TX, y0 = by * TY;
     const int gxl = x0 + tx, gyl = y0 + ty;         // own column (may be outside)
-    const bool active = gxl < g.nx && (D == 2 || gyl < g.ny);
+    const bool active = FULL || (gxl < g.nx && (D == 2 || gyl < g.ny));
     const int xw = active ? gxl : gxl % g.nx;       // wrapped column for loads
     const int yw = (D == 3) ? (active ? gyl : gyl % g.ny) : 0;
     const int col = xw + g.nx * yw;                 // < nx * ny
@@ -253,18 +256,32 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
                                   ww[3], ww[4], kap, eps);
     }
 
+    // deposit of stage 3 (D += Vs (C/6 + a1/6 + 2 a2/3) at the bottom cell),
+    // done before the march so that no load or store sits on a path of its own
+    if constexpr (STAGE == 3) {
+        if (walls && v0 == 0 && active) {
+            const double o0 = r.vs * (double)at<T>(plane(r.c, 0), colb);
+            const double o1 = r.vs * (double)at<T>(plane(r.c1, 0), colb);
+            const double o2 = r.vs * (double)aw[2];
+            r.dep[col] += o0 / 6.0 + o1 / 6.0 + 2.0 / 3.0 * o2;
+        }
+    }
+
     // prefetch registers for the lateral planes
     T pA[SA], pX[SUX], pY[(SUY > 0) ? SUY : 1];
     auto prefetch = [&](int v) {
         bool flip;
         const int vv = vidx(v, flip);
         const void *pa = plane(ain, vv), *px = plane(ux, vv), *py = plane(uy, vv);
+        // unconditional: slots without an LDS target read column 0 (in
+        // bounds) and are dropped at publication, so no load sits behind a
+        // branch
 #pragma unroll
-        for (int s = 0; s < SA; ++s) pA[s] = ldsA[s] >= 0 ? at<T>(pa, offA[s]) : (T)0;
+        for (int s = 0; s < SA; ++s) pA[s] = at<T>(pa, offA[s]);
 #pragma unroll
-        for (int s = 0; s < SUX; ++s) pX[s] = ldsX[s] >= 0 ? at<T>(px, offX[s]) : (T)0;
+        for (int s = 0; s < SUX; ++s) pX[s] = at<T>(px, offX[s]);
 #pragma unroll
-        for (int s = 0; s < SUY; ++s) pY[s] = ldsY[s] >= 0 ? at<T>(py, offY[s]) : (T)0;
+        for (int s = 0; s < SUY; ++s) pY[s] = at<T>(py, offY[s]);
     };
     prefetch(v0);
 
@@ -277,12 +294,18 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
 #pragma unroll
         for (int s = 0; s < SUY; ++s) if (ldsY[s] >= 0) sUy[ldsY[s]] = pY[s];
         __syncthreads();
-        // next plane's loads in flight while this one is computed
-        if (v + 1 < v1) prefetch(v + 1);
-        T anext, wnext;
-        load_av(v + 4, anext, wnext);
+        // loads, in the order they are consumed (the load counter drains in
+        // issue order, so waiting for one waits for all issued before it):
+        // this cell's C and the vertical pair at v+4, both used at the end of
+        // this plane, then the next lateral plane, used only after the next
+        // barrier and so in flight across this plane's face computation
+        // (past the chunk it is still a valid plane: the vertical rule maps
+        // it inside)
         T cown = (T)0;
         if (STAGE != 1) cown = at<T>(plane(r.c, v), colb);
+        T anext, wnext;
+        load_av(v + 4, anext, wnext);
+        prefetch(v + 1);
 
         // lateral faces: each thread the x face on the left of its cell and
         // (3D) the y face below it
@@ -332,12 +355,6 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
             } else if constexpr (STAGE == 2) {
                 *(T *)((char *)wplane(r.c2, v) + colb) = (T)0.75 * cown + (T)0.25 * a + (T)0.25 * L;
             } else {
-                if (walls && v == 0) {
-                    const double o0 = r.vs * (double)cown;
-                    const double o1 = r.vs * (double)at<T>(plane(r.c1, 0), colb);
-                    const double o2 = r.vs * (double)a;
-                    r.dep[col] += o0 / 6.0 + o1 / 6.0 + 2.0 / 3.0 * o2;
-                }
                 *(T *)((char *)wplane(r.c, v) + colb) = cown / (T)3 + (T)(2.0 / 3.0) * a + (T)(2.0 / 3.0) * L;
             }
         }
@@ -350,11 +367,11 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
     }
 }
 
-template <typename T, int D, int SCHEME, int STAGE, int TX, int TY>
+template <typename T, int D, int SCHEME, int STAGE, int TX, int TY, bool FULL>
 __global__ void __launch_bounds__(TX *TY) k_stage_tiled(RunDev r, TileGeom g) {
     int bx, by, bz;
     block_tile(g, bx, by, bz);
-    stage_tile<T, D, SCHEME, STAGE, TX, TY>(r, g, bx, by, bz);
+    stage_tile<T, D, SCHEME, STAGE, TX, TY, FULL>(r, g, bx, by, bz);
 }
 
 template <int D>
@@ -395,8 +412,17 @@ __global__ void __launch_bounds__(TX *TY) k_stage_batched(const RunDev *__restri
         const TileGeom g = make_geom<D>(r, chunk, TX, TY);
         const int t = w - tile_start[b];
         const int bx = t % g.gx, rest = t / g.gx;
-        stage_tile<T, D, SCHEME, STAGE, TX, TY>(r, g, bx, rest % g.gy, rest / g.gy);
+        stage_tile<T, D, SCHEME, STAGE, TX, TY, false>(r, g, bx, rest % g.gy, rest / g.gy);
     }
+}
+
+// The whole-tile form when the grid divides into tiles, else the masked one.
+template <typename T, int D, int SCHEME, int STAGE, int TX, int TY>
+void launch_stage(const RunDev &r, const TileGeom &g, unsigned nb, hipStream_t st) {
+    if (g.nx % TX == 0 && (D == 2 || g.ny % TY == 0))
+        k_stage_tiled<T, D, SCHEME, STAGE, TX, TY, true><<<nb, TX * TY, 0, st>>>(r, g);
+    else
+        k_stage_tiled<T, D, SCHEME, STAGE, TX, TY, false><<<nb, TX * TY, 0, st>>>(r, g);
 }
 
 template <typename T, int D, int SCHEME, int TX, int TY>
@@ -404,15 +430,15 @@ hipError_t stages(const RunDev &r, int chunk, hipStream_t st) {
     const TileGeom g = make_geom<D>(r, chunk, TX, TY);
     const int64_t nb = (int64_t)g.gx * g.gy * g.gz;
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
-    k_stage_tiled<T, D, SCHEME, 1, TX, TY><<<(unsigned)nb, TX * TY, 0, st>>>(r, g);
-    k_stage_tiled<T, D, SCHEME, 2, TX, TY><<<(unsigned)nb, TX * TY, 0, st>>>(r, g);
+    launch_stage<T, D, SCHEME, 1, TX, TY>(r, g, (unsigned)nb, st);
+    launch_stage<T, D, SCHEME, 2, TX, TY>(r, g, (unsigned)nb, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (r.has_s) {
         e = launch_s_update(D, sizeof(T) == 4 ? LBW_FP32_SHIFTED : LBW_FP64, r, st);
         if (e != hipSuccess) return e;
     }
-    k_stage_tiled<T, D, SCHEME, 3, TX, TY><<<(unsigned)nb, TX * TY, 0, st>>>(r, g);
+    launch_stage<T, D, SCHEME, 3, TX, TY>(r, g, (unsigned)nb, st);
     return hipGetLastError();
 }
 
@@ -424,9 +450,9 @@ hipError_t stage_slab_t(const RunDev &r, int chunk, int stage, int v_lo, int v_h
     g.bz0 = c0;
     g.gz = c1 - c0;
     const int64_t nb = (int64_t)g.gx * g.gy * g.gz;
-    if (stage == 1) k_stage_tiled<T, D, SCHEME, 1, TX, TY><<<(unsigned)nb, TX * TY, 0, st>>>(r, g);
-    else if (stage == 2) k_stage_tiled<T, D, SCHEME, 2, TX, TY><<<(unsigned)nb, TX * TY, 0, st>>>(r, g);
-    else k_stage_tiled<T, D, SCHEME, 3, TX, TY><<<(unsigned)nb, TX * TY, 0, st>>>(r, g);
+    if (stage == 1) launch_stage<T, D, SCHEME, 1, TX, TY>(r, g, (unsigned)nb, st);
+    else if (stage == 2) launch_stage<T, D, SCHEME, 2, TX, TY>(r, g, (unsigned)nb, st);
+    else launch_stage<T, D, SCHEME, 3, TX, TY>(r, g, (unsigned)nb, st);
     return hipGetLastError();
 }
 
