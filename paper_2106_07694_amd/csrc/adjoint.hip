@@ -42,6 +42,14 @@ struct AdjDev {
     int have_u, have_rho, have_stages;   // forward intermediates supplied by the caller
 };
 
+// Periodic index of a position at most three cells outside [0, n): one
+// conditional add when n >= 4, the general remainder for tiny axes.
+__device__ __forceinline__ int wrap_near(int j, int n) {
+    if (n >= 4) return j < 0 ? j + n : (j >= n ? j - n : j);
+    j %= n;
+    return j < 0 ? j + n : j;
+}
+
 template <int D>
 __device__ __forceinline__ void xyz(const RunDev &r, int64_t k, int &x, int &y, int &z) {
     x = (int)(k % r.nx);
@@ -76,75 +84,85 @@ __global__ void __launch_bounds__(256) k_adj_moments(AdjDev a) {
 // 2. transpose of the spatial operator
 // ---------------------------------------------------------------------------
 
+// Reciprocal: exact in double; the hardware reciprocal (about 1 ulp) in
+// single precision.
+template <typename T> __device__ __forceinline__ T rcp(T x) { return (T)1 / x; }
+template <> __device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // Reverse of the WENO5-JS face value for stencil values (upwind -> downwind)
-// h (fluxes) and a (smoothness input): gb = dJ/d(face value); adds dJ/dh and
-// the smoothness part of dJ/da.
+// h (fluxes) and a (smoothness input): gb = dJ/d(face value); returns dJ/dh
+// and the smoothness part of dJ/da.  Four reciprocals, no divisions.
 template <typename T>
 __device__ __forceinline__ void weno5_vjp(const T h[5], const T a[5], T eps, T gb, T hb[5], T ab[5]) {
-    const T d0 = (T)0.1, d1 = (T)0.6, d2 = (T)0.3;
-    const T q0 = ((T)2 * h[0] - (T)7 * h[1] + (T)11 * h[2]) / (T)6;
-    const T q1 = (-h[1] + (T)5 * h[2] + (T)2 * h[3]) / (T)6;
-    const T q2 = ((T)2 * h[2] + (T)5 * h[3] - h[4]) / (T)6;
+    constexpr T i6 = (T)(1.0 / 6.0);
+    const T q0 = ((T)2 * h[0] - (T)7 * h[1] + (T)11 * h[2]) * i6;
+    const T q1 = (-h[1] + (T)5 * h[2] + (T)2 * h[3]) * i6;
+    const T q2 = ((T)2 * h[2] + (T)5 * h[3] - h[4]) * i6;
     const T t0 = a[0] - (T)2 * a[1] + a[2], s0 = a[0] - (T)4 * a[1] + (T)3 * a[2];
     const T t1 = a[1] - (T)2 * a[2] + a[3], s1 = a[1] - a[3];
     const T t2 = a[2] - (T)2 * a[3] + a[4], s2 = (T)3 * a[2] - (T)4 * a[3] + a[4];
     const T e0 = eps + ((T)(13.0 / 12.0) * t0 * t0 + (T)0.25 * s0 * s0);
     const T e1 = eps + ((T)(13.0 / 12.0) * t1 * t1 + (T)0.25 * s1 * s1);
     const T e2 = eps + ((T)(13.0 / 12.0) * t2 * t2 + (T)0.25 * s2 * s2);
-    const T al0 = d0 / (e0 * e0), al1 = d1 / (e1 * e1), al2 = d2 / (e2 * e2);
-    const T S = al0 + al1 + al2;
-    const T g = (al0 * q0 + al1 * q1 + al2 * q2) / S;
+    const T ie0 = rcp<T>(e0), ie1 = rcp<T>(e1), ie2 = rcp<T>(e2);
+    const T al0 = (T)0.1 * ie0 * ie0, al1 = (T)0.6 * ie1 * ie1, al2 = (T)0.3 * ie2 * ie2;
+    const T iS = rcp<T>(al0 + al1 + al2);
+    const T g = (al0 * q0 + al1 * q1 + al2 * q2) * iS;
     // g = sum al_k q_k / S: dg/dq_k = al_k / S, dg/dal_k = (q_k - g) / S,
     // dal_k/de_k = -2 al_k / e_k (e_k = eps + smoothness indicator k)
-    const T qb0 = gb * al0 / S, qb1 = gb * al1 / S, qb2 = gb * al2 / S;
-    const T bb0 = gb * (q0 - g) / S * ((T)-2 * al0 / e0);
-    const T bb1 = gb * (q1 - g) / S * ((T)-2 * al1 / e1);
-    const T bb2 = gb * (q2 - g) / S * ((T)-2 * al2 / e2);
-    hb[0] += (T)2 / (T)6 * qb0;
-    hb[1] += -(T)7 / (T)6 * qb0 - qb1 / (T)6;
-    hb[2] += (T)11 / (T)6 * qb0 + (T)5 / (T)6 * qb1 + (T)2 / (T)6 * qb2;
-    hb[3] += (T)2 / (T)6 * qb1 + (T)5 / (T)6 * qb2;
-    hb[4] += -qb2 / (T)6;
+    const T gS = gb * iS;
+    const T qb0 = gS * al0, qb1 = gS * al1, qb2 = gS * al2;
+    const T bb0 = (q0 - g) * qb0 * ((T)-2 * ie0);
+    const T bb1 = (q1 - g) * qb1 * ((T)-2 * ie1);
+    const T bb2 = (q2 - g) * qb2 * ((T)-2 * ie2);
+    hb[0] = (T)(2.0 / 6.0) * qb0;
+    hb[1] = (T)(-7.0 / 6.0) * qb0 - i6 * qb1;
+    hb[2] = (T)(11.0 / 6.0) * qb0 + (T)(5.0 / 6.0) * qb1 + (T)(2.0 / 6.0) * qb2;
+    hb[3] = (T)(2.0 / 6.0) * qb1 + (T)(5.0 / 6.0) * qb2;
+    hb[4] = -i6 * qb2;
     // indicator = 13/12 t^2 + 1/4 s^2
     T tb = (T)(13.0 / 6.0) * t0 * bb0, sb = (T)0.5 * s0 * bb0;
-    ab[0] += tb + sb;
-    ab[1] += (T)-2 * tb - (T)4 * sb;
-    ab[2] += tb + (T)3 * sb;
+    ab[0] = tb + sb;
+    ab[1] = (T)-2 * tb - (T)4 * sb;
+    ab[2] = tb + (T)3 * sb;
     tb = (T)(13.0 / 6.0) * t1 * bb1;
     sb = (T)0.5 * s1 * bb1;
     ab[1] += tb + sb;
     ab[2] += (T)-2 * tb;
-    ab[3] += tb - sb;
+    ab[3] = tb - sb;
     tb = (T)(13.0 / 6.0) * t2 * bb2;
     sb = (T)0.5 * s2 * bb2;
     ab[2] += tb + (T)3 * sb;
     ab[3] += (T)-2 * tb - (T)4 * sb;
-    ab[4] += tb + sb;
+    ab[4] = tb + sb;
 }
 
 // Products of one face's local Jacobian with its adjoint pb, for the six
 // stencil nodes j-2..j+3 (values av, transport velocities wv):
 //   A[s] = pb * dPhi/da_s (WENO5 through h = w a and the indicators, plus the
 //          central diffusion), W[s] = pb * dPhi/dw_s.
+// The upwind side is taken with selects (the stencil is read mirrored when
+// the face velocity is negative), so lanes of a wave do not diverge.
 template <typename T>
 __device__ __forceinline__ void face_vjp(const T av[6], const T wv[6], T pb, T kap, T eps, T A[6],
                                          T W[6]) {
-    T hb[6] = {0, 0, 0, 0, 0, 0}, ab[6] = {0, 0, 0, 0, 0, 0};
     const bool pos = (wv[2] + wv[3]) >= (T)0;
-    if (pos) {
-        T h5[5] = {wv[0] * av[0], wv[1] * av[1], wv[2] * av[2], wv[3] * av[3], wv[4] * av[4]};
-        T a5[5] = {av[0], av[1], av[2], av[3], av[4]};
-        T hb5[5] = {0, 0, 0, 0, 0}, ab5[5] = {0, 0, 0, 0, 0};
-        weno5_vjp<T>(h5, a5, eps, pb, hb5, ab5);
+    T h5[5], a5[5], hb5[5], ab5[5];
 #pragma unroll
-        for (int s = 0; s < 5; ++s) { hb[s] += hb5[s]; ab[s] += ab5[s]; }
-    } else {
-        T h5[5] = {wv[5] * av[5], wv[4] * av[4], wv[3] * av[3], wv[2] * av[2], wv[1] * av[1]};
-        T a5[5] = {av[5], av[4], av[3], av[2], av[1]};
-        T hb5[5] = {0, 0, 0, 0, 0}, ab5[5] = {0, 0, 0, 0, 0};
-        weno5_vjp<T>(h5, a5, eps, pb, hb5, ab5);
+    for (int s = 0; s < 5; ++s) {
+        const T aa = pos ? av[s] : av[5 - s];
+        const T ww = pos ? wv[s] : wv[5 - s];
+        a5[s] = aa;
+        h5[s] = ww * aa;
+    }
+    weno5_vjp<T>(h5, a5, eps, pb, hb5, ab5);
+    T hb[6], ab[6];
 #pragma unroll
-        for (int s = 0; s < 5; ++s) { hb[5 - s] += hb5[s]; ab[5 - s] += ab5[s]; }
+    for (int s = 0; s < 6; ++s) {
+        const T hp = s < 5 ? hb5[s] : (T)0, hn = s > 0 ? hb5[5 - s] : (T)0;
+        const T ap = s < 5 ? ab5[s] : (T)0, an = s > 0 ? ab5[5 - s] : (T)0;
+        hb[s] = pos ? hp : hn;
+        ab[s] = pos ? ap : an;
     }
     ab[3] += -kap * pb;   // diffusion -kappa (a_{j+1} - a_j)
     ab[2] += kap * pb;
@@ -187,7 +205,7 @@ __global__ void __launch_bounds__(256) k_adj_face(AdjDev A, const T *__restrict_
         for (int s = 0; s < 6; ++s) {
             int jj = j + s - 2;
             bool ghost = false;
-            if (!walls) { jj %= n; if (jj < 0) jj += n; }
+            if (!walls) jj = wrap_near(jj, n);
             else if (jj < 0) { jj = -1 - jj; ghost = true; }
             else if (jj >= n) { jj = 2 * n - 1 - jj; ghost = true; }
             const int64_t kk = k + (int64_t)(jj - j) * stride;
@@ -320,8 +338,7 @@ __global__ void __launch_bounds__(256) k_adj_gather(AdjDev A) {
                 if (walls) {
                     if (jf < 0 || jf > n - 2) continue;
                 } else {
-                    jf %= n;
-                    if (jf < 0) jf += n;
+                    jf = wrap_near(jf, n);
                 }
                 const int64_t kf = k + (int64_t)(jf - m) * stride;
                 const int64_t idx = ((int64_t)d * 6 + s) * r.N + kf;
