@@ -52,10 +52,7 @@ __device__ __forceinline__ int wrap_near(int j, int n) {
 
 template <int D>
 __device__ __forceinline__ void xyz(const RunDev &r, int64_t k, int &x, int &y, int &z) {
-    x = (int)(k % r.nx);
-    const int64_t t = k / r.nx;
-    if constexpr (D == 2) { y = (int)t; z = 0; }
-    else { y = (int)(t % r.ny); z = (int)(t / r.ny); }
+    coords<D>(r, k, x, y, z);
 }
 
 // ---------------------------------------------------------------------------
@@ -289,11 +286,12 @@ __device__ __forceinline__ T collide_reverse_node(const AdjDev &A, int64_t k, in
     }
     // u = (m + F/2) / rho, m = sum f c, rho = sum f (+1 when shifted)
     T mb[3];
+    const T irho = rcp<T>(rho);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        mb[d] = ub[d] / rho;
-        Fb[d] += (T)0.5 * ub[d] / rho;
-        rb -= ub[d] * u[d] / rho;
+        mb[d] = ub[d] * irho;
+        Fb[d] += (T)0.5 * mb[d];
+        rb -= mb[d] * u[d];
     }
 #pragma unroll
     for (int i = 0; i < Q; ++i)
@@ -372,7 +370,7 @@ __global__ void __launch_bounds__(256) k_adj_gather(AdjDev A) {
     T *cb = (T *)A.cbar;
     if constexpr (STAGE == 3) {
         T a2b = (T)(2.0 / 3.0) * cbn[k] + abar;
-        T cbv = cbn[k] / (T)3;
+        T cbv = cbn[k] * (T)(1.0 / 3.0);
         if (bottom) {
             // D+ = D + vs (C/6 + a1/6 + 2 a2/3)
             a2b += (T)(2.0 / 3.0 * r.vs * db);

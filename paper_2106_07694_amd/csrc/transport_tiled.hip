@@ -355,7 +355,7 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
             } else if constexpr (STAGE == 2) {
                 *(T *)((char *)wplane(r.c2, v) + colb) = (T)0.75 * cown + (T)0.25 * a + (T)0.25 * L;
             } else {
-                *(T *)((char *)wplane(r.c, v) + colb) = cown / (T)3 + (T)(2.0 / 3.0) * a + (T)(2.0 / 3.0) * L;
+                *(T *)((char *)wplane(r.c, v) + colb) = (T)(1.0 / 3.0) * cown + (T)(2.0 / 3.0) * a + (T)(2.0 / 3.0) * L;
             }
         }
         fbelow = fabove;
