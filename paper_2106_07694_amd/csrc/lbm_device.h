@@ -63,25 +63,8 @@ __device__ __forceinline__ T load_canonical(const RunDev &r, const T *__restrict
     return v;
 }
 
-// Grid coordinates of node k.  Runs of up to 2^32 nodes (all practical
-// sizes) use 32-bit unsigned division, which is several times cheaper than
-// the 64-bit kind; the branch is uniform.
 template <int D>
 __device__ __forceinline__ void coords(const RunDev &r, int64_t k, int &x, int &y, int &z) {
-    if (r.N <= (int64_t)0xffffffffu) {
-        const uint32_t kk = (uint32_t)k, nx = (uint32_t)r.nx;
-        const uint32_t t = kk / nx;
-        x = (int)(kk - t * nx);
-        if constexpr (D == 2) {
-            y = (int)t;
-            z = 0;
-        } else {
-            const uint32_t ny = (uint32_t)r.ny, zz = t / ny;
-            y = (int)(t - zz * ny);
-            z = (int)zz;
-        }
-        return;
-    }
     x = (int)(k % r.nx);
     const int64_t t = k / r.nx;
     if constexpr (D == 2) {
