@@ -160,6 +160,52 @@ def run_sweep(steps: int, warmup: int) -> dict:
             "speedup": ms_seq / ms_batched, "launch": launch}
 
 
+def run_precision(nsteps: int, marks=(1000, 5000, 10000, 20000)) -> dict:
+    """Form (1) against the plain FP64 step on the same GPU: the 2D two-scalar
+    workload run in FP32 with shifted populations and in FP64 from the same
+    seeded state; relative L2 differences of u, C and the per-column deposit
+    (and of the total deposited mass) at several step counts.  The FP64 GPU
+    path is the reference here because it equals the FP64 oracle to 1e-12 on
+    every size the oracle can step; at this size the oracle would need tens
+    of minutes on the host."""
+    import numpy as np
+    import torch
+    from paper_2106_07694_amd import autotune, lbw, workloads as W
+
+    wl = W.C2
+    marks = [m for m in marks if m <= nsteps] or [nsteps]
+    runs = {}
+    for prec in ("fp64", "fp32_shifted"):
+        cfg = lbw.RunConfig.from_workload(wl.replace(precision=prec))
+        sol = lbw.Solver(cfg)
+        tuned = autotune.lookup(wl.name)
+        if tuned:
+            sol.set_launch(**tuned)
+        sol.setup_workload(wl)
+        snaps, done = {}, 0
+        for m in marks:
+            sol.step(m - done)
+            done = m
+            torch.cuda.synchronize()
+            snaps[m] = {k: sol.field(k).double().cpu().numpy() for k in ("u", "c", "deposit")}
+            snaps[m]["deposited"] = float(sol.reduce(lbw.DEPOSIT)[0])
+        sol.close()
+        runs[prec] = snaps
+    rel = lambda a, b: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    out = {"workload": wl.name, "reference": "fp64 (GPU)", "steps": marks, "l2_rel": {}}
+    for m in marks:
+        a, b = runs["fp32_shifted"][m], runs["fp64"][m]
+        out["l2_rel"][str(m)] = {
+            "u": rel(a["u"], b["u"]), "c": rel(a["c"], b["c"]),
+            "deposit": rel(a["deposit"], b["deposit"]),
+            # the front has not reached the floor here: the deposit is the sum
+            # of the seeded +-1e-3 noise of the clear layer, near zero, so the
+            # totals are given with their absolute difference
+            "deposited_mass_fp64": b["deposited"], "deposited_mass_fp32": a["deposited"],
+            "deposited_mass_abs_diff": abs(a["deposited"] - b["deposited"])}
+    return out
+
+
 def run_adjoint(nsteps: int) -> dict:
     """Gradient of the deposited mass for the 512x1024 FP32 run: the plain
     forward, the checkpointed forward (a checkpoint every ~sqrt(N) steps) and
@@ -255,6 +301,9 @@ def main() -> int:
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=5000)
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the FP32-vs-FP64 error report of the 2D workload")
+    ap.add_argument("--precision-steps", type=int, default=20000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a known-size copy kernel (profiler counter calibration)")
     args = ap.parse_args()
@@ -296,6 +345,12 @@ def main() -> int:
         adj = run_adjoint(args.adjoint_steps)
         print(f"[bench] adjoint: forward {adj['forward_s']:.3f} s, backward {adj['backward_s']:.3f} s "
               f"(ratio {adj['adjoint_forward_ratio']:.2f})", file=sys.stderr, flush=True)
+    prec = None
+    if not args.no_precision:
+        prec = run_precision(args.precision_steps)
+        last = prec["l2_rel"][str(prec["steps"][-1])]
+        print(f"[bench] fp32 vs fp64 after {prec['steps'][-1]} steps: u {last['u']:.2e}, "
+              f"C {last['c']:.2e}, deposit {last['deposit']:.2e}", file=sys.stderr, flush=True)
     copy = calibrate_copy() if args.calibrate_copy else None
     cpu = None
     if not args.no_cpu_baseline:
@@ -328,6 +383,7 @@ def main() -> int:
         "also": also,
         "sweep": sweep,
         "adjoint": adj,
+        "fp32_vs_fp64": prec,
         "copy_calibration": copy,
     }
     print(json.dumps(line))

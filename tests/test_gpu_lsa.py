@@ -1,0 +1,39 @@
+"""The early-time growth rate on the GPU path (FP64 and the FP32 shifted
+production form) against linear stability analysis: the same run as the
+oracle's growth-rate test (tests/test_oracle_lsa.py), stepped through the C
+ABI, with the LSA eigenvalue of the run's own mean profile."""
+import numpy as np
+import pytest
+
+from paper_2106_07694_amd import lbw
+from lsa import fitted_rate, layer_setup, lsa_rate_for_profile, mode_amplitude
+
+pytestmark = pytest.mark.gpu
+TAU, GP, KAPPA, WIDTH, ETA = 0.6, 5e-5, 1e-4, 3.0, 0.02
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_shifted"])
+def test_gpu_growth_rate_matches_lsa(precision):
+    nx, ny, nsteps, chunk, vs = 64, 160, 4000, 100, 5e-4
+    cfg = lbw.RunConfig(lattice=9, nx=nx, ny=ny, precision=precision, tau=TAU, gp_c=GP,
+                        kappa_c=KAPPA, vs=vs)
+    c, rho, k = layer_setup(nx, ny, GP, WIDTH, ETA)
+    sol = lbw.Solver(cfg)
+    sol.set_field("c", c)
+    sol.init_equilibrium(rho=rho)
+    ts, amps, profs = [], [], {}
+    for it in range(nsteps // chunk):
+        sol.step(chunk)
+        t = (it + 1) * chunk
+        u = sol.field("u").double().cpu().numpy()
+        ts.append(t)
+        amps.append(mode_amplitude(u[1, 0]))
+        profs[t] = sol.field("c").double().cpu().numpy()[0].mean(axis=1)
+    sol.close()
+    ts, amps = np.array(ts), np.array(amps)
+    win = (ts >= 2500) & (ts <= 3500)
+    sim = fitted_rate(ts[win], amps[win])
+    pred = lsa_rate_for_profile(profs[3000], k, (TAU - 0.5) / 3, KAPPA, GP, vs)
+    print(f"\n{precision}: growth rate {sim:.5e}, LSA {pred:.5e}, ratio {sim / pred:.4f}")
+    assert amps[win][-1] > 2 * amps[win][0]
+    assert abs(sim / pred - 1) < 0.01, (sim, pred)
