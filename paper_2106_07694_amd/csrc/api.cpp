@@ -385,10 +385,13 @@ int enqueue_step(lbw_handle *h) {
     int sp = span_open(h, LBW_PHASE_COLLIDE_STREAM, h->stream);
     if (h->fluid_mode == LBW_FLUID_LBM) {
         hipError_t e;
-        if (h->nbatch > 1)
+        if (h->nbatch > 1) {
+            int64_t nodes = 0;
+            for (const auto &rr : h->run) nodes += rr.N;
             e = lbw::launch_collide_stream_batched(h->q, h->precision, h->d_runs, h->d_blk, h->nbatch,
                                                    h->sflip ? 1 : 0, h->odd, h->launch.lbm_block,
-                                                   h->grid_lbm, h->stream);
+                                                   h->grid_lbm, nodes, h->stream);
+        }
         else
             e = lbw::launch_collide_stream(h->q, h->precision, current(h, 0), h->odd,
                                            h->launch.lbm_block, h->stream);

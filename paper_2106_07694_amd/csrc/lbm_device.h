@@ -41,6 +41,20 @@ __device__ __forceinline__ int64_t displaced(const RunDev &r, int x, int y, int 
     }
 }
 
+// Population accesses of the collide-stream kernels: NT marks them
+// non-temporal (streamed past the caches), which pays when the populations
+// are far larger than the last-level cache and costs when they fit in it.
+template <typename T, bool NT>
+__device__ __forceinline__ T pop_load(const T *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <typename T, bool NT>
+__device__ __forceinline__ void pop_store(T *p, T v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 // 6 w_i (c_i . u_top): momentum a moving top wall hands to a reflected
 // population (half-way bounce-back with a wall velocity).
 template <int Q>
@@ -51,14 +65,14 @@ __device__ __forceinline__ double lid_term(const RunDev &r, int i) {
 
 // Canonical pre-collision population f_i at node k when the buffer holds the
 // state after an even-step kernel (odd = true) or after an odd-step kernel.
-template <int Q, typename T>
+template <int Q, typename T, bool NT = false>
 __device__ __forceinline__ T load_canonical(const RunDev &r, const T *__restrict__ f, int i,
                                             int64_t k, int x, int y, int z, bool odd) {
     using L = Lattice<Q>;
-    if (!odd) return f[(int64_t)i * r.N + k];
+    if (!odd) return pop_load<T, NT>(&f[(int64_t)i * r.N + k]);
     const int64_t src = displaced<L::D>(r, x, y, z, -L::cx[i], -L::cy[i], -L::cz[i]);
-    if (src >= 0) return f[(int64_t)L::opp[i] * r.N + src];
-    T v = f[(int64_t)i * r.N + k];
+    if (src >= 0) return pop_load<T, NT>(&f[(int64_t)L::opp[i] * r.N + src]);
+    T v = pop_load<T, NT>(&f[(int64_t)i * r.N + k]);
     if (src == -2) v += (T)lid_term<Q>(r, i);  // f_i = f*_opp(i) + 6 w_i c_i.u_top
     return v;
 }

@@ -100,9 +100,11 @@ TileShape resolve_tile_shape(int dim, const lbw_launch &l);
 int64_t transport_tiles(int dim, const RunDev &r, const lbw_launch &l);
 hipError_t launch_transport_batched(int dim, int precision, const BatchArgs &b, const lbw_launch &l,
                                     hipStream_t st);
+// nodes: total nodes of the batch (chooses the cache policy of the
+// population accesses)
 hipError_t launch_collide_stream_batched(int q, int precision, const RunDev *runs, const int *blk_start,
                                          int nbatch, int sflip, bool odd, int block, int grid,
-                                         hipStream_t st);
+                                         int64_t nodes, hipStream_t st);
 hipError_t launch_rk_stages12(int dim, int precision, const RunDev &r, hipStream_t st);
 size_t adjoint_work_bytes(int dim, int precision, int64_t N);
 hipError_t launch_adjoint(int q, int precision, const RunDev &r, bool frozen, const void *f_n,
