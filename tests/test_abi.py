@@ -68,6 +68,7 @@ def test_valid_config_creates():
     (dict(weno_eps=0.0), "weno_eps"),
     (dict(u_top=(2.0, 0, 0)), "lid"),
     (dict(nx=0), "grid"),
+    (dict(lattice=19, nx=32768, ny=16384, nz=6), "horizontal plane"),
 ])
 def test_invalid_configs_rejected(bad, frag):
     rc, msg = _create([lbw.RunConfig(**bad)])

@@ -61,6 +61,7 @@ def _rng_fields(cfg, seed):
     dict(nx=1, ny=6),                                               # degenerate lateral, minimal height
     dict(nx=64, ny=40, has_s=True, kappa_s=1e-3, gp_s=-2e-4),
     dict(nx=40, ny=24, precision="fp64_shifted", has_s=True, kappa_s=1e-3, gp_s=2e-4),
+    dict(nx=16, ny=12, vs=0.0, kappa_c=0.0, gp_c=0.0),             # uncoupled: no settling, diffusion, buoyancy
 ])
 def test_d2q9_fp64_variants(kw):
     base = dict(tau=0.6, vs=2e-3, kappa_c=2e-3, gp_c=5e-4)
@@ -75,6 +76,8 @@ def test_d2q9_fp64_variants(kw):
     dict(nx=9, ny=7, nz=11, vert_periodic=True),
     dict(nx=8, ny=6, nz=12, u_top=(0.02, -0.01, 0), body_force=(1e-4, 0, 2e-5)),
     dict(nx=10, ny=6, nz=8, precision="fp64_shifted", has_s=True, kappa_s=1e-3, gp_s=1e-4),
+    dict(nx=1, ny=3, nz=6),                                         # degenerate lateral axes, minimal height
+    dict(nx=5, ny=1, nz=9, vert_periodic=True),
 ])
 def test_d3q19_fp64_variants(kw):
     base = dict(lattice=19, tau=0.55, vs=2e-3, kappa_c=2e-3, gp_c=5e-4)
