@@ -305,52 +305,16 @@ __device__ __forceinline__ T collide_reverse_node(const AdjDev &A, int64_t k, in
 // ---------------------------------------------------------------------------
 // Node-wise gather of the face products.  STAGE selects the RK stage being
 // reversed (3, 2, 1 in that order) and how the result combines.
+// The per-node end of a reversed RK stage, given the node's gathered face
+// products (abar, the velocity parts ubs and the settling part vsp): the
+// absorbing bottom face, the deposit update, the RK combination and, after the
+// last stage, the collision and moments in reverse.
 template <int Q, typename T, bool SH, int STAGE>
-__global__ void __launch_bounds__(256) k_adj_gather(AdjDev A) {
+__device__ __forceinline__ void gather_finish(const AdjDev &A, int64_t k, int x, int y, int z, T abar,
+                                              const T ubs[3], double vsp) {
     constexpr int D = Lattice<Q>::D;
     const RunDev &r = A.r;
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= r.N) return;
-    int x, y, z;
-    xyz<D>(r, k, x, y, z);
-    const T *fa = (const T *)A.faceA, *fw = (const T *)A.faceW;
     T *ub = (T *)A.ubar;
-    double vsp = 0.0;
-    T abar = 0;
-    T ubs[3] = {0, 0, 0};
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-        const bool vert = (d == D - 1);
-        const bool walls = vert && !r.vper;
-        const int m = d == 0 ? x : (d == 1 ? y : z);
-        const int n = d == 0 ? r.nx : (d == 1 ? r.ny : r.nz);
-        const int64_t stride = d == 0 ? 1 : (d == 1 ? (int64_t)r.nx : (int64_t)r.nx * r.ny);
-        // images of node m as seen by stencils: itself, and beyond each wall
-        const int nimg = walls ? 3 : 1;
-        for (int im = 0; im < nimg; ++im) {
-            const int p = im == 0 ? m : (im == 1 ? -1 - m : 2 * n - 1 - m);
-            const bool ghost = im != 0;
-#pragma unroll
-            for (int s = 0; s < 6; ++s) {
-                int jf = p - s + 2;              // face whose slot s reads position p
-                if (walls) {
-                    if (jf < 0 || jf > n - 2) continue;
-                } else {
-                    jf = wrap_near(jf, n);
-                }
-                const int64_t kf = k + (int64_t)(jf - m) * stride;
-                const int64_t idx = ((int64_t)d * 6 + s) * r.N + kf;
-                abar += fa[idx];
-                const T wb = fw[idx];
-                if (vert) {
-                    ubs[d] += ghost ? -wb : wb;
-                    vsp -= (double)wb;
-                } else {
-                    ubs[d] += wb;
-                }
-            }
-        }
-    }
     // bottom wall face: L_0 contains -vs a_0
     const int v = (D == 2) ? y : z;
     const bool bottom = !r.vper && v == 0;
@@ -405,6 +369,224 @@ __global__ void __launch_bounds__(256) k_adj_gather(AdjDev A) {
             for (int d = 0; d < D; ++d) ut[d] = ub[(int64_t)d * r.N + k] + ubs[d];
             cb[k] = cbv + collide_reverse_node<Q, T, SH>(A, k, x, y, z, ut);
         }
+    }
+}
+
+template <int Q, typename T, bool SH, int STAGE>
+__global__ void __launch_bounds__(256) k_adj_gather(AdjDev A) {
+    constexpr int D = Lattice<Q>::D;
+    const RunDev &r = A.r;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= r.N) return;
+    int x, y, z;
+    xyz<D>(r, k, x, y, z);
+    const T *fa = (const T *)A.faceA, *fw = (const T *)A.faceW;
+    double vsp = 0.0;
+    T abar = 0;
+    T ubs[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const bool vert = (d == D - 1);
+        const bool walls = vert && !r.vper;
+        const int m = d == 0 ? x : (d == 1 ? y : z);
+        const int n = d == 0 ? r.nx : (d == 1 ? r.ny : r.nz);
+        const int64_t stride = d == 0 ? 1 : (d == 1 ? (int64_t)r.nx : (int64_t)r.nx * r.ny);
+        // images of node m as seen by stencils: itself, and beyond each wall
+        const int nimg = walls ? 3 : 1;
+        for (int im = 0; im < nimg; ++im) {
+            const int p = im == 0 ? m : (im == 1 ? -1 - m : 2 * n - 1 - m);
+            const bool ghost = im != 0;
+#pragma unroll
+            for (int s = 0; s < 6; ++s) {
+                int jf = p - s + 2;              // face whose slot s reads position p
+                if (walls) {
+                    if (jf < 0 || jf > n - 2) continue;
+                } else {
+                    jf = wrap_near(jf, n);
+                }
+                const int64_t kf = k + (int64_t)(jf - m) * stride;
+                const int64_t idx = ((int64_t)d * 6 + s) * r.N + kf;
+                abar += fa[idx];
+                const T wb = fw[idx];
+                if (vert) {
+                    ubs[d] += ghost ? -wb : wb;
+                    vsp -= (double)wb;
+                } else {
+                    ubs[d] += wb;
+                }
+            }
+        }
+    }
+    gather_finish<Q, T, SH, STAGE>(A, k, x, y, z, abar, ubs, vsp);
+}
+
+// ---------------------------------------------------------------------------
+// 2D: one reversed RK stage in one kernel.  A block owns a TX x TY tile of
+// nodes and keeps everything between the stage's inputs and its per-node
+// results in LDS: the stage input a, the transport velocity and the face
+// adjoints lam with the halos the tile's face stencils reach (wall images
+// already mirrored, with the sign of the vertical velocity flipped); the
+// products of every x face the tile's nodes read (five faces beyond the
+// tile), gathered per node; then the same for the y faces.  Faces are
+// evaluated with the same face_vjp on the same values as the two-kernel form
+// and gathered in the same order, so the results are identical bit for bit;
+// the workspace round trip of the face products disappears, at the price of
+// recomputing the five faces per row and column that neighbouring tiles also
+// need.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int wrap_any(int j, int n) {
+    j %= n;
+    return j < 0 ? j + n : j;
+}
+
+template <typename T, bool SH, int STAGE, int TX, int TY>
+__global__ void __launch_bounds__(256) k_adj_stage2d(AdjDev A, const T *__restrict__ a,
+                                                     const T *__restrict__ lam, T scale) {
+    constexpr int NT = 256, PER = TX * TY / NT;
+    static_assert(TX * TY % NT == 0, "tile must be a multiple of the block");
+    constexpr int HX = TX + 10, LX = TX + 6, NFX = TX + 5;   // x: a/w row, lam row, faces per row
+    constexpr int HY = TY + 10, LY = TY + 6, NFY = TY + 5;   // y: the same per column
+    constexpr int NP = (NFX * TY > NFY * TX) ? NFX * TY : NFY * TX;
+    __shared__ T sAx[TY * HX], sWx[TY * HX], sLx[TY * LX];
+    __shared__ T sAy[HY * TX], sWy[HY * TX], sLy[LY * TX];
+    __shared__ T sPA[6 * NP], sPW[6 * NP];
+
+    const RunDev &r = A.r;
+    const int nx = r.nx, ny = r.ny;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int tid = threadIdx.x;
+    const bool walls = !r.vper;
+    const T *u = (const T *)(A.frozen ? r.u : A.u);
+    const T *ux = u, *uy = u + r.N;
+    const T vs = (T)r.vs, kap = (T)r.kappa_c, eps = (T)r.eps;
+    // vertical position p of a stencil or lam row -> stored row (mirrored
+    // beyond walls; rows no face of the tile reads are clamped into range)
+    auto vrow = [&](int p, bool &ghost) {
+        ghost = false;
+        if (!walls) return wrap_any(p, ny);
+        if (p < 0) { p = -1 - p; ghost = true; }
+        else if (p >= ny) { p = 2 * ny - 1 - p; ghost = true; }
+        return p < 0 ? 0 : (p >= ny ? ny - 1 : p);
+    };
+
+    // stage the inputs
+    for (int i = tid; i < TY * HX; i += NT) {
+        const int ly = i / HX, c = i % HX;
+        const int gy = min(y0 + ly, ny - 1);
+        const int64_t k = (int64_t)wrap_any(x0 - 5 + c, nx) + (int64_t)nx * gy;
+        sAx[i] = a[k];
+        sWx[i] = ux[k];
+    }
+    for (int i = tid; i < TY * LX; i += NT) {
+        const int ly = i / LX, c = i % LX;
+        const int gy = min(y0 + ly, ny - 1);
+        sLx[i] = lam[(int64_t)wrap_any(x0 - 3 + c, nx) + (int64_t)nx * gy];
+    }
+    for (int i = tid; i < HY * TX; i += NT) {
+        const int ry = i / TX, lx = i % TX;
+        bool ghost;
+        const int gy = vrow(y0 - 5 + ry, ghost);
+        const int64_t k = (int64_t)wrap_any(x0 + lx, nx) + (int64_t)nx * gy;
+        sAy[i] = a[k];
+        const T uu = uy[k];
+        sWy[i] = (ghost ? -uu : uu) - vs;
+    }
+    for (int i = tid; i < LY * TX; i += NT) {
+        const int ry = i / TX, lx = i % TX;
+        bool ghost;
+        const int gy = vrow(y0 - 3 + ry, ghost);
+        sLy[i] = lam[(int64_t)wrap_any(x0 + lx, nx) + (int64_t)nx * gy];
+    }
+    __syncthreads();
+
+    // x faces j = x0 - 3 + i of every tile row (the x axis is periodic)
+    for (int f = tid; f < NFX * TY; f += NT) {
+        const int ly = f / NFX, i = f % NFX;
+        T av[6], wv[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            av[q] = sAx[ly * HX + i + q];
+            wv[q] = sWx[ly * HX + i + q];
+        }
+        const T pb = scale * (sLx[ly * LX + i + 1] - sLx[ly * LX + i]);
+        T fa6[6], fw6[6];
+        face_vjp<T>(av, wv, pb, kap, eps, fa6, fw6);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            sPA[q * NP + f] = fa6[q];
+            sPW[q * NP + f] = fw6[q];
+        }
+    }
+    __syncthreads();
+    T abar[PER], ubx[PER], uby[PER];
+    double vsp[PER];
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        const int node = tid + e * NT, lx = node % TX, ly = node / TX;
+        abar[e] = 0;
+        ubx[e] = 0;
+        uby[e] = 0;
+        vsp[e] = 0.0;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {            // face x - q + 2 reads this node at slot q
+            const int f = ly * NFX + lx + 5 - q;
+            abar[e] += sPA[q * NP + f];
+            ubx[e] += sPW[q * NP + f];
+        }
+    }
+    __syncthreads();
+
+    // y faces j = y0 - 3 + i of every tile column (faces exist for
+    // 0 <= j <= ny - 2 with walls; periodic positions wrap)
+    for (int f = tid; f < NFY * TX; f += NT) {
+        const int iy = f / TX, lx = f % TX;
+        const int j = y0 - 3 + iy;
+        if (walls && (j < 0 || j > ny - 2)) continue;   // never gathered
+        T av[6], wv[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            av[q] = sAy[(iy + q) * TX + lx];
+            wv[q] = sWy[(iy + q) * TX + lx];
+        }
+        const T pb = scale * (sLy[(iy + 1) * TX + lx] - sLy[iy * TX + lx]);
+        T fa6[6], fw6[6];
+        face_vjp<T>(av, wv, pb, kap, eps, fa6, fw6);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            sPA[q * NP + f] = fa6[q];
+            sPW[q * NP + f] = fw6[q];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        const int node = tid + e * NT, lx = node % TX, ly = node / TX;
+        const int m = y0 + ly;
+        // only nodes of the grid gather: for a row beyond the top of a ragged
+        // tile the image above the wall could name a face outside the tile's
+        // range.  For a grid node every face it reads lies in [y0 - 3, y0 + TY + 1]:
+        // its own faces m - 3 .. m + 2, the bottom images (faces 0, 1, read only
+        // when m <= 1, so y0 = 0) and the top images (faces >= ny - 3 >= m - 2,
+        // read only when m >= ny - 3).
+        if (x0 + lx >= nx || m >= ny) continue;
+        const int nimg = walls ? 3 : 1;
+        for (int im = 0; im < nimg; ++im) {
+            const int p = im == 0 ? m : (im == 1 ? -1 - m : 2 * ny - 1 - m);
+            const bool ghost = im != 0;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                const int jf = p - q + 2;        // face whose slot q reads position p
+                if (walls && (jf < 0 || jf > ny - 2)) continue;
+                const int f = (jf - (y0 - 3)) * TX + lx;
+                abar[e] += sPA[q * NP + f];
+                const T wb = sPW[q * NP + f];
+                uby[e] += ghost ? -wb : wb;
+                vsp[e] -= (double)wb;
+            }
+        }
+        const int64_t k = (int64_t)(x0 + lx) + (int64_t)nx * m;
+        const T ubs[3] = {ubx[e], uby[e], (T)0};
+        gather_finish<9, T, SH, STAGE>(A, k, x0 + lx, m, 0, abar[e], ubs, vsp[e]);
     }
 }
 
@@ -466,12 +648,21 @@ hipError_t adjoint_t(const AdjDev &A, const lbw_launch &l, hipStream_t st) {
         if (e == hipSuccess) e = launch_stage_slab(D, prec, fr, lt, 2, 0, nv, st);
         if (e != hipSuccess) return e;
     }
-    k_adj_face<T, D><<<grid, block, 0, st>>>(A, (const T *)A.a2, (const T *)A.cbar_next, (T)(2.0 / 3.0));
-    k_adj_gather<Q, T, SH, 3><<<grid, block, 0, st>>>(A);
-    k_adj_face<T, D><<<grid, block, 0, st>>>(A, (const T *)A.a1, (const T *)A.abar2, (T)0.25);
-    k_adj_gather<Q, T, SH, 2><<<grid, block, 0, st>>>(A);
-    k_adj_face<T, D><<<grid, block, 0, st>>>(A, (const T *)A.c_n, (const T *)A.abar1, (T)1);
-    k_adj_gather<Q, T, SH, 1><<<grid, block, 0, st>>>(A);
+    if (D == 2 && l.variant != 1) {
+        // one kernel per reversed stage, face products kept in LDS
+        constexpr int TX = sizeof(T) == 4 ? 32 : 16, TY = sizeof(T) == 4 ? 8 : 16;
+        const dim3 tg((unsigned)((A.r.nx + TX - 1) / TX), (unsigned)((A.r.ny + TY - 1) / TY));
+        k_adj_stage2d<T, SH, 3, TX, TY><<<tg, 256, 0, st>>>(A, (const T *)A.a2, (const T *)A.cbar_next, (T)(2.0 / 3.0));
+        k_adj_stage2d<T, SH, 2, TX, TY><<<tg, 256, 0, st>>>(A, (const T *)A.a1, (const T *)A.abar2, (T)0.25);
+        k_adj_stage2d<T, SH, 1, TX, TY><<<tg, 256, 0, st>>>(A, (const T *)A.c_n, (const T *)A.abar1, (T)1);
+    } else {
+        k_adj_face<T, D><<<grid, block, 0, st>>>(A, (const T *)A.a2, (const T *)A.cbar_next, (T)(2.0 / 3.0));
+        k_adj_gather<Q, T, SH, 3><<<grid, block, 0, st>>>(A);
+        k_adj_face<T, D><<<grid, block, 0, st>>>(A, (const T *)A.a1, (const T *)A.abar2, (T)0.25);
+        k_adj_gather<Q, T, SH, 2><<<grid, block, 0, st>>>(A);
+        k_adj_face<T, D><<<grid, block, 0, st>>>(A, (const T *)A.c_n, (const T *)A.abar1, (T)1);
+        k_adj_gather<Q, T, SH, 1><<<grid, block, 0, st>>>(A);
+    }
     if (A.vs_bar) {
         k_adj_vs_partial<<<kReduceBlocks, 256, 0, st>>>(A.vs_part, A.r.N, A.partials);
         k_adj_vs_final<<<1, 256, 0, st>>>(A.partials, kReduceBlocks, A.vs_bar);
