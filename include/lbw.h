@@ -125,7 +125,7 @@ typedef struct {
 typedef struct {
     int32_t lbm_block;     /* threads per block of the collide-stream kernel */
     int32_t tile_x;        /* transport tile width: 32, 64, 128 (3D) or
-                              64, 128, 256 (2D) columns */
+                              64, 128, 256, 512 (2D) columns */
     int32_t tile_y;        /* transport chunk: vertical planes per block */
     int32_t variant;       /* 0 tiled transport (LDS, marching) after the
                               collide-stream kernel; 1 plain transport (one
@@ -139,6 +139,10 @@ typedef struct {
                               steps (needs a non-null stream; the graph is
                               runtime-owned and rebuilt after lbw_set_launch) */
     int32_t slabs;         /* pipelined variant: number of vertical slabs */
+    int32_t tile_rows;     /* transport tile rows (3D): 0 = 256 / tile_x
+                              (32x8, 64x4, 128x2 with 256 threads), or 16 with
+                              tile_x 32 and 8 with tile_x 64 (512 threads);
+                              2D tiles are one row (0 or 1) */
 } lbw_launch;
 
 /* Library ABI version (LBW_ABI_VERSION). */

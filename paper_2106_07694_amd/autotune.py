@@ -19,7 +19,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuned.json")
 
 LBM_BLOCKS = (128, 256, 512, 1024)
-TILES = {2: (64, 128, 256), 3: (32, 64, 128)}
+# transport tiles (columns, rows): 256 threads, and 512-thread tiles
+TILES = {2: ((64, 1), (128, 1), (256, 1), (512, 1)),
+         3: ((32, 8), (64, 4), (128, 2), (32, 16), (64, 8))}
 CHUNKS = {2: (8, 16, 32, 64, 128), 3: (16, 32, 64, 128)}
 
 
@@ -49,15 +51,16 @@ def tune(cfgs, setup, steps: int = 20, graph: bool = False, log=print) -> dict:
         if ms < best_lbm_ms:
             best_lbm, best_lbm_ms = blk, ms
     best_tile, best_tr_ms = None, float("inf")
-    for tx in TILES[dim]:
+    for tx, rows in TILES[dim]:
         for ch in CHUNKS[dim]:
-            sol.set_launch(lbm_block=best_lbm, tile_x=tx, tile_y=ch)
+            sol.set_launch(lbm_block=best_lbm, tile_x=tx, tile_y=ch, tile_rows=rows)
             ms = _time_phases(sol, steps)["transport_ms"] / steps
-            log(f"  tile_x={tx} chunk={ch}: {ms * 1e3:.1f} us/step")
+            log(f"  tile {tx}x{rows} chunk={ch}: {ms * 1e3:.1f} us/step")
             if ms < best_tr_ms:
-                best_tile, best_tr_ms = (tx, ch), ms
+                best_tile, best_tr_ms = (tx, rows, ch), ms
     sol.close()
-    out = {"lbm_block": best_lbm, "tile_x": best_tile[0], "tile_y": best_tile[1]}
+    out = {"lbm_block": best_lbm, "tile_x": best_tile[0], "tile_rows": best_tile[1],
+           "tile_y": best_tile[2]}
     if graph:
         out["graph"] = 1
     out["_ms"] = {"collide_stream": best_lbm_ms, "transport": best_tr_ms}

@@ -23,7 +23,7 @@ struct lbw_handle {
     std::vector<lbw::RunDev> run;
     int64_t steps = 0;
     bool odd = false;  // next collide-stream kernel is the odd one of the pair
-    lbw_launch launch{256, 0, 0, 0, 0, 0};
+    lbw_launch launch{256, 0, 0, 0, 0, 0, 0};
     // timing: spans (phase, start, end) drawn from a pool of events
     bool timing = false;
     struct Span {
@@ -314,9 +314,19 @@ int lbw_set_launch(lbw_handle *h, const lbw_launch *l) {
     }
     if (l->tile_x) {
         const bool ok = h->dim == 3 ? (l->tile_x == 32 || l->tile_x == 64 || l->tile_x == 128)
-                                    : (l->tile_x == 64 || l->tile_x == 128 || l->tile_x == 256);
-        if (!ok) return fail(LBW_ERR_INVAL, "tile_x must be 32, 64 or 128 (3D) or 64, 128 or 256 (2D)");
+                                    : (l->tile_x == 64 || l->tile_x == 128 || l->tile_x == 256 ||
+                                       l->tile_x == 512);
+        if (!ok) return fail(LBW_ERR_INVAL, "tile_x must be 32, 64 or 128 (3D) or 64, 128, 256 or 512 (2D)");
         n.tile_x = l->tile_x;
+    }
+    {
+        const int tx = n.tile_x ? n.tile_x : (h->dim == 3 ? 32 : 256);
+        const int tr = l->tile_rows;
+        const bool ok = tr == 0 || (h->dim == 2 ? tr == 1
+                                                : (tr == 256 / tx || (tx == 32 && tr == 16) ||
+                                                   (tx == 64 && tr == 8)));
+        if (!ok) return fail(LBW_ERR_INVAL, "tile_rows must be 0, 256 / tile_x, 16 (tile_x 32) or 8 (tile_x 64) in 3D, 0 or 1 in 2D");
+        n.tile_rows = tr;
     }
     if (l->tile_y) {
         if (l->tile_y < 1 || l->tile_y > 4096) return fail(LBW_ERR_INVAL, "tile_y must lie in [1, 4096]");

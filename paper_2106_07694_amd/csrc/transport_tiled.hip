@@ -456,19 +456,34 @@ hipError_t stage_slab_t(const RunDev &r, int chunk, int stage, int v_lo, int v_h
     return hipGetLastError();
 }
 
+// Calls fn(integral_constant TX, integral_constant TY) for the tile shape:
+// 3D 32x8, 64x4, 128x2 (256 threads), 32x16, 64x8 (512 threads); 2D one row
+// of 64, 128, 256 or 512 columns.
+template <int D, typename F>
+hipError_t with_tile(const TileShape &sh, F &&fn) {
+    using std::integral_constant;
+    if constexpr (D == 3) {
+        if (sh.tx == 64 && sh.ty == 8) return fn(integral_constant<int, 64>{}, integral_constant<int, 8>{});
+        if (sh.tx == 32 && sh.ty == 16) return fn(integral_constant<int, 32>{}, integral_constant<int, 16>{});
+        if (sh.tx == 64) return fn(integral_constant<int, 64>{}, integral_constant<int, 4>{});
+        if (sh.tx == 128) return fn(integral_constant<int, 128>{}, integral_constant<int, 2>{});
+        return fn(integral_constant<int, 32>{}, integral_constant<int, 8>{});
+    } else {
+        if (sh.tx == 64) return fn(integral_constant<int, 64>{}, integral_constant<int, 1>{});
+        if (sh.tx == 128) return fn(integral_constant<int, 128>{}, integral_constant<int, 1>{});
+        if (sh.tx == 512) return fn(integral_constant<int, 512>{}, integral_constant<int, 1>{});
+        return fn(integral_constant<int, 256>{}, integral_constant<int, 1>{});
+    }
+}
+
 template <typename T, int D, int SCHEME>
 hipError_t stage_slab_shape(const RunDev &r, const lbw_launch &l, int stage, int v_lo, int v_hi,
                             hipStream_t st) {
     const TileShape sh = resolve_tile_shape(D, l);
-    if constexpr (D == 3) {
-        if (sh.tx == 64) return stage_slab_t<T, D, SCHEME, 64, 4>(r, sh.chunk, stage, v_lo, v_hi, st);
-        if (sh.tx == 128) return stage_slab_t<T, D, SCHEME, 128, 2>(r, sh.chunk, stage, v_lo, v_hi, st);
-        return stage_slab_t<T, D, SCHEME, 32, 8>(r, sh.chunk, stage, v_lo, v_hi, st);
-    } else {
-        if (sh.tx == 64) return stage_slab_t<T, D, SCHEME, 64, 1>(r, sh.chunk, stage, v_lo, v_hi, st);
-        if (sh.tx == 128) return stage_slab_t<T, D, SCHEME, 128, 1>(r, sh.chunk, stage, v_lo, v_hi, st);
-        return stage_slab_t<T, D, SCHEME, 256, 1>(r, sh.chunk, stage, v_lo, v_hi, st);
-    }
+    return with_tile<D>(sh, [&](auto tx, auto ty) {
+        return stage_slab_t<T, D, SCHEME, decltype(tx)::value, decltype(ty)::value>(r, sh.chunk, stage, v_lo,
+                                                                                  v_hi, st);
+    });
 }
 
 template <typename T, int D>
@@ -503,26 +518,11 @@ hipError_t stages_batched(const BatchArgs &a, hipStream_t st) {
 template <typename T, int D, int SCHEME>
 hipError_t stages_shape(const RunDev &r, const lbw_launch &l, hipStream_t st, const BatchArgs *batch) {
     const TileShape sh = resolve_tile_shape(D, l);
-    if (batch) {
-        if constexpr (D == 3) {
-            if (sh.tx == 64) return stages_batched<T, D, SCHEME, 64, 4>(*batch, st);
-            if (sh.tx == 128) return stages_batched<T, D, SCHEME, 128, 2>(*batch, st);
-            return stages_batched<T, D, SCHEME, 32, 8>(*batch, st);
-        } else {
-            if (sh.tx == 64) return stages_batched<T, D, SCHEME, 64, 1>(*batch, st);
-            if (sh.tx == 128) return stages_batched<T, D, SCHEME, 128, 1>(*batch, st);
-            return stages_batched<T, D, SCHEME, 256, 1>(*batch, st);
-        }
-    }
-    if constexpr (D == 3) {
-        if (sh.tx == 64) return stages<T, D, SCHEME, 64, 4>(r, sh.chunk, st);
-        if (sh.tx == 128) return stages<T, D, SCHEME, 128, 2>(r, sh.chunk, st);
-        return stages<T, D, SCHEME, 32, 8>(r, sh.chunk, st);
-    } else {
-        if (sh.tx == 64) return stages<T, D, SCHEME, 64, 1>(r, sh.chunk, st);
-        if (sh.tx == 128) return stages<T, D, SCHEME, 128, 1>(r, sh.chunk, st);
-        return stages<T, D, SCHEME, 256, 1>(r, sh.chunk, st);
-    }
+    return with_tile<D>(sh, [&](auto tx, auto ty) {
+        constexpr int TX = decltype(tx)::value, TY = decltype(ty)::value;
+        return batch ? stages_batched<T, D, SCHEME, TX, TY>(*batch, st)
+                     : stages<T, D, SCHEME, TX, TY>(r, sh.chunk, st);
+    });
 }
 
 template <typename T, int D>
@@ -542,8 +542,9 @@ TileShape resolve_tile_shape(int dim, const lbw_launch &l) {
     if (dim == 3) {
         s.tx = (l.tile_x == 64 || l.tile_x == 128) ? l.tile_x : 32;
         s.ty = 256 / s.tx;
+        if ((s.tx == 32 && l.tile_rows == 16) || (s.tx == 64 && l.tile_rows == 8)) s.ty = l.tile_rows;
     } else {
-        s.tx = (l.tile_x == 64 || l.tile_x == 128) ? l.tile_x : 256;
+        s.tx = (l.tile_x == 64 || l.tile_x == 128 || l.tile_x == 512) ? l.tile_x : 256;
         s.ty = 1;
     }
     s.chunk = l.tile_y > 0 ? l.tile_y : (dim == 3 ? 64 : 32);

@@ -65,7 +65,8 @@ class CBuffers(ctypes.Structure):
 class CLaunch(ctypes.Structure):
     _fields_ = [("lbm_block", ctypes.c_int32), ("tile_x", ctypes.c_int32),
                 ("tile_y", ctypes.c_int32), ("variant", ctypes.c_int32),
-                ("graph", ctypes.c_int32), ("slabs", ctypes.c_int32)]
+                ("graph", ctypes.c_int32), ("slabs", ctypes.c_int32),
+                ("tile_rows", ctypes.c_int32)]
 
 
 _lib = None
@@ -314,15 +315,16 @@ class Solver:
         check(self._lib.lbw_steps_done(self._h, ctypes.byref(v)))
         return v.value
 
-    def set_launch(self, lbm_block=0, tile_x=0, tile_y=0, variant=0, graph=0, slabs=0):
-        lc = CLaunch(lbm_block, tile_x, tile_y, variant, graph, slabs)
+    def set_launch(self, lbm_block=0, tile_x=0, tile_y=0, variant=0, graph=0, slabs=0, tile_rows=0):
+        lc = CLaunch(lbm_block, tile_x, tile_y, variant, graph, slabs, tile_rows)
         check(self._lib.lbw_set_launch(self._h, ctypes.byref(lc)))
 
     def get_launch(self) -> dict:
         lc = CLaunch()
         check(self._lib.lbw_get_launch(self._h, ctypes.byref(lc)))
         return {"lbm_block": lc.lbm_block, "tile_x": lc.tile_x, "tile_y": lc.tile_y,
-                "variant": lc.variant, "graph": lc.graph, "slabs": lc.slabs}
+                "variant": lc.variant, "graph": lc.graph, "slabs": lc.slabs,
+                "tile_rows": lc.tile_rows}
 
     def reduce(self, what) -> np.ndarray:
         out = (ctypes.c_double * self.nbatch)()

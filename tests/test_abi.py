@@ -117,7 +117,7 @@ def test_launch_shape_validation():
     h = ctypes.c_void_p()
     assert lib.lbw_create(ctypes.byref(c), ctypes.byref(b), 1, None, ctypes.byref(h)) == 0
     try:
-        ok = lbw.CLaunch(512, 128, 16, 1, 1, 0)
+        ok = lbw.CLaunch(512, 128, 16, 1, 1, 0, 0)
         assert lib.lbw_set_launch(h, ctypes.byref(ok)) == 0
         got = lbw.CLaunch()
         assert lib.lbw_get_launch(h, ctypes.byref(got)) == 0
@@ -125,10 +125,12 @@ def test_launch_shape_validation():
         assert lib.lbw_set_launch(h, ctypes.byref(lbw.CLaunch(0, 0, 0, 2, 0, 6))) == 0
         lib.lbw_get_launch(h, ctypes.byref(got))
         assert (got.variant, got.slabs) == (2, 6)
+        # 2D: one-row tiles of 64..512 columns
+        assert lib.lbw_set_launch(h, ctypes.byref(lbw.CLaunch(0, 512, 0, 0, 0, 0, 1))) == 0
         for bad in (lbw.CLaunch(100, 0, 0, 0, 0, 0), lbw.CLaunch(2048, 0, 0, 0, 0, 0),
                     lbw.CLaunch(0, 96, 0, 0, 0, 0), lbw.CLaunch(0, 32, 0, 0, 0, 0),
                     lbw.CLaunch(0, 0, 0, 3, 0, 0), lbw.CLaunch(0, 0, 0, 0, 3, 0),
-                    lbw.CLaunch(0, 0, 0, 2, 0, 65)):
+                    lbw.CLaunch(0, 0, 0, 2, 0, 65), lbw.CLaunch(0, 256, 0, 0, 0, 0, 2)):
             assert lib.lbw_set_launch(h, ctypes.byref(bad)) == lbw.ERR_INVAL
         assert lib.lbw_step(h, -1) == lbw.ERR_INVAL
         v = ctypes.c_int64(-1)
@@ -162,6 +164,24 @@ def test_rebind_accepts_only_per_step_outputs():
             assert lib.lbw_rebind(h, 3, lbw.FIELD_STAGE1, p) == lbw.ERR_INVAL
         finally:
             lib.lbw_destroy(h)
+
+
+def test_tile_rows_validation_3d():
+    lib = lbw.load()
+    cfg = lbw.RunConfig(lattice=19, nx=8, ny=8, nz=16)
+    c, b = cfg.to_c(), _fake_buffers(cfg)
+    h = ctypes.c_void_p()
+    assert lib.lbw_create(ctypes.byref(c), ctypes.byref(b), 1, None, ctypes.byref(h)) == 0
+    try:
+        for tx, rows in ((32, 0), (32, 8), (32, 16), (64, 4), (64, 8), (128, 2), (128, 0)):
+            assert lib.lbw_set_launch(h, ctypes.byref(lbw.CLaunch(0, tx, 0, 0, 0, 0, rows))) == 0
+            got = lbw.CLaunch()
+            lib.lbw_get_launch(h, ctypes.byref(got))
+            assert (got.tile_x, got.tile_rows) == (tx, rows)
+        for tx, rows in ((32, 4), (64, 16), (128, 8), (32, 32), (32, 1)):
+            assert lib.lbw_set_launch(h, ctypes.byref(lbw.CLaunch(0, tx, 0, 0, 0, 0, rows))) == lbw.ERR_INVAL
+    finally:
+        lib.lbw_destroy(h)
 
 
 def test_batched_needs_scratch():

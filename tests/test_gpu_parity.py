@@ -124,6 +124,7 @@ def test_launch_shapes_give_identical_bits(lbm_block):
     dict(tile_x=64, tile_y=7),
     dict(tile_x=128, tile_y=5),
     dict(tile_x=256, tile_y=1000),
+    dict(tile_x=512, tile_y=6),
     dict(variant=2, tile_y=4, slabs=3),
     dict(variant=2, tile_y=8, slabs=64),
 ])
@@ -140,6 +141,8 @@ def test_2d_transport_launches(launch):
     dict(tile_x=32, tile_y=5),
     dict(tile_x=64, tile_y=3),
     dict(tile_x=128, tile_y=64),
+    dict(tile_x=32, tile_rows=16, tile_y=5),
+    dict(tile_x=64, tile_rows=8, tile_y=3),
     dict(variant=2, tile_y=2, slabs=4),
     dict(variant=2, tile_y=3, slabs=2),
 ])
