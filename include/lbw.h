@@ -69,7 +69,7 @@ extern "C" {
 enum {
     LBW_OK = 0,
     LBW_ERR_INVAL = -1,       /* bad argument or configuration */
-    LBW_ERR_UNSUPPORTED = -2, /* valid request this build does not provide */
+    LBW_ERR_UNSUPPORTED = -2, /* valid request the library does not provide */
     LBW_ERR_HIP = -3,         /* a HIP runtime call failed */
     LBW_ERR_NONFINITE = -4    /* a reduction found NaN or Inf */
 };
