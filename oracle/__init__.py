@@ -16,4 +16,6 @@ from .oracle import (  # noqa: F401
     sums,
     library_path,
     adjoint_step,
+    front_height,
+    mass_below,
 )

@@ -779,6 +779,48 @@ int orc_adjoint_step(const orc_cfg *cfg, const double *f_n, const double *c_n,
     return 0;
 }
 
+int orc_front_height(const orc_cfg *cfg, const double *c, double thr, double *out)
+{
+    grid_t g;
+    long col, plane;
+    int v, nv;
+    if (setup(cfg, &g)) return -1;
+    nv = g.n[g.dim - 1];
+    plane = g.ncol;                          /* cells per horizontal plane */
+    for (col = 0; col < g.ncol; col++) {
+        double h = (double)nv;               /* no cell reaches thr */
+        for (v = 0; v < nv; v++) {
+            double cv = c[col + (long)v * plane];
+            if (cv >= thr) {
+                if (v == 0) {
+                    h = 0.0;
+                } else {
+                    double cb = c[col + (long)(v - 1) * plane];
+                    /* crossing between the centres of cells v-1 and v */
+                    h = (double)(v - 1) + 0.5 + (thr - cb) / (cv - cb);
+                }
+                break;
+            }
+        }
+        out[col] = h;
+    }
+    return 0;
+}
+
+int orc_mass_below(const orc_cfg *cfg, const double *c, int plane, double *out)
+{
+    grid_t g;
+    long k, n;
+    int nv;
+    if (setup(cfg, &g)) return -1;
+    nv = g.n[g.dim - 1];
+    if (plane < 0 || plane > nv) return -1;
+    n = (long)plane * g.ncol;
+    *out = 0.0;
+    for (k = 0; k < n; k++) *out += c[k];
+    return 0;
+}
+
 int orc_sums(const orc_cfg *cfg, const double *f, const double *c,
              const double *s, const double *dep, double *out)
 {

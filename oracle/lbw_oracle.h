@@ -82,6 +82,20 @@ int orc_adjoint_step(const orc_cfg *cfg, const double *f_n, const double *c_n,
 int orc_sums(const orc_cfg *cfg, const double *f, const double *c,
              const double *s, const double *dep, double *out);
 
+/* Front of the particle field per bottom column (section "Comparison of
+ * model results with predictions from linear stability analysis"): the
+ * lowest height where C reaches thr, measured from the bottom wall (cell v
+ * has its centre at height v + 1/2), linear between the two cells that
+ * straddle thr; 0 if the bottom cell already holds C >= thr, the domain
+ * height if no cell does.  out[ncol]. */
+int orc_front_height(const orc_cfg *cfg, const double *c, double thr, double *out);
+
+/* Particle mass (sum of C) in the planes below plane index `plane`, i.e. in
+ * the cells with vertical index v < plane (the mass whose change gives the
+ * flux through a horizontal plane, eq. for J in section "Particle mass flux,
+ * particle concentration in the lower layer and accumulation rate"). */
+int orc_mass_below(const orc_cfg *cfg, const double *c, int plane, double *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -114,6 +114,8 @@ def _load():
         lib.orc_run.argtypes = [cfgp, P, P, P, P, P, P, ctypes.c_int32]
         lib.orc_sums.argtypes = [cfgp, P, P, P, P, P]
         lib.orc_adjoint_step.argtypes = [cfgp, P, P, P, P, P, ctypes.c_double, P, P, P]
+        lib.orc_front_height.argtypes = [cfgp, P, ctypes.c_double, P]
+        lib.orc_mass_below.argtypes = [cfgp, P, ctypes.c_int32, P]
         _lib = lib
     return _lib
 
@@ -187,6 +189,26 @@ def run(cfg: OracleConfig, f, c, s=None, dep=None, u_in=None, nsteps=1, want_u=F
     _check(lib.orc_run(ctypes.byref(cc), fp, _ptr(c), _ptr(s), _ptr(dep), _ptr(u_in),
                        _ptr(u_out), int(nsteps)), "run")
     return f, c, s, dep, u_out
+
+
+def front_height(cfg: OracleConfig, c, thr: float) -> np.ndarray:
+    """Lowest height per bottom column where C reaches thr (see the C header)."""
+    lib = _load()
+    c = np.ascontiguousarray(c, np.float64)
+    out = np.zeros(cfg.ncol, np.float64)
+    cc = cfg._c()
+    _check(lib.orc_front_height(ctypes.byref(cc), _ptr(c), float(thr), _ptr(out)), "front_height")
+    return out
+
+
+def mass_below(cfg: OracleConfig, c, plane: int) -> float:
+    """Sum of C over the cells with vertical index < plane."""
+    lib = _load()
+    c = np.ascontiguousarray(c, np.float64)
+    out = np.zeros(1, np.float64)
+    cc = cfg._c()
+    _check(lib.orc_mass_below(ctypes.byref(cc), _ptr(c), int(plane), _ptr(out)), "mass_below")
+    return float(out[0])
 
 
 def sums(cfg: OracleConfig, f, c, s=None, dep=None):
