@@ -41,10 +41,17 @@ def _alg_bytes(wl) -> dict:
 
 
 def _kernel_hash() -> str:
+    """Hash of what the collide-stream kernel is built from: its two source
+    files and the run descriptor it reads (the RunDev struct)."""
+    csrc = os.path.join(ROOT, "paper_2106_07694_amd", "csrc")
     h = hashlib.sha256()
-    for name in ("lbm.hip", "lbm_device.h", "lbw_internal.h"):
-        with open(os.path.join(ROOT, "paper_2106_07694_amd", "csrc", name), "rb") as fh:
+    for name in ("lbm.hip", "lbm_device.h"):
+        with open(os.path.join(csrc, name), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(csrc, "lbw_internal.h")) as fh:
+        text = fh.read()
+    start = text.index("struct RunDev {")
+    h.update(text[start:text.index("};", start)].encode())
     return h.hexdigest()[:16]
 
 
