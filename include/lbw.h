@@ -227,6 +227,32 @@ int lbw_rebind(lbw_handle *h, int32_t run, int32_t field, void *ptr);
  * LBW_ERR_NONFINITE if any sum is NaN or Inf (the values are still written). */
 int lbw_reduce(lbw_handle *h, int32_t what, double *out_host);
 
+/* Particle mass below a horizontal plane, per run, into out_host[nbatch]:
+ * the FP64 sum of C over the cells whose vertical index v is below `plane`
+ * (the first plane * ncol nodes, planes being the slowest axis).  Its change
+ * over an interval divided by the plane's area and the interval gives the
+ * particle mass flux J through that plane (section "Particle mass flux,
+ * particle concentration in the lower layer and accumulation rate"); plane
+ * = nv gives the LBW_MASS_C total.  Same deterministic reduction as
+ * lbw_reduce; synchronises the stream.  LBW_ERR_INVAL if plane is outside
+ * [0, nv] for any run of the batch (nv = ny in 2D, nz in 3D);
+ * LBW_ERR_NONFINITE as lbw_reduce. */
+int lbw_mass_below(lbw_handle *h, int32_t plane, double *out_host);
+
+/* Height of the particle front in every bottom column of run `run`, into the
+ * caller's device array out_dev[ncol] (FP64; ncol = nx in 2D, nx*ny in 3D,
+ * column index x + nx*y): scanning each column upward from the bottom wall,
+ * the height where C first reaches `threshold`, measured from the wall with
+ * the centre of cell v at v + 1/2 and linear between the two cells that
+ * straddle the threshold; 0 if the bottom cell already reaches it and the
+ * domain height nv if no cell does.  Its lateral Fourier modes give the
+ * finger growth of section "Comparison of model results with predictions
+ * from linear stability analysis".  C is read in the run's storage type
+ * and compared in FP64.  Enqueued on the handle's stream, no
+ * synchronisation.  LBW_ERR_INVAL for a bad run, NULL out_dev or a
+ * non-finite threshold. */
+int lbw_front_height(lbw_handle *h, int32_t run, double threshold, double *out_dev);
+
 /* Device workspace lbw_adjoint_step needs for run `run` (bytes). */
 int lbw_adjoint_work_bytes(const lbw_handle *h, int32_t run, size_t *out_bytes);
 

@@ -744,12 +744,11 @@ int lbw_import(lbw_handle *h, int32_t run, int32_t field, const void *src) {
     return e == hipSuccess ? LBW_OK : hip_fail(e, "import");
 }
 
-int lbw_reduce(lbw_handle *h, int32_t what, double *out_host) {
-    if (!h || !out_host) return fail(LBW_ERR_INVAL, "NULL argument");
-    if (what < LBW_MASS_C || what > LBW_DEPOSIT) return fail(LBW_ERR_INVAL, "unknown reduction %d", what);
-    if (what == LBW_MASS_S && !h->has_s) return fail(LBW_ERR_INVAL, "run has no S");
-    if (what == LBW_MASS_FLUID && h->fluid_mode != LBW_FLUID_LBM)
-        return fail(LBW_ERR_INVAL, "frozen fluid has no populations");
+namespace {
+
+// The sums of lbw_reduce, over the cells below a horizontal plane of each run
+// (plane >= 0) or over all cells (-1).
+int reduce_impl(lbw_handle *h, int32_t what, double *out_host, int plane) {
     size_t need = 0;
     lbw_scratch_bytes(h->cfg.data(), h->nbatch, &need);
     const lbw_buffers &b0 = h->buf[0];
@@ -759,7 +758,7 @@ int lbw_reduce(lbw_handle *h, int32_t what, double *out_host) {
     std::vector<lbw::RunDev> cur(h->nbatch);
     for (int b = 0; b < h->nbatch; ++b) cur[b] = current(h, b);
     hipError_t e = lbw::launch_reduce(h->q, h->precision, cur.data(), h->nbatch, what, h->odd,
-                                      scratch, h->stream);
+                                      scratch, h->stream, plane);
     if (e != hipSuccess) return hip_fail(e, "reduce launch");
     e = hipMemcpyAsync(out_host, (char *)b0.scratch + scratch_layout(h->nbatch).out,
                        sizeof(double) * h->nbatch, hipMemcpyDeviceToHost, h->stream);
@@ -769,6 +768,37 @@ int lbw_reduce(lbw_handle *h, int32_t what, double *out_host) {
     for (int b = 0; b < h->nbatch; ++b)
         if (!std::isfinite(out_host[b])) return fail(LBW_ERR_NONFINITE, "run %d: sum is not finite", b);
     return LBW_OK;
+}
+
+}  // namespace
+
+int lbw_reduce(lbw_handle *h, int32_t what, double *out_host) {
+    if (!h || !out_host) return fail(LBW_ERR_INVAL, "NULL argument");
+    if (what < LBW_MASS_C || what > LBW_DEPOSIT) return fail(LBW_ERR_INVAL, "unknown reduction %d", what);
+    if (what == LBW_MASS_S && !h->has_s) return fail(LBW_ERR_INVAL, "run has no S");
+    if (what == LBW_MASS_FLUID && h->fluid_mode != LBW_FLUID_LBM)
+        return fail(LBW_ERR_INVAL, "frozen fluid has no populations");
+    return reduce_impl(h, what, out_host, -1);
+}
+
+int lbw_mass_below(lbw_handle *h, int32_t plane, double *out_host) {
+    if (!h || !out_host) return fail(LBW_ERR_INVAL, "NULL argument");
+    for (int b = 0; b < h->nbatch; ++b) {
+        const lbw::RunDev &r = h->run[b];
+        const int nv = h->dim == 2 ? r.ny : r.nz;
+        if (plane < 0 || plane > nv)
+            return fail(LBW_ERR_INVAL, "run %d: plane %d outside [0, %d]", b, plane, nv);
+    }
+    return reduce_impl(h, LBW_MASS_C, out_host, plane);
+}
+
+int lbw_front_height(lbw_handle *h, int32_t run, double threshold, double *out_dev) {
+    int rc = check_run(h, run);
+    if (rc) return rc;
+    if (!out_dev) return fail(LBW_ERR_INVAL, "NULL output");
+    if (!std::isfinite(threshold)) return fail(LBW_ERR_INVAL, "threshold must be finite");
+    hipError_t e = lbw::launch_front_height(h->precision, h->run[run], h->dim, threshold, out_dev, h->stream);
+    return e == hipSuccess ? LBW_OK : hip_fail(e, "front-height launch");
 }
 
 }  // extern "C"

@@ -113,8 +113,13 @@ hipError_t launch_adjoint(int q, int precision, const RunDev &r, bool frozen, co
                           const void *fbar_next, const void *cbar_next,
                           double dep_bar, void *fbar, void *cbar, double *vs_bar, void *work,
                           const lbw_launch &l, hipStream_t st);
+// plane >= 0: MASS_C / MASS_S sum only the cells below that horizontal plane
+// (the first plane * ncol nodes of each run); -1: all nodes.
 hipError_t launch_reduce(int q, int precision, const RunDev *runs, int nbatch, int what,
-                         bool odd, double *scratch, hipStream_t st);
+                         bool odd, double *scratch, hipStream_t st, int plane = -1);
+// Front of the particle field per bottom column into out (device, ncol).
+hipError_t launch_front_height(int precision, const RunDev &r, int dim, double thr, double *out,
+                               hipStream_t st);
 
 constexpr int kReduceBlocks = 256;  // partial sums per run
 

@@ -5,6 +5,11 @@
 // with shuffles and across waves through LDS, and writes one partial; a
 // single block per run then adds the partials in a fixed order.  The result
 // does not depend on timing: the same inputs give the same bits.
+//
+// Also the in-situ diagnostics of the paper's analysis: the mass below a
+// horizontal plane (a prefix of the node order, whose change over time is the
+// particle mass flux through the plane) and the front of the particle field
+// per column (lowest height where C reaches a threshold).
 #include "lbm_device.h"
 
 namespace lbw {
@@ -27,9 +32,11 @@ __device__ __forceinline__ double block_sum(double acc) {
 
 template <int Q, typename T>
 __global__ void __launch_bounds__(256) k_partial(RunDev r, int what, bool odd, bool shifted,
-                                                 double *__restrict__ part) {
+                                                 int plane, double *__restrict__ part) {
     double acc = 0.0;
-    const int64_t n = (what == LBW_DEPOSIT) ? r.ncol : r.N;
+    int64_t n = (what == LBW_DEPOSIT) ? r.ncol : r.N;
+    if (plane >= 0 && (what == LBW_MASS_C || what == LBW_MASS_S) && (int64_t)plane * r.ncol < n)
+        n = (int64_t)plane * r.ncol;   // planes are the slowest axis
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
         if (what == LBW_MASS_C) {
@@ -63,24 +70,59 @@ __global__ void __launch_bounds__(256) k_final(const double *__restrict__ part, 
 
 template <int Q, typename T>
 hipError_t reduce_t(const RunDev *runs, int nbatch, int what, bool odd, bool shifted,
-                    double *scratch, hipStream_t st) {
+                    double *scratch, hipStream_t st, int plane) {
     for (int b = 0; b < nbatch; ++b)
-        k_partial<Q, T><<<kReduceBlocks, 256, 0, st>>>(runs[b], what, odd, shifted,
+        k_partial<Q, T><<<kReduceBlocks, 256, 0, st>>>(runs[b], what, odd, shifted, plane,
                                                         scratch + (int64_t)b * kReduceBlocks);
     k_final<<<nbatch, 256, 0, st>>>(scratch, kReduceBlocks, scratch + (int64_t)nbatch * kReduceBlocks);
     return hipGetLastError();
 }
 
+// One thread per bottom column scans upward for the first cell with
+// C >= thr (consecutive threads read consecutive cells of a plane) and
+// interpolates linearly between the centres of that cell and the one below,
+// in double: height (v - 1) + 1/2 + (thr - C_{v-1}) / (C_v - C_{v-1}) from the
+// bottom wall; 0 if the bottom cell already holds C >= thr, the domain height
+// if no cell does.
+template <typename T>
+__global__ void __launch_bounds__(256) k_front_height(const T *__restrict__ c, int64_t ncol, int nv,
+                                                      double thr, double *__restrict__ out) {
+    const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= ncol) return;
+    double h = (double)nv;
+    double below = 0.0;
+    for (int v = 0; v < nv; ++v) {
+        const double cv = (double)c[col + (int64_t)v * ncol];
+        if (cv >= thr) {
+            h = v == 0 ? 0.0 : (double)(v - 1) + 0.5 + (thr - below) / (cv - below);
+            break;
+        }
+        below = cv;
+    }
+    out[col] = h;
+}
+
 }  // namespace
 
 hipError_t launch_reduce(int q, int precision, const RunDev *runs, int nbatch, int what, bool odd,
-                         double *scratch, hipStream_t st) {
+                         double *scratch, hipStream_t st, int plane) {
     const bool sh = precision != LBW_FP64;
     if (precision == LBW_FP32_SHIFTED)
-        return q == 9 ? reduce_t<9, float>(runs, nbatch, what, odd, sh, scratch, st)
-                      : reduce_t<19, float>(runs, nbatch, what, odd, sh, scratch, st);
-    return q == 9 ? reduce_t<9, double>(runs, nbatch, what, odd, sh, scratch, st)
-                  : reduce_t<19, double>(runs, nbatch, what, odd, sh, scratch, st);
+        return q == 9 ? reduce_t<9, float>(runs, nbatch, what, odd, sh, scratch, st, plane)
+                      : reduce_t<19, float>(runs, nbatch, what, odd, sh, scratch, st, plane);
+    return q == 9 ? reduce_t<9, double>(runs, nbatch, what, odd, sh, scratch, st, plane)
+                  : reduce_t<19, double>(runs, nbatch, what, odd, sh, scratch, st, plane);
+}
+
+hipError_t launch_front_height(int precision, const RunDev &r, int dim, double thr, double *out,
+                               hipStream_t st) {
+    const int nv = dim == 2 ? r.ny : r.nz;
+    const unsigned grid = (unsigned)((r.ncol + 255) / 256);
+    if (precision == LBW_FP32_SHIFTED)
+        k_front_height<float><<<grid, 256, 0, st>>>((const float *)r.c, r.ncol, nv, thr, out);
+    else
+        k_front_height<double><<<grid, 256, 0, st>>>((const double *)r.c, r.ncol, nv, thr, out);
+    return hipGetLastError();
 }
 
 }  // namespace lbw

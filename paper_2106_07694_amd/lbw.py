@@ -30,7 +30,8 @@ SCHEMES = {"weno5": WENO5, "weno3": WENO3, "upwind1": UPWIND1}
 EXPORTED = ("lbw_version", "lbw_last_error", "lbw_scratch_bytes", "lbw_create", "lbw_destroy",
             "lbw_set_launch", "lbw_get_launch", "lbw_init_equilibrium", "lbw_step",
             "lbw_steps_done", "lbw_export", "lbw_import", "lbw_rebind", "lbw_reduce", "lbw_timing_begin",
-            "lbw_timing_end", "lbw_adjoint_work_bytes", "lbw_adjoint_step")
+            "lbw_timing_end", "lbw_adjoint_work_bytes", "lbw_adjoint_step", "lbw_mass_below",
+            "lbw_front_height")
 
 
 class LbwError(RuntimeError):
@@ -97,6 +98,8 @@ def load() -> ctypes.CDLL:
     lib.lbw_import.argtypes = [P, I32, I32, P]
     lib.lbw_rebind.argtypes = [P, I32, I32, P]
     lib.lbw_reduce.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double)]
+    lib.lbw_mass_below.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double)]
+    lib.lbw_front_height.argtypes = [P, I32, ctypes.c_double, P]
     lib.lbw_adjoint_work_bytes.argtypes = [P, I32, ctypes.POINTER(ctypes.c_size_t)]
     lib.lbw_adjoint_step.argtypes = [P, I32, P, P, P, P, P, P, P, P, ctypes.c_double, P, P, P, P,
                                      ctypes.c_size_t]
@@ -330,6 +333,28 @@ class Solver:
         out = (ctypes.c_double * self.nbatch)()
         check(self._lib.lbw_reduce(self._h, int(what), out))
         return np.array(out[:], dtype=np.float64)
+
+    def mass_below(self, plane: int) -> np.ndarray:
+        """Sum of C below vertical plane index `plane`, per run (FP64)."""
+        out = (ctypes.c_double * self.nbatch)()
+        check(self._lib.lbw_mass_below(self._h, int(plane), out))
+        return np.array(out[:], dtype=np.float64)
+
+    def front_height(self, threshold: float, run: int = 0, out=None):
+        """Front height per bottom column as an FP64 device tensor of the
+        lateral shape (written on the solver's stream)."""
+        import torch
+
+        cfg = self.cfgs[run]
+        lateral = (cfg.nx,) if cfg.dim == 2 else (cfg.ny, cfg.nx)
+        if out is None:
+            with torch.cuda.stream(self.stream):
+                out = torch.empty(lateral, dtype=torch.float64, device=self.device)
+        if out.dtype != torch.float64 or not out.is_contiguous() or out.numel() != int(np.prod(lateral)):
+            raise ValueError("out must be a contiguous float64 tensor of the lateral shape")
+        check(self._lib.lbw_front_height(self._h, int(run), float(threshold),
+                                         ctypes.c_void_p(out.data_ptr())))
+        return out
 
     def timing_begin(self):
         check(self._lib.lbw_timing_begin(self._h))

@@ -1,0 +1,190 @@
+"""GPU parity of the in-situ diagnostics (front height per column, particle
+mass below a horizontal plane) against the FP64 oracle on the same seeded
+fields.
+
+The front height compares C with the threshold in FP64 and interpolates in
+the same operation order on both sides (no products, so no fused
+multiply-add can differ): it must agree bit for bit.  The mass below a plane
+is the same deterministic tree reduction as the mass sums against the
+oracle's sequential sum: 1e-12 relative.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2106_07694_amd import lbw, workloads as W
+
+from parity import as_input, oracle_cfg, run_oracle
+
+pytestmark = pytest.mark.gpu
+TOL64 = 1e-12
+
+
+def _solver_with(cfg, c):
+    sol = lbw.Solver(cfg)
+    sol.set_field("c", c)
+    if cfg.fluid_mode == lbw.FLUID_LBM:
+        sol.init_equilibrium()
+    return sol
+
+
+def _layer(cfg, seed, width=3.0, amp=0.05):
+    """Particle-laden fluid above clear fluid with a seeded, column-wise
+    random interface displacement and cell noise."""
+    rng = np.random.default_rng(seed)
+    nv = cfg.ny if cfg.dim == 2 else cfg.nz
+    lateral = (1, 1, cfg.nx) if cfg.dim == 2 else (1, cfg.ny, cfg.nx)
+    disp = rng.uniform(-0.25, 0.25, lateral) * nv
+    v = np.arange(nv, dtype=np.float64)
+    v = v[None, :, None] if cfg.dim == 2 else v[:, None, None]
+    c = 0.5 * (1 + np.tanh((v - 0.5 * (nv - 1) - disp) / width))
+    c = c + amp * rng.uniform(-1, 1, cfg.shape)
+    return as_input(c, cfg)
+
+
+CASES = [
+    dict(nx=37, ny=29),
+    dict(nx=64, ny=128, precision="fp32_shifted"),
+    dict(lattice=19, nx=9, ny=7, nz=23),
+    dict(lattice=19, nx=33, ny=17, nz=40, precision="fp32_shifted"),
+    dict(nx=1, ny=6),
+    dict(lattice=19, nx=1, ny=1, nz=6, precision="fp32_shifted"),
+]
+
+
+@pytest.mark.parametrize("kw", CASES)
+@pytest.mark.parametrize("field", ["layer", "uniform_random"])
+def test_front_height_bitwise(kw, field):
+    import torch
+
+    cfg = lbw.RunConfig(tau=0.6, vs=1e-3, kappa_c=1e-3, gp_c=1e-5, **kw)
+    if field == "layer":
+        c = _layer(cfg, 11)
+    else:
+        c = as_input(np.random.default_rng(12).uniform(0, 1, cfg.shape), cfg)
+    sol = _solver_with(cfg, c)
+    ocfg = oracle_cfg(cfg)
+    for thr in (0.5, 0.05, 0.95, float(c.flat[c.size // 2]), -1.0, 2.0):
+        got = sol.front_height(thr)
+        torch.cuda.synchronize()
+        want = oracle.front_height(ocfg, c, thr)
+        assert got.shape == ((cfg.nx,) if cfg.dim == 2 else (cfg.ny, cfg.nx))
+        assert np.array_equal(got.cpu().numpy().ravel(), want), (thr, kw)
+    sol.close()
+
+
+def test_front_height_degenerate_columns():
+    """Bottom cell at the threshold gives 0; no cell reaching it gives nv."""
+    import torch
+
+    cfg = lbw.RunConfig(nx=4, ny=8, tau=0.6, vs=1e-3, kappa_c=1e-3, gp_c=1e-5)
+    c = np.zeros(cfg.shape)
+    c[0, :, 1] = 0.5                      # column 1: every cell at the threshold
+    c[0, 5:, 2] = 1.0                     # column 2: step between cells 4 and 5
+    sol = _solver_with(cfg, c)
+    got = sol.front_height(0.5)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    assert np.array_equal(got, oracle.front_height(oracle_cfg(cfg), c, 0.5))
+    assert got[0] == 8.0 and got[3] == 8.0 and got[1] == 0.0 and got[2] == 5.0
+    sol.close()
+
+
+@pytest.mark.parametrize("kw", CASES)
+def test_mass_below_matches_oracle(kw):
+    cfg = lbw.RunConfig(tau=0.6, vs=1e-3, kappa_c=1e-3, gp_c=1e-5, **kw)
+    c = _layer(cfg, 13)
+    sol = _solver_with(cfg, c)
+    ocfg = oracle_cfg(cfg)
+    nv = cfg.ny if cfg.dim == 2 else cfg.nz
+    total = sol.reduce(lbw.MASS_C)[0]
+    for plane in sorted({0, 1, nv // 3, nv // 2, nv - 1, nv}):
+        got = sol.mass_below(plane)
+        assert got.shape == (1,)
+        want = oracle.mass_below(ocfg, c, plane)
+        assert abs(got[0] - want) <= TOL64 * max(abs(want), 1e-300), (plane, got, want)
+    assert sol.mass_below(0)[0] == 0.0
+    assert sol.mass_below(nv)[0] == total        # same reduction over the same cells
+    sol.close()
+
+
+def test_mass_below_rejects_planes_outside_the_domain():
+    cfg = lbw.RunConfig(nx=8, ny=10, tau=0.6, vs=1e-3, kappa_c=1e-3, gp_c=1e-5)
+    sol = _solver_with(cfg, np.ones(cfg.shape))
+    for plane in (-1, 11):
+        with pytest.raises(lbw.LbwError):
+            sol.mass_below(plane)
+    with pytest.raises(lbw.LbwError):
+        sol.front_height(float("nan"))
+    sol.close()
+
+
+def test_batch_diagnostics_per_run():
+    """Runs of uneven height in one batch: each run's mass below a plane and
+    front height equal the oracle's on that run's field."""
+    import torch
+
+    runs = [w for w in W.sweep_runs(6, grids=((16, 24), (32, 40), (24, 32)))]
+    cfgs = [lbw.RunConfig.from_workload(w) for w in runs]
+    sol = lbw.Solver(cfgs)
+    fields = []
+    for r, (w, cfg) in enumerate(zip(runs, cfgs)):
+        c = as_input(W.initial_scalars(w)[0], cfg)
+        fields.append(c)
+        sol.set_field("c", c, run=r)
+        sol.init_equilibrium(run=r)
+    plane = min(c.ny for c in cfgs) // 2
+    got = sol.mass_below(plane)
+    for r, (cfg, c) in enumerate(zip(cfgs, fields)):
+        want = oracle.mass_below(oracle_cfg(cfg), c, plane)
+        assert abs(got[r] - want) <= TOL64 * abs(want), (r, got[r], want)
+        thr = 0.5 * runs[r].c0
+        h = sol.front_height(thr, run=r)
+        torch.cuda.synchronize()
+        assert np.array_equal(h.cpu().numpy(), oracle.front_height(oracle_cfg(cfg), c, thr)), r
+    with pytest.raises(lbw.LbwError):
+        sol.mass_below(max(c.ny for c in cfgs))   # beyond the lowest run
+    sol.close()
+
+
+def test_front_height_after_steps_fp64():
+    """After stepping both sides from the seeded two-layer state, the front
+    heights agree to the accuracy of the fields themselves."""
+    import torch
+
+    wl = W.C1.replace(nx=48, ny=64)
+    cfg = lbw.RunConfig.from_workload(wl)
+    c0, _ = W.initial_scalars(wl)
+    sol = _solver_with(cfg, c0)
+    sol.step(200)
+    got = sol.front_height(0.5)
+    torch.cuda.synchronize()
+    o = run_oracle(cfg, c0, nsteps=200)
+    want = oracle.front_height(oracle_cfg(cfg), o["c"], 0.5)
+    assert np.max(np.abs(got.cpu().numpy() - want)) <= 1e-9
+    ocfg = oracle_cfg(cfg)
+    for plane in (10, 32):
+        m = sol.mass_below(plane)[0]
+        mw = oracle.mass_below(ocfg, o["c"], plane)
+        assert abs(m - mw) <= TOL64 * abs(mw)
+    sol.close()
+
+
+def test_front_height_full_3d_size():
+    """At the full 3D size (256 x 256 x 512, FP32 storage) on a seeded layer
+    field: every column's front height equals the oracle's."""
+    import torch
+
+    wl = W.C3
+    cfg = lbw.RunConfig.from_workload(wl)
+    c = _layer(cfg, 14, width=8.0, amp=0.02)
+    sol = lbw.Solver(cfg)
+    sol.set_field("c", c)
+    got = sol.front_height(0.5)
+    torch.cuda.synchronize()
+    want = oracle.front_height(oracle_cfg(cfg), c, 0.5)
+    assert np.array_equal(got.cpu().numpy().ravel(), want)
+    m = sol.mass_below(wl.nz // 2)[0]
+    mw = oracle.mass_below(oracle_cfg(cfg), c, wl.nz // 2)
+    assert abs(m - mw) <= TOL64 * abs(mw)
+    sol.close()
