@@ -18,4 +18,5 @@ from .oracle import (  # noqa: F401
     adjoint_step,
     front_height,
     mass_below,
+    front_psd,
 )

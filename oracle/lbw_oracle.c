@@ -821,6 +821,46 @@ int orc_mass_below(const orc_cfg *cfg, const double *c, int plane, double *out)
     return 0;
 }
 
+int orc_front_psd(const orc_cfg *cfg, const double *h, int axis, int index, double *out)
+{
+    const double two_pi = 6.28318530717958647692528676655900577;
+    grid_t g;
+    long stride, step;
+    int len, nslice, s, s0, s1, j, k;
+    if (setup(cfg, &g)) return -1;
+    if (axis < 0 || axis > g.dim - 2) return -1;        /* lateral axes only */
+    if (axis == 0) {                                    /* along x, rows y */
+        len = g.n[0];
+        nslice = g.dim == 3 ? g.n[1] : 1;
+        step = 1;
+        stride = g.n[0];
+    } else {                                            /* along y, rows x */
+        len = g.n[1];
+        nslice = g.n[0];
+        step = g.n[0];
+        stride = 1;
+    }
+    if (index < -1 || index >= nslice) return -1;
+    s0 = index < 0 ? 0 : index;
+    s1 = index < 0 ? nslice : index + 1;
+    for (k = 0; k <= len / 2; k++) {
+        double acc = 0.0;
+        for (s = s0; s < s1; s++) {
+            double re = 0.0, im = 0.0;
+            for (j = 0; j < len; j++) {
+                /* exp(-2 pi i k j / L), phase reduced modulo L exactly */
+                double ang = two_pi * (double)(((long)k * j) % len) / (double)len;
+                double hj = h[(long)s * stride + (long)j * step];
+                re += hj * cos(ang);
+                im -= hj * sin(ang);
+            }
+            acc += (re * re + im * im) / (double)len;
+        }
+        out[k] = acc / (double)(s1 - s0);
+    }
+    return 0;
+}
+
 int orc_sums(const orc_cfg *cfg, const double *f, const double *c,
              const double *s, const double *dep, double *out)
 {

@@ -96,6 +96,16 @@ int orc_front_height(const orc_cfg *cfg, const double *c, double thr, double *ou
  * particle concentration in the lower layer and accumulation rate"). */
 int orc_mass_below(const orc_cfg *cfg, const double *c, int plane, double *out);
 
+/* Power spectral density of a front height H[ncol] (as orc_front_height
+ * writes it) along one lateral axis, the diagnostic the paper fits growth
+ * rates to (eq. 45-46): for the slice of L samples along `axis` (0: x,
+ * length nx; 1: y, length ny, 3D only) at index `index` of the other
+ * lateral axis, Gamma(k) = |sum_j H_j exp(-2 pi i k j / L)|^2 / (kS L) for
+ * k = 0 .. L/2 with kS = 1 (one sample per lattice spacing).  index = -1
+ * averages Gamma over every slice along that axis.  out[L/2 + 1].  Returns
+ * -1 for an invalid axis or index. */
+int orc_front_psd(const orc_cfg *cfg, const double *h, int axis, int index, double *out);
+
 #ifdef __cplusplus
 }
 #endif

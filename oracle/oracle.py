@@ -116,6 +116,7 @@ def _load():
         lib.orc_adjoint_step.argtypes = [cfgp, P, P, P, P, P, ctypes.c_double, P, P, P]
         lib.orc_front_height.argtypes = [cfgp, P, ctypes.c_double, P]
         lib.orc_mass_below.argtypes = [cfgp, P, ctypes.c_int32, P]
+        lib.orc_front_psd.argtypes = [cfgp, P, ctypes.c_int32, ctypes.c_int32, P]
         _lib = lib
     return _lib
 
@@ -209,6 +210,19 @@ def mass_below(cfg: OracleConfig, c, plane: int) -> float:
     cc = cfg._c()
     _check(lib.orc_mass_below(ctypes.byref(cc), _ptr(c), int(plane), _ptr(out)), "mass_below")
     return float(out[0])
+
+
+def front_psd(cfg: OracleConfig, h, axis: int = 0, index: int = 0) -> np.ndarray:
+    """Power spectral density of a front height along a lateral axis (see
+    the C header): Gamma(k), k = 0 .. L/2."""
+    lib = _load()
+    h = np.ascontiguousarray(h, np.float64).ravel()
+    length = (cfg.nx if axis == 0 else cfg.ny)
+    out = np.zeros(length // 2 + 1, np.float64)
+    cc = cfg._c()
+    _check(lib.orc_front_psd(ctypes.byref(cc), _ptr(h), int(axis), int(index), _ptr(out)),
+           "front_psd")
+    return out
 
 
 def sums(cfg: OracleConfig, f, c, s=None, dep=None):

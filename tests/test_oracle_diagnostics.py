@@ -82,3 +82,53 @@ def test_mass_below_a_plane(q):
     assert oracle.mass_below(cfg, step, 15) == 5.0 * ncol
     with pytest.raises(ValueError):
         oracle.mass_below(cfg, c, 25)
+
+
+def test_psd_of_a_cosine_is_two_closed_form_bins():
+    """H_j = B + A cos(2 pi m j / L): Gamma(0) = B^2 L, Gamma(m) = A^2 L / 4,
+    every other bin zero (the transform of a single mode)."""
+    nx, m, a, b = 48, 5, 2.5, 30.0
+    cfg = _cfg(nx=nx, ny=40)
+    h = b + a * np.cos(2 * np.pi * m * np.arange(nx) / nx)
+    g = oracle.front_psd(cfg, h)
+    assert g.shape == (nx // 2 + 1,)
+    want = np.zeros(nx // 2 + 1)
+    want[0] = b * b * nx
+    want[m] = a * a * nx / 4
+    assert np.max(np.abs(g - want)) < 1e-9 * want[0]
+
+
+@pytest.mark.parametrize("nx", [1, 2, 31, 64])
+def test_psd_parseval_and_fft(nx):
+    """Parseval: sum over the full spectrum of |H~|^2 / L (the one-sided bins
+    counted twice except k = 0 and, for even L, k = L/2) equals sum H_j^2; and
+    every bin equals |rfft(H)|^2 / L."""
+    cfg = _cfg(nx=nx, ny=40)
+    h = np.random.default_rng(nx).uniform(0, 40, nx)
+    g = oracle.front_psd(cfg, h)
+    w = np.full(len(g), 2.0)
+    w[0] = 1.0
+    if nx % 2 == 0:
+        w[-1] = 1.0
+    assert abs(np.sum(w * g) - np.sum(h * h)) <= 1e-12 * np.sum(h * h)
+    assert np.allclose(g, np.abs(np.fft.rfft(h)) ** 2 / nx, rtol=1e-11, atol=1e-11 * np.sum(h * h))
+
+
+def test_psd_slices_of_a_3d_front():
+    """3D: axis 0 transforms the row at y = index, axis 1 the row at x =
+    index; index -1 averages over every row."""
+    nx, ny = 12, 9
+    cfg = _cfg(q=19, nx=nx, ny=ny, nz=8)
+    h = np.random.default_rng(5).uniform(0, 8, (ny, nx))
+    ref = lambda rows: np.abs(np.fft.rfft(rows, axis=-1)) ** 2 / rows.shape[-1]
+    for y in (0, 4, ny - 1):
+        assert np.allclose(oracle.front_psd(cfg, h, 0, y), ref(h[y]), rtol=1e-11, atol=1e-9)
+    for x in (0, 7):
+        assert np.allclose(oracle.front_psd(cfg, h, 1, x), ref(h[:, x]), rtol=1e-11, atol=1e-9)
+    assert np.allclose(oracle.front_psd(cfg, h, 0, -1), ref(h).mean(axis=0), rtol=1e-11, atol=1e-9)
+    assert np.allclose(oracle.front_psd(cfg, h, 1, -1), ref(h.T).mean(axis=0), rtol=1e-11, atol=1e-9)
+    for axis, index in ((2, 0), (0, ny), (1, nx), (0, -2)):
+        with pytest.raises(ValueError):
+            oracle.front_psd(cfg, h, axis, index)
+    with pytest.raises(ValueError):
+        oracle.front_psd(_cfg(nx=8, ny=40), np.zeros(8), 1, 0)     # 2D has one lateral axis
