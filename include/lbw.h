@@ -253,6 +253,21 @@ int lbw_mass_below(lbw_handle *h, int32_t plane, double *out_host);
  * non-finite threshold. */
 int lbw_front_height(lbw_handle *h, int32_t run, double threshold, double *out_dev);
 
+/* Power spectral density of a front height along one lateral axis, the
+ * spectrum the paper extracts dominant wavenumbers and growth rates from
+ * (eq. 45-46 and the passage defining it): for the row of L samples of
+ * height_dev (device, FP64, ncol values in the layout lbw_front_height
+ * writes) along `axis` (0: x, L = nx; 1: y, L = ny, 3D runs only) at index
+ * `index` of the other lateral axis,
+ *   Gamma(k) = |sum_j H_j exp(-2 pi i k j / L)|^2 / (kS L),  k = 0 .. L/2,
+ * with kS = 1 (one sample per lattice spacing), into the caller's device
+ * array out_dev[L/2 + 1] (FP64).  index = -1 averages Gamma over every row
+ * along that axis.  The sums run in a fixed order: the same input gives the
+ * same bits.  Enqueued on the handle's stream.  LBW_ERR_INVAL for a bad run,
+ * NULL pointers, an axis that is not lateral or an index outside [-1, rows). */
+int lbw_front_psd(lbw_handle *h, int32_t run, const double *height_dev, int32_t axis,
+                  int32_t index, double *out_dev);
+
 /* Device workspace lbw_adjoint_step needs for run `run` (bytes). */
 int lbw_adjoint_work_bytes(const lbw_handle *h, int32_t run, size_t *out_bytes);
 

@@ -792,6 +792,21 @@ int lbw_mass_below(lbw_handle *h, int32_t plane, double *out_host) {
     return reduce_impl(h, LBW_MASS_C, out_host, plane);
 }
 
+int lbw_front_psd(lbw_handle *h, int32_t run, const double *height_dev, int32_t axis,
+                  int32_t index, double *out_dev) {
+    int rc = check_run(h, run);
+    if (rc) return rc;
+    if (!height_dev || !out_dev) return fail(LBW_ERR_INVAL, "NULL argument");
+    const lbw::RunDev &r = h->run[run];
+    if (axis < 0 || axis > h->dim - 2)
+        return fail(LBW_ERR_INVAL, "axis %d is not a lateral axis of a %dD run", axis, h->dim);
+    const int nslice = axis == 0 ? (h->dim == 3 ? r.ny : 1) : r.nx;
+    if (index < -1 || index >= nslice)
+        return fail(LBW_ERR_INVAL, "slice index %d outside [-1, %d)", index, nslice);
+    hipError_t e = lbw::launch_front_psd(r, h->dim, height_dev, axis, index, out_dev, h->stream);
+    return e == hipSuccess ? LBW_OK : hip_fail(e, "front-psd launch");
+}
+
 int lbw_front_height(lbw_handle *h, int32_t run, double threshold, double *out_dev) {
     int rc = check_run(h, run);
     if (rc) return rc;

@@ -118,6 +118,10 @@ hipError_t launch_adjoint(int q, int precision, const RunDev &r, bool frozen, co
 hipError_t launch_reduce(int q, int precision, const RunDev *runs, int nbatch, int what,
                          bool odd, double *scratch, hipStream_t st, int plane = -1);
 // Front of the particle field per bottom column into out (device, ncol).
+// Power spectral density of a front height (device, ncol values) along
+// lateral axis `axis` for slice `index` (-1: mean over slices); out[len/2+1].
+hipError_t launch_front_psd(const RunDev &r, int dim, const double *h, int axis, int index,
+                            double *out, hipStream_t st);
 hipError_t launch_front_height(int precision, const RunDev &r, int dim, double thr, double *out,
                                hipStream_t st);
 

@@ -125,4 +125,76 @@ hipError_t launch_front_height(int precision, const RunDev &r, int dim, double t
     return hipGetLastError();
 }
 
+namespace {
+
+// Power spectral density of a front height along one lateral axis (the
+// spectrum whose growth the paper fits against linear stability, eq. 45-46):
+// Gamma(k) = |sum_j H_j exp(-2 pi i k j / L)|^2 / (kS L), kS = 1, averaged
+// over slices s0 .. s1-1.  One block per wavenumber; each slice's transform
+// is a block-wide sum in a fixed order (the same bits on every call), with
+// the phase k j reduced modulo L exactly before the sine and cosine.
+__global__ void __launch_bounds__(256) k_front_psd(const double *__restrict__ h, int len,
+                                                   int64_t step, int64_t stride, int s0, int s1,
+                                                   double *__restrict__ out) {
+    __shared__ double wre[4], wim[4];
+    const int64_t k = blockIdx.x;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const double two_over_len = 2.0 / (double)len;
+    double acc = 0.0;
+    for (int s = s0; s < s1; ++s) {
+        const double *row = h + (int64_t)s * stride;
+        double re = 0.0, im = 0.0;
+        for (int j = threadIdx.x; j < len; j += blockDim.x) {
+            const int64_t m = (k * j) % len;
+            double sn, cs;
+            sincospi((double)m * two_over_len, &sn, &cs);   // angle 2 pi m / L
+            const double hj = row[(int64_t)j * step];
+            re += hj * cs;
+            im -= hj * sn;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            re += __shfl_down(re, off, 64);
+            im += __shfl_down(im, off, 64);
+        }
+        if (lane == 0) {
+            wre[wid] = re;
+            wim[wid] = im;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double tr = 0.0, ti = 0.0;
+            for (int i = 0; i < 4; ++i) {
+                tr += wre[i];
+                ti += wim[i];
+            }
+            acc += (tr * tr + ti * ti) / (double)len;
+        }
+        __syncthreads();   // the next slice overwrites wre / wim
+    }
+    if (threadIdx.x == 0) out[k] = acc / (double)(s1 - s0);
+}
+
+}  // namespace
+
+hipError_t launch_front_psd(const RunDev &r, int dim, const double *h, int axis, int index,
+                            double *out, hipStream_t st) {
+    int len, nslice;
+    int64_t step, stride;
+    if (axis == 0) {            // rows along x, one per y
+        len = r.nx;
+        nslice = dim == 3 ? r.ny : 1;
+        step = 1;
+        stride = r.nx;
+    } else {                    // rows along y, one per x
+        len = r.ny;
+        nslice = r.nx;
+        step = r.nx;
+        stride = 1;
+    }
+    const int s0 = index < 0 ? 0 : index, s1 = index < 0 ? nslice : index + 1;
+    k_front_psd<<<(unsigned)(len / 2 + 1), 256, 0, st>>>(h, len, step, stride, s0, s1, out);
+    return hipGetLastError();
+}
+
 }  // namespace lbw

@@ -31,7 +31,7 @@ EXPORTED = ("lbw_version", "lbw_last_error", "lbw_scratch_bytes", "lbw_create", 
             "lbw_set_launch", "lbw_get_launch", "lbw_init_equilibrium", "lbw_step",
             "lbw_steps_done", "lbw_export", "lbw_import", "lbw_rebind", "lbw_reduce", "lbw_timing_begin",
             "lbw_timing_end", "lbw_adjoint_work_bytes", "lbw_adjoint_step", "lbw_mass_below",
-            "lbw_front_height")
+            "lbw_front_height", "lbw_front_psd")
 
 
 class LbwError(RuntimeError):
@@ -100,6 +100,7 @@ def load() -> ctypes.CDLL:
     lib.lbw_reduce.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double)]
     lib.lbw_mass_below.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double)]
     lib.lbw_front_height.argtypes = [P, I32, ctypes.c_double, P]
+    lib.lbw_front_psd.argtypes = [P, I32, P, I32, I32, P]
     lib.lbw_adjoint_work_bytes.argtypes = [P, I32, ctypes.POINTER(ctypes.c_size_t)]
     lib.lbw_adjoint_step.argtypes = [P, I32, P, P, P, P, P, P, P, P, ctypes.c_double, P, P, P, P,
                                      ctypes.c_size_t]
@@ -339,6 +340,25 @@ class Solver:
         out = (ctypes.c_double * self.nbatch)()
         check(self._lib.lbw_mass_below(self._h, int(plane), out))
         return np.array(out[:], dtype=np.float64)
+
+    def front_psd(self, height, axis: int = 0, index: int = 0, run: int = 0, out=None):
+        """Power spectral density of a front height (the device tensor
+        front_height returns) along a lateral axis: an FP64 device tensor of
+        L/2 + 1 bins; index -1 averages over every row along that axis."""
+        import torch
+
+        cfg = self.cfgs[run]
+        if height.dtype != torch.float64 or not height.is_contiguous() or height.numel() != cfg.ncol:
+            raise ValueError("height must be a contiguous float64 tensor of ncol values")
+        length = cfg.nx if axis == 0 else cfg.ny
+        if out is None:
+            with torch.cuda.stream(self.stream):
+                out = torch.empty(length // 2 + 1, dtype=torch.float64, device=self.device)
+        if out.dtype != torch.float64 or not out.is_contiguous() or out.numel() != length // 2 + 1:
+            raise ValueError("out must be a contiguous float64 tensor of L/2 + 1 values")
+        check(self._lib.lbw_front_psd(self._h, int(run), ctypes.c_void_p(height.data_ptr()),
+                                      int(axis), int(index), ctypes.c_void_p(out.data_ptr())))
+        return out
 
     def front_height(self, threshold: float, run: int = 0, out=None):
         """Front height per bottom column as an FP64 device tensor of the

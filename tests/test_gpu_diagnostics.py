@@ -1,12 +1,14 @@
-"""GPU parity of the in-situ diagnostics (front height per column, particle
-mass below a horizontal plane) against the FP64 oracle on the same seeded
-fields.
+"""GPU parity of the in-situ diagnostics (front height per column, its power
+spectral density along a lateral axis, particle mass below a horizontal
+plane) against the FP64 oracle on the same seeded fields.
 
 The front height compares C with the threshold in FP64 and interpolates in
 the same operation order on both sides (no products, so no fused
 multiply-add can differ): it must agree bit for bit.  The mass below a plane
 is the same deterministic tree reduction as the mass sums against the
-oracle's sequential sum: 1e-12 relative.
+oracle's sequential sum: 1e-12 relative.  The spectrum is a sum of L terms
+with sines and cosines of the exact phase on both sides: bounded as stated
+in _psd_close.
 """
 import numpy as np
 import pytest
@@ -170,6 +172,94 @@ def test_front_height_after_steps_fp64():
     sol.close()
 
 
+def _lateral(cfg):
+    return (cfg.nx,) if cfg.dim == 2 else (cfg.ny, cfg.nx)
+
+
+def _psd_close(got, want, h, cfg, axis):
+    """Rounding bound of the transform: each |X(k)| = |sum_j H_j e^(..)| may
+    differ by delta = 1e-13 sum_j |H_j| (sum order and the sine/cosine of
+    the exact phase, both within L eps), so Gamma = |X|^2 / L by at most
+    (2 sqrt(L Gamma) delta + delta^2) / L, also for the mean over rows."""
+    rows = np.asarray(h, np.float64).reshape(_lateral(cfg) if cfg.dim == 3 else (1, cfg.nx))
+    if axis == 1:
+        rows = rows.T
+    length = rows.shape[1]
+    delta = 1e-13 * float(np.max(np.sum(np.abs(rows), axis=1)))
+    bound = (2 * np.sqrt(length * np.abs(want)) * delta + delta * delta) / length
+    assert np.all(np.abs(got - want) <= bound), float(np.max(np.abs(got - want) / bound))
+
+
+PSD_CASES = [
+    (dict(nx=37, ny=29), 0, 0),
+    (dict(nx=64, ny=128, precision="fp32_shifted"), 0, 0),
+    (dict(nx=1, ny=6), 0, 0),
+    (dict(nx=2, ny=6), 0, -1),
+    (dict(lattice=19, nx=9, ny=7, nz=23), 0, 3),
+    (dict(lattice=19, nx=9, ny=7, nz=23), 1, 8),
+    (dict(lattice=19, nx=33, ny=17, nz=40, precision="fp32_shifted"), 0, -1),
+    (dict(lattice=19, nx=33, ny=17, nz=40, precision="fp32_shifted"), 1, -1),
+    (dict(lattice=19, nx=300, ny=2, nz=6), 0, 1),
+]
+
+
+@pytest.mark.parametrize("kw,axis,index", PSD_CASES)
+def test_front_psd_matches_oracle(kw, axis, index):
+    """The spectrum of the in-situ front height against the oracle's spectrum
+    of the oracle's front height (the two heights are equal bit for bit),
+    and repeated calls give the same bits."""
+    import torch
+
+    cfg = lbw.RunConfig(tau=0.6, vs=1e-3, kappa_c=1e-3, gp_c=1e-5, **kw)
+    c = _layer(cfg, 15)
+    ocfg = oracle_cfg(cfg)
+    sol = _solver_with(cfg, c)
+    h = sol.front_height(0.5)
+    g = sol.front_psd(h, axis, index)
+    g2 = sol.front_psd(h, axis, index)
+    torch.cuda.synchronize()
+    h_o = oracle.front_height(ocfg, c, 0.5)
+    assert np.array_equal(h.cpu().numpy().ravel(), h_o)
+    want = oracle.front_psd(ocfg, h_o, axis, index)
+    length = cfg.nx if axis == 0 else cfg.ny
+    assert g.shape == (length // 2 + 1,)
+    _psd_close(g.cpu().numpy(), want, h_o, cfg, axis)
+    assert torch.equal(g, g2)
+    sol.close()
+
+
+@pytest.mark.parametrize("nx", [1, 2, 63, 64, 1024])
+def test_front_psd_of_seeded_heights(nx):
+    """Seeded heights uploaded directly (not produced by the front kernel)."""
+    import torch
+
+    cfg = lbw.RunConfig(nx=nx, ny=40, tau=0.6, vs=1e-3, kappa_c=1e-3, gp_c=1e-5)
+    h = np.random.default_rng(nx).uniform(0, 40, nx)
+    sol = lbw.Solver(cfg)
+    g = sol.front_psd(torch.tensor(h, device="cuda"))
+    torch.cuda.synchronize()
+    want = oracle.front_psd(oracle_cfg(cfg), h)
+    _psd_close(g.cpu().numpy(), want, h, cfg, 0)
+    sol.close()
+
+
+def test_front_psd_rejects_bad_axes_and_rows():
+    import torch
+
+    cfg2 = lbw.RunConfig(nx=8, ny=10, tau=0.6, vs=1e-3, kappa_c=1e-3, gp_c=1e-5)
+    cfg3 = lbw.RunConfig(lattice=19, nx=8, ny=5, nz=10, tau=0.6, vs=1e-3, kappa_c=1e-3, gp_c=1e-5)
+    for cfg, bad in ((cfg2, [(1, 0), (0, 1), (0, -2), (2, 0)]),
+                     (cfg3, [(0, 5), (1, 8), (0, -2), (2, 0), (-1, 0)])):
+        sol = lbw.Solver(cfg)
+        h = torch.zeros(cfg.ncol, dtype=torch.float64, device="cuda")
+        out = torch.zeros(64, dtype=torch.float64, device="cuda")
+        for axis, index in bad:
+            with pytest.raises(lbw.LbwError):
+                length = cfg.nx if axis == 0 else cfg.ny
+                sol.front_psd(h, axis, index, out=out[: length // 2 + 1])
+        sol.close()
+
+
 def test_front_height_full_3d_size():
     """At the full 3D size (256 x 256 x 512, FP32 storage) on a seeded layer
     field: every column's front height equals the oracle's."""
@@ -184,6 +274,10 @@ def test_front_height_full_3d_size():
     torch.cuda.synchronize()
     want = oracle.front_height(oracle_cfg(cfg), c, 0.5)
     assert np.array_equal(got.cpu().numpy().ravel(), want)
+    for axis in (0, 1):
+        g = sol.front_psd(got, axis, -1)
+        torch.cuda.synchronize()
+        _psd_close(g.cpu().numpy(), oracle.front_psd(oracle_cfg(cfg), want, axis, -1), want, cfg, axis)
     m = sol.mass_below(wl.nz // 2)[0]
     mw = oracle.mass_below(oracle_cfg(cfg), c, wl.nz // 2)
     assert abs(m - mw) <= TOL64 * abs(mw)

@@ -21,13 +21,15 @@ def test_gpu_growth_rate_matches_lsa(precision):
     sol = lbw.Solver(cfg)
     sol.set_field("c", c)
     sol.init_equilibrium(rho=rho)
-    ts, amps, profs = [], [], {}
+    ts, amps, psd, profs = [], [], [], {}
     for it in range(nsteps // chunk):
         sol.step(chunk)
         t = (it + 1) * chunk
         u = sol.field("u").double().cpu().numpy()
         ts.append(t)
         amps.append(mode_amplitude(u[1, 0]))
+        # in-situ: front height and its spectrum stay on the device
+        psd.append(float(sol.front_psd(sol.front_height(0.5))[1]))
         profs[t] = sol.field("c").double().cpu().numpy()[0].mean(axis=1)
     sol.close()
     ts, amps = np.array(ts), np.array(amps)
@@ -37,3 +39,6 @@ def test_gpu_growth_rate_matches_lsa(precision):
     print(f"\n{precision}: growth rate {sim:.5e}, LSA {pred:.5e}, ratio {sim / pred:.4f}")
     assert amps[win][-1] > 2 * amps[win][0]
     assert abs(sim / pred - 1) < 0.01, (sim, pred)
+    sim_h = 0.5 * fitted_rate(ts[win], np.array(psd)[win])     # Gamma_H ~ exp(2 sigma t)
+    print(f"front-height PSD rate {sim_h:.5e}, ratio {sim_h / pred:.4f}")
+    assert abs(sim_h / pred - 1) < 0.03, (sim_h, pred)
