@@ -93,6 +93,7 @@ def run_gpu(wl, steps: int, warmup: int) -> dict:
     phases = sol.timing_end()
     # untimed sanity: the particle budget must close
     mass = sol.reduce(lbw.MASS_C)[0] + sol.reduce(lbw.DEPOSIT)[0]
+    diag = run_diagnostics(sol, wl)
     sol.close()
     cells = wl.cells
     ab = _alg_bytes(wl)
@@ -110,6 +111,57 @@ def run_gpu(wl, steps: int, warmup: int) -> dict:
                      "kernel": "collide_stream", "alg_bytes_per_cell": ab["collide_stream"],
                      "cells_per_launch": cells},
         "particle_budget": mass,
+        "diagnostics": diag,
+    }
+
+
+def run_diagnostics(sol, wl, reps: int = 20) -> dict:
+    """Time the in-situ diagnostics on the state the timed steps left (outside
+    the timed region): front height per column at C0/2, its spectrum averaged
+    over the rows along each lateral axis, and the mass below the mid plane.
+    The front scan stops at the first cell that reaches the threshold, so its
+    algorithmic bytes are the cells scanned (from the heights it returns)
+    plus the heights written."""
+    import numpy as np
+    import torch
+
+    thr = 0.5 * wl.c0
+    st = sol.stream
+    esize = 4 if wl.precision == "fp32_shifted" else 8
+    h = sol.front_height(thr)
+    psd = {axis: sol.front_psd(h, axis, -1) for axis in range(wl.dim - 1)}
+    torch.cuda.synchronize()
+
+    def timed(fn) -> float:
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        for _ in range(reps):
+            fn()
+        b.record(st)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    ms_front = timed(lambda: sol.front_height(thr, out=h))
+    ms_psd = {axis: timed(lambda axis=axis: sol.front_psd(h, axis, -1, out=psd[axis]))
+              for axis in psd}
+    plane = wl.nvert // 2
+    ms_mass = timed(lambda: sol.mass_below(plane))
+    hv = h.cpu().numpy().ravel()
+    scanned = np.where(hv >= wl.nvert, wl.nvert,
+                       np.clip(np.ceil(hv - 0.5), 0, wl.nvert - 1) + 1).sum()
+    front_bytes = float(scanned) * esize + hv.size * 8
+    mass_bytes = float(plane) * (wl.cells // wl.nvert) * esize
+    return {
+        "threshold": thr,
+        "front_height_ms": ms_front,
+        "front_height_alg_gbs": front_bytes / (ms_front * 1e-3) / 1e9,
+        "front_cells_scanned": int(scanned),
+        "front_psd_ms": {("x", "y")[a]: v for a, v in ms_psd.items()},
+        "psd_bins": {("x", "y")[a]: int(psd[a].numel()) for a in psd},
+        "mass_below_ms": ms_mass,
+        "mass_below_alg_gbs": mass_bytes / (ms_mass * 1e-3) / 1e9,
+        "mass_below_note": "includes the device-to-host copy and stream synchronisation",
+        "mean_front_height": float(hv.mean()),
     }
 
 
@@ -340,7 +392,8 @@ def main() -> int:
         print(f"[bench] {other.name}: {o['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
         also = {"workload": other.name, "value": o["mlups"], "unit": "MLUPS",
                 "ms_per_step": o["ms_per_step"], "phase_ms_per_step": o["phase_ms_per_step"],
-                "step_alg_gbs": o["step_alg_gbs"], "roofline": o["roofline"]}
+                "step_alg_gbs": o["step_alg_gbs"], "roofline": o["roofline"],
+                "diagnostics": o["diagnostics"]}
     sweep = None
     if not args.no_sweep:
         sweep = run_sweep(min(args.steps, 200), 4)
@@ -386,6 +439,7 @@ def main() -> int:
         "step_alg_gbs": res["step_alg_gbs"],
         "step_alg_frac": res["step_alg_gbs"] / HBM_PEAK_GBS,
         "roofline": res["roofline"],
+        "diagnostics": res["diagnostics"],
         "cpu_baseline": cpu,
         "also": also,
         "sweep": sweep,

@@ -12,6 +12,8 @@
 // per column (lowest height where C reaches a threshold).
 #include "lbm_device.h"
 
+#include <climits>
+
 namespace lbw {
 namespace {
 
@@ -30,29 +32,46 @@ __device__ __forceinline__ double block_sum(double acc) {
     return t;
 }
 
+// Sum of x[0 .. n-1] over a grid-stride slice with four independent
+// accumulators (four loads in flight per thread), combined in a fixed order.
+template <typename V>
+__device__ __forceinline__ double strided_sum(const V *__restrict__ x, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (; k + 3 * stride < n; k += 4 * stride) {
+        a0 += (double)x[k];
+        a1 += (double)x[k + stride];
+        a2 += (double)x[k + 2 * stride];
+        a3 += (double)x[k + 3 * stride];
+    }
+    for (; k < n; k += stride) a0 += (double)x[k];
+    return (a0 + a1) + (a2 + a3);
+}
+
 template <int Q, typename T>
-__global__ void __launch_bounds__(256) k_partial(RunDev r, int what, bool odd, bool shifted,
-                                                 int plane, double *__restrict__ part) {
+__global__ void __launch_bounds__(1024) k_partial(RunDev r, int what, bool odd, bool shifted,
+                                                  int plane, double *__restrict__ part) {
     double acc = 0.0;
     int64_t n = (what == LBW_DEPOSIT) ? r.ncol : r.N;
     if (plane >= 0 && (what == LBW_MASS_C || what == LBW_MASS_S) && (int64_t)plane * r.ncol < n)
         n = (int64_t)plane * r.ncol;   // planes are the slowest axis
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
-        if (what == LBW_MASS_C) {
-            acc += (double)((const T *)r.c)[k];
-        } else if (what == LBW_MASS_S) {
-            acc += (double)((const T *)r.s)[k];
-        } else if (what == LBW_MASS_FLUID) {
-            using L = Lattice<Q>;
+    if (what == LBW_MASS_C) {
+        acc = strided_sum((const T *)r.c, n);
+    } else if (what == LBW_MASS_S) {
+        acc = strided_sum((const T *)r.s, n);
+    } else if (what == LBW_DEPOSIT) {
+        acc = strided_sum(r.dep, n);
+    } else {
+        using L = Lattice<Q>;
+        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+        for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
             int x, y, z;
             coords<L::D>(r, k, x, y, z);
             double s = shifted ? 1.0 : 0.0;
 #pragma unroll
             for (int i = 0; i < Q; ++i) s += (double)load_canonical<Q, T>(r, (const T *)r.f, i, k, x, y, z, odd);
             acc += s;
-        } else {
-            acc += r.dep[k];
         }
     }
     const double t = block_sum(acc);
@@ -72,34 +91,66 @@ template <int Q, typename T>
 hipError_t reduce_t(const RunDev *runs, int nbatch, int what, bool odd, bool shifted,
                     double *scratch, hipStream_t st, int plane) {
     for (int b = 0; b < nbatch; ++b)
-        k_partial<Q, T><<<kReduceBlocks, 256, 0, st>>>(runs[b], what, odd, shifted, plane,
+        k_partial<Q, T><<<kReduceBlocks, 1024, 0, st>>>(runs[b], what, odd, shifted, plane,
                                                         scratch + (int64_t)b * kReduceBlocks);
     k_final<<<nbatch, 256, 0, st>>>(scratch, kReduceBlocks, scratch + (int64_t)nbatch * kReduceBlocks);
     return hipGetLastError();
 }
 
-// One thread per bottom column scans upward for the first cell with
-// C >= thr (consecutive threads read consecutive cells of a plane) and
-// interpolates linearly between the centres of that cell and the one below,
-// in double: height (v - 1) + 1/2 + (thr - C_{v-1}) / (C_v - C_{v-1}) from the
-// bottom wall; 0 if the bottom cell already holds C >= thr, the domain height
-// if no cell does.
-template <typename T>
-__global__ void __launch_bounds__(256) k_front_height(const T *__restrict__ c, int64_t ncol, int nv,
-                                                      double thr, double *__restrict__ out) {
-    const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (col >= ncol) return;
-    double h = (double)nv;
-    double below = 0.0;
-    for (int v = 0; v < nv; ++v) {
-        const double cv = (double)c[col + (int64_t)v * ncol];
-        if (cv >= thr) {
-            h = v == 0 ? 0.0 : (double)(v - 1) + 0.5 + (thr - below) / (cv - below);
-            break;
+// Front of the particle field: for each bottom column, the first cell v
+// (from the bottom wall) with C >= thr, and linear interpolation between the
+// centres of that cell and the one below, in double: height (v - 1) + 1/2 +
+// (thr - C_{v-1}) / (C_v - C_{v-1}); 0 if the bottom cell already holds
+// C >= thr, the domain height if no cell does.
+//
+// A block owns 64 consecutive columns (a wave reads 64 consecutive cells of
+// a plane) and climbs them in rounds of W * U cells: wave w loads cells
+// [base + w U, base + (w + 1) U) of its lane's column, U independent loads in
+// flight, and the lowest hit of the round over the W waves ends the column.
+// The scan thus stops within one round of the front, with W * U loads per
+// column in flight instead of one dependent load at a time.
+template <typename T, int W, int U>
+__global__ void __launch_bounds__(64 * W) k_front_height(const T *__restrict__ c, int64_t ncol,
+                                                         int nv, double thr,
+                                                         double *__restrict__ out) {
+    __shared__ int hit[W][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t col = (int64_t)blockIdx.x * 64 + lane;
+    bool done = col >= ncol;                 // the same in every wave of the block
+    for (int base = 0; base < nv; base += W * U) {
+        int first = INT_MAX;
+        if (!done) {
+            const int v0 = base + w * U;
+            T cv[U];
+            // unconditional loads (the index clamped into the column): a
+            // guarded load would make the compiler wait for each one in turn
+#pragma unroll
+            for (int u = 0; u < U; ++u) cv[u] = c[col + (int64_t)min(v0 + u, nv - 1) * ncol];
+#pragma unroll
+            for (int u = U - 1; u >= 0; --u)
+                if (v0 + u < nv && (double)cv[u] >= thr) first = v0 + u;
         }
-        below = cv;
+        hit[w][lane] = first;
+        __syncthreads();
+        int v = INT_MAX;
+#pragma unroll
+        for (int i = 0; i < W; ++i) v = min(v, hit[i][lane]);
+        if (!done && v != INT_MAX) {
+            if (w == 0) {
+                double h = 0.0;
+                if (v > 0) {
+                    const double cv = (double)c[col + (int64_t)v * ncol];
+                    const double cb = (double)c[col + (int64_t)(v - 1) * ncol];
+                    h = (double)(v - 1) + 0.5 + (thr - cb) / (cv - cb);
+                }
+                out[col] = h;
+            }
+            done = true;
+        }
+        // also orders this round's reads of hit[] before the next round's writes
+        if (__syncthreads_and(done)) return;
     }
-    out[col] = h;
+    if (!done && w == 0) out[col] = (double)nv;
 }
 
 }  // namespace
@@ -114,14 +165,24 @@ hipError_t launch_reduce(int q, int precision, const RunDev *runs, int nbatch, i
                   : reduce_t<19, double>(runs, nbatch, what, odd, sh, scratch, st, plane);
 }
 
+template <typename T>
+static void front_height_t(const T *c, int64_t ncol, int nv, double thr, double *out,
+                           hipStream_t st) {
+    const unsigned grid = (unsigned)((ncol + 63) / 64);
+    // few columns (2D grids): more waves per column keep enough loads in flight
+    if (ncol >= 16384)
+        k_front_height<T, 4, 16><<<grid, 256, 0, st>>>(c, ncol, nv, thr, out);
+    else
+        k_front_height<T, 16, 8><<<grid, 1024, 0, st>>>(c, ncol, nv, thr, out);
+}
+
 hipError_t launch_front_height(int precision, const RunDev &r, int dim, double thr, double *out,
                                hipStream_t st) {
     const int nv = dim == 2 ? r.ny : r.nz;
-    const unsigned grid = (unsigned)((r.ncol + 255) / 256);
     if (precision == LBW_FP32_SHIFTED)
-        k_front_height<float><<<grid, 256, 0, st>>>((const float *)r.c, r.ncol, nv, thr, out);
+        front_height_t((const float *)r.c, r.ncol, nv, thr, out, st);
     else
-        k_front_height<double><<<grid, 256, 0, st>>>((const double *)r.c, r.ncol, nv, thr, out);
+        front_height_t((const double *)r.c, r.ncol, nv, thr, out, st);
     return hipGetLastError();
 }
 
@@ -130,70 +191,125 @@ namespace {
 // Power spectral density of a front height along one lateral axis (the
 // spectrum whose growth the paper fits against linear stability, eq. 45-46):
 // Gamma(k) = |sum_j H_j exp(-2 pi i k j / L)|^2 / (kS L), kS = 1, averaged
-// over slices s0 .. s1-1.  One block per wavenumber; each slice's transform
-// is a block-wide sum in a fixed order (the same bits on every call), with
-// the phase k j reduced modulo L exactly before the sine and cosine.
-__global__ void __launch_bounds__(256) k_front_psd(const double *__restrict__ h, int len,
-                                                   int64_t step, int64_t stride, int s0, int s1,
-                                                   double *__restrict__ out) {
-    __shared__ double wre[4], wim[4];
+// over rows s0 .. s1-1.  One block of four waves per wavenumber k.  The
+// twiddles exp(-2 pi i k j / L), with the phase k j reduced modulo L exactly,
+// are tabulated once per block in LDS when the row fits (L <= kPsdTable).
+// Every sum runs in a fixed order, so the same input gives the same bits.
+constexpr int kPsdTable = 2048;   // 32 KiB of LDS
+
+template <bool TABLE>
+__device__ __forceinline__ void twiddle(const double *tw, int64_t k, int j, int len, double &cs,
+                                        double &sn) {
+    if constexpr (TABLE) {
+        cs = tw[2 * j];
+        sn = tw[2 * j + 1];
+    } else {
+        sincospi((double)((k * j) % len) * (2.0 / (double)len), &sn, &cs);
+    }
+}
+
+template <bool TABLE>
+__device__ __forceinline__ void fill_twiddles(double *tw, int64_t k, int len) {
+    if constexpr (TABLE) {
+        for (int j = threadIdx.x; j < len; j += blockDim.x)
+            sincospi((double)((k * j) % len) * (2.0 / (double)len), &tw[2 * j + 1], &tw[2 * j]);
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Few rows: one wave per row, lanes over its samples (element j of row s at
+// h[s * row_stride + j * step]).
+template <bool TABLE>
+__global__ void __launch_bounds__(256) k_front_psd_waves(const double *__restrict__ h, int len,
+                                                         int64_t row_stride, int64_t step, int s0,
+                                                         int s1, double *__restrict__ out) {
+    extern __shared__ double tw[];
+    __shared__ double wsum[4];
     const int64_t k = blockIdx.x;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const double two_over_len = 2.0 / (double)len;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    fill_twiddles<TABLE>(tw, k, len);
     double acc = 0.0;
-    for (int s = s0; s < s1; ++s) {
-        const double *row = h + (int64_t)s * stride;
+    for (int s = s0 + w; s < s1; s += 4) {
+        const double *row = h + (int64_t)s * row_stride;
         double re = 0.0, im = 0.0;
-        for (int j = threadIdx.x; j < len; j += blockDim.x) {
-            const int64_t m = (k * j) % len;
-            double sn, cs;
-            sincospi((double)m * two_over_len, &sn, &cs);   // angle 2 pi m / L
+        for (int j = lane; j < len; j += 64) {
+            double cs, sn;
+            twiddle<TABLE>(tw, k, j, len, cs, sn);
             const double hj = row[(int64_t)j * step];
             re += hj * cs;
             im -= hj * sn;
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            re += __shfl_down(re, off, 64);
-            im += __shfl_down(im, off, 64);
-        }
-        if (lane == 0) {
-            wre[wid] = re;
-            wim[wid] = im;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double tr = 0.0, ti = 0.0;
-            for (int i = 0; i < 4; ++i) {
-                tr += wre[i];
-                ti += wim[i];
-            }
-            acc += (tr * tr + ti * ti) / (double)len;
-        }
-        __syncthreads();   // the next slice overwrites wre / wim
+        re = wave_sum(re);
+        im = wave_sum(im);
+        acc += (re * re + im * im) / (double)len;    // meaningful in lane 0
     }
-    if (threadIdx.x == 0) out[k] = acc / (double)(s1 - s0);
+    if (lane == 0) wsum[w] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[k] = (wsum[0] + wsum[1] + wsum[2] + wsum[3]) / (double)(s1 - s0);
+}
+
+// Many rows: one lane per row, each lane walking its own row with the
+// twiddle of sample j broadcast from LDS; no cross-lane sum per row.  Along
+// y (rows one per x) a wave reads 64 consecutive values per sample.
+template <bool TABLE>
+__global__ void __launch_bounds__(256) k_front_psd_lanes(const double *__restrict__ h, int len,
+                                                         int64_t row_stride, int64_t step, int s0,
+                                                         int s1, double *__restrict__ out) {
+    extern __shared__ double tw[];
+    __shared__ double wsum[4];
+    const int64_t k = blockIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    fill_twiddles<TABLE>(tw, k, len);
+    double acc = 0.0;
+    for (int sb = s0 + 64 * w; sb < s1; sb += 256) {
+        const int s = sb + lane;
+        if (s < s1) {
+            const double *row = h + (int64_t)s * row_stride;
+            double re = 0.0, im = 0.0;
+            for (int j = 0; j < len; ++j) {
+                double cs, sn;
+                twiddle<TABLE>(tw, k, j, len, cs, sn);
+                const double hj = row[(int64_t)j * step];
+                re += hj * cs;
+                im -= hj * sn;
+            }
+            acc += (re * re + im * im) / (double)len;
+        }
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) wsum[w] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[k] = (wsum[0] + wsum[1] + wsum[2] + wsum[3]) / (double)(s1 - s0);
 }
 
 }  // namespace
 
 hipError_t launch_front_psd(const RunDev &r, int dim, const double *h, int axis, int index,
                             double *out, hipStream_t st) {
-    int len, nslice;
-    int64_t step, stride;
-    if (axis == 0) {            // rows along x, one per y
-        len = r.nx;
-        nslice = dim == 3 ? r.ny : 1;
-        step = 1;
-        stride = r.nx;
-    } else {                    // rows along y, one per x
-        len = r.ny;
-        nslice = r.nx;
-        step = r.nx;
-        stride = 1;
-    }
+    // along x: rows one per y, samples contiguous; along y: rows one per x,
+    // samples nx apart
+    const int len = axis == 0 ? r.nx : r.ny;
+    const int nslice = axis == 0 ? (dim == 3 ? r.ny : 1) : r.nx;
+    const int64_t row_stride = axis == 0 ? r.nx : 1, step = axis == 0 ? 1 : r.nx;
     const int s0 = index < 0 ? 0 : index, s1 = index < 0 ? nslice : index + 1;
-    k_front_psd<<<(unsigned)(len / 2 + 1), 256, 0, st>>>(h, len, step, stride, s0, s1, out);
+    const unsigned grid = (unsigned)(len / 2 + 1);
+    const bool table = len <= kPsdTable;
+    const size_t lds = table ? (size_t)len * 2 * sizeof(double) : 0;
+    const bool lanes = s1 - s0 >= 64;
+    if (lanes && table)
+        k_front_psd_lanes<true><<<grid, 256, lds, st>>>(h, len, row_stride, step, s0, s1, out);
+    else if (lanes)
+        k_front_psd_lanes<false><<<grid, 256, 0, st>>>(h, len, row_stride, step, s0, s1, out);
+    else if (table)
+        k_front_psd_waves<true><<<grid, 256, lds, st>>>(h, len, row_stride, step, s0, s1, out);
+    else
+        k_front_psd_waves<false><<<grid, 256, 0, st>>>(h, len, row_stride, step, s0, s1, out);
     return hipGetLastError();
 }
 

@@ -51,6 +51,8 @@ CASES = [
     dict(lattice=19, nx=33, ny=17, nz=40, precision="fp32_shifted"),
     dict(nx=1, ny=6),
     dict(lattice=19, nx=1, ny=1, nz=6, precision="fp32_shifted"),
+    dict(nx=70, ny=700, precision="fp32_shifted"),                  # several rounds of the scan
+    dict(lattice=19, nx=130, ny=128, nz=70),                        # many columns, several rounds
 ]
 
 
@@ -200,6 +202,11 @@ PSD_CASES = [
     (dict(lattice=19, nx=33, ny=17, nz=40, precision="fp32_shifted"), 0, -1),
     (dict(lattice=19, nx=33, ny=17, nz=40, precision="fp32_shifted"), 1, -1),
     (dict(lattice=19, nx=300, ny=2, nz=6), 0, 1),
+    (dict(lattice=19, nx=3, ny=2100, nz=6), 1, -1),                 # row longer than the LDS table
+    (dict(lattice=19, nx=130, ny=128, nz=70), 1, 77),
+    (dict(lattice=19, nx=70, ny=30, nz=6), 1, -1),                  # one lane per row
+    (dict(lattice=19, nx=20, ny=65, nz=6), 0, -1),
+    (dict(lattice=19, nx=2049, ny=64, nz=6), 0, -1),                # lanes, no LDS table
 ]
 
 
@@ -228,7 +235,7 @@ def test_front_psd_matches_oracle(kw, axis, index):
     sol.close()
 
 
-@pytest.mark.parametrize("nx", [1, 2, 63, 64, 1024])
+@pytest.mark.parametrize("nx", [1, 2, 63, 64, 1024, 2048, 2049, 5000])
 def test_front_psd_of_seeded_heights(nx):
     """Seeded heights uploaded directly (not produced by the front kernel)."""
     import torch
@@ -282,3 +289,38 @@ def test_front_height_full_3d_size():
     mw = oracle.mass_below(oracle_cfg(cfg), c, wl.nz // 2)
     assert abs(m - mw) <= TOL64 * abs(mw)
     sol.close()
+
+
+@pytest.mark.parametrize("kw", [
+    dict(nx=37, ny=29, has_s=True, kappa_s=1e-3, gp_s=1e-4),
+    dict(nx=37, ny=29, precision="fp32_shifted"),
+    dict(lattice=19, nx=9, ny=7, nz=23, precision="fp64_shifted", has_s=True, kappa_s=1e-3,
+         gp_s=1e-4),
+    dict(lattice=19, nx=130, ny=128, nz=70),
+])
+@pytest.mark.parametrize("nsteps", [0, 3])
+def test_reduction_sums_match_oracle(kw, nsteps):
+    """The four FP64 sums (C, S, fluid mass, deposit) of lbw_reduce against
+    the oracle's sequential sums of the oracle's state, after an even and an
+    odd number of steps (the in-place populations sit in the other layout)."""
+    cfg = lbw.RunConfig(tau=0.6, vs=2e-3, kappa_c=1e-3, gp_c=1e-4, **kw)
+    rng = np.random.default_rng(21)
+    c0 = as_input(rng.uniform(0, 1, cfg.shape), cfg)
+    s0 = as_input(rng.uniform(0, 1, cfg.shape), cfg) if cfg.has_s else None
+    sol = lbw.Solver(cfg)
+    sol.set_field("c", c0)
+    if s0 is not None:
+        sol.set_field("s", s0)
+    sol.init_equilibrium()
+    sol.step(nsteps)
+    got = {w: sol.reduce(w)[0] for w in (lbw.MASS_C, lbw.MASS_FLUID, lbw.DEPOSIT)}
+    if cfg.has_s:
+        got[lbw.MASS_S] = sol.reduce(lbw.MASS_S)[0]
+    sol.close()
+    o = run_oracle(cfg, c0, s0, nsteps=nsteps)
+    want = oracle.sums(oracle_cfg(cfg), o["f"], o["c"], o.get("s"), o["deposit"])
+    tol = TOL64 if cfg.precision != "fp32_shifted" else 3e-6
+    for w, i in ((lbw.MASS_C, 0), (lbw.MASS_S, 1), (lbw.MASS_FLUID, 2), (lbw.DEPOSIT, 3)):
+        if w in got:
+            scale = max(abs(want[i]), 1e-300)
+            assert abs(got[w] - want[i]) <= tol * scale, (w, got[w], want[i])
