@@ -39,6 +39,7 @@ typedef struct {
     int n[3];
     long N;       /* nodes */
     long ncol;    /* bottom columns */
+    int ncls;     /* particle size classes (>= 1) */
     int c[MAXQ][3];
     double w[MAXQ];
     int opp[MAXQ];
@@ -102,6 +103,8 @@ static int setup(const orc_cfg *cfg, grid_t *g)
     if (g->dim == 2 && cfg->nz != 1) return -1;
     if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1) return -1;
     if (g->n[g->vert] < 6) return -1;
+    if (cfg->n_classes < 0 || cfg->n_classes > ORC_MAX_CLASSES) return -1;
+    g->ncls = cfg->n_classes > 1 ? cfg->n_classes : 1;
     g->N = (long)cfg->nx * cfg->ny * cfg->nz;
     g->ncol = (g->dim == 2) ? cfg->nx : (long)cfg->nx * cfg->ny;
     return 0;
@@ -127,13 +130,16 @@ static long column_of(const grid_t *g, const int p[3])
 /* ----------------------------------------------------------------------- */
 /* Moments, eq. 19-20 with the Guo shift rho u = sum f c + F/2 (eq. 22).    */
 /* Force (eq. 10, linearised in C and S): F = body + e_vert(-gp_c C - gp_s S) */
+/* with C the total over the size classes (eq. 11-12).                      */
 /* ----------------------------------------------------------------------- */
 static void force_at(const grid_t *g, const orc_cfg *cfg, const double *c,
                      const double *s, long k, double F[3])
 {
-    int d;
+    double ctot = 0.0;   /* total particle concentration, eq. 12 */
+    int d, i;
     for (d = 0; d < 3; d++) F[d] = cfg->body_force[d];
-    F[g->vert] += -cfg->gp_c * c[k];
+    for (i = 0; i < g->ncls; i++) ctot += c[(long)i * g->N + k];
+    F[g->vert] += -cfg->gp_c * ctot;
     if (cfg->has_s) F[g->vert] += -cfg->gp_s * s[k];
 }
 
@@ -443,6 +449,17 @@ int orc_moments(const orc_cfg *cfg, const double *f, const double *c,
     return 0;
 }
 
+/* Settling speed and diffusivity of size class i. */
+static double class_vs(const orc_cfg *cfg, int i)
+{
+    return cfg->n_classes > 1 ? cfg->vs_class[i] : cfg->vs;
+}
+
+static double class_kappa(const orc_cfg *cfg, int i)
+{
+    return cfg->n_classes > 1 ? cfg->kappa_class[i] : cfg->kappa_c;
+}
+
 int orc_rhs_c(const orc_cfg *cfg, const double *a, const double *u,
               double *out, double *outflow)
 {
@@ -458,7 +475,7 @@ int orc_run(const orc_cfg *cfg, double *f, double *c, double *s, double *dep,
 {
     grid_t g;
     long k, N;
-    int step, d;
+    int step, d, i;
     double *rho, *u, *F, *a1, *a2, *L, *cn, *out0, *out1, *out2, *fnew;
     if (setup(cfg, &g)) return -1;
     if (cfg->tau <= 0.5 || nsteps < 0) return -1;
@@ -493,23 +510,29 @@ int orc_run(const orc_cfg *cfg, double *f, double *c, double *s, double *dep,
                 }
             }
         }
-        /* 2. C: TVD-RK3 (S21-S23), velocity frozen over the substeps */
-        spatial_operator(&g, cfg, cfg->scheme_c, cfg->kappa_c, cfg->vs, 1, c, u, L, out0);
-        for (k = 0; k < N; k++) a1[k] = c[k] + L[k];
-        spatial_operator(&g, cfg, cfg->scheme_c, cfg->kappa_c, cfg->vs, 1, a1, u, L, out1);
-        for (k = 0; k < N; k++) a2[k] = 0.75 * c[k] + 0.25 * a1[k] + 0.25 * L[k];
-        spatial_operator(&g, cfg, cfg->scheme_c, cfg->kappa_c, cfg->vs, 1, a2, u, L, out2);
-        for (k = 0; k < N; k++)
-            cn[k] = c[k] / 3.0 + 2.0 / 3.0 * a2[k] + 2.0 / 3.0 * L[k];
-        if (dep)
-            for (k = 0; k < g.ncol; k++)
-                dep[k] += out0[k] / 6.0 + out1[k] / 6.0 + 2.0 / 3.0 * out2[k];
+        /* 2. each size class C_i: TVD-RK3 (S21-S23) with its own settling
+              speed and diffusivity, velocity frozen over the substeps; the
+              force above already holds the classes at level n */
+        for (i = 0; i < g.ncls; i++) {
+            double *ci = c + (long)i * N;
+            const double vs = class_vs(cfg, i), kappa = class_kappa(cfg, i);
+            spatial_operator(&g, cfg, cfg->scheme_c, kappa, vs, 1, ci, u, L, out0);
+            for (k = 0; k < N; k++) a1[k] = ci[k] + L[k];
+            spatial_operator(&g, cfg, cfg->scheme_c, kappa, vs, 1, a1, u, L, out1);
+            for (k = 0; k < N; k++) a2[k] = 0.75 * ci[k] + 0.25 * a1[k] + 0.25 * L[k];
+            spatial_operator(&g, cfg, cfg->scheme_c, kappa, vs, 1, a2, u, L, out2);
+            for (k = 0; k < N; k++)
+                cn[k] = ci[k] / 3.0 + 2.0 / 3.0 * a2[k] + 2.0 / 3.0 * L[k];
+            if (dep)
+                for (k = 0; k < g.ncol; k++)
+                    dep[(long)i * g.ncol + k] += out0[k] / 6.0 + out1[k] / 6.0 + 2.0 / 3.0 * out2[k];
+            for (k = 0; k < N; k++) ci[k] = cn[k];
+        }
         /* 3. S: forward Euler, first-order upwind, no settling, closed walls */
         if (cfg->has_s) {
             spatial_operator(&g, cfg, 2, cfg->kappa_s, 0.0, 0, s, u, L, NULL);
             for (k = 0; k < N; k++) s[k] = s[k] + L[k];
         }
-        for (k = 0; k < N; k++) c[k] = cn[k];
         /* 4-5. collide and stream */
         if (!cfg->frozen) {
             collide_stream(&g, cfg, f, rho, u, F, fnew);
@@ -654,7 +677,7 @@ int orc_adjoint_step(const orc_cfg *cfg, const double *f_n, const double *c_n,
     double *rho, *u, *F, *a1, *a2, *L, *ubar, *abar1, *abar2, *lam, vsb = 0.0;
     const double vs = cfg->vs;
     if (setup(cfg, &g)) return -1;
-    if (cfg->scheme_c != 0 || cfg->has_s || cfg->shifted < 0) return -1;
+    if (cfg->scheme_c != 0 || cfg->has_s || cfg->shifted < 0 || g.ncls > 1) return -1;
     if (cfg->frozen ? !u_in : (!f_n || !fbar_next || !fbar)) return -1;
     N = g.N;
     rho = (double *)calloc(N, sizeof(double));
@@ -779,6 +802,16 @@ int orc_adjoint_step(const orc_cfg *cfg, const double *f_n, const double *c_n,
     return 0;
 }
 
+/* Total particle concentration (eq. 12) at node k: the sum over the size
+ * classes in class order. */
+static double total_c(const grid_t *g, const double *c, long k)
+{
+    double t = 0.0;
+    int i;
+    for (i = 0; i < g->ncls; i++) t += c[(long)i * g->N + k];
+    return t;
+}
+
 int orc_front_height(const orc_cfg *cfg, const double *c, double thr, double *out)
 {
     grid_t g;
@@ -790,12 +823,12 @@ int orc_front_height(const orc_cfg *cfg, const double *c, double thr, double *ou
     for (col = 0; col < g.ncol; col++) {
         double h = (double)nv;               /* no cell reaches thr */
         for (v = 0; v < nv; v++) {
-            double cv = c[col + (long)v * plane];
+            double cv = total_c(&g, c, col + (long)v * plane);
             if (cv >= thr) {
                 if (v == 0) {
                     h = 0.0;
                 } else {
-                    double cb = c[col + (long)(v - 1) * plane];
+                    double cb = total_c(&g, c, col + (long)(v - 1) * plane);
                     /* crossing between the centres of cells v-1 and v */
                     h = (double)(v - 1) + 0.5 + (thr - cb) / (cv - cb);
                 }
@@ -811,13 +844,14 @@ int orc_mass_below(const orc_cfg *cfg, const double *c, int plane, double *out)
 {
     grid_t g;
     long k, n;
-    int nv;
+    int nv, i;
     if (setup(cfg, &g)) return -1;
     nv = g.n[g.dim - 1];
     if (plane < 0 || plane > nv) return -1;
     n = (long)plane * g.ncol;
     *out = 0.0;
-    for (k = 0; k < n; k++) *out += c[k];
+    for (i = 0; i < g.ncls; i++)             /* every size class */
+        for (k = 0; k < n; k++) *out += c[(long)i * g.N + k];
     return 0;
 }
 
@@ -869,7 +903,7 @@ int orc_sums(const orc_cfg *cfg, const double *f, const double *c,
     int i;
     if (setup(cfg, &g)) return -1;
     out[0] = out[1] = out[2] = out[3] = 0.0;
-    for (k = 0; k < g.N; k++) out[0] += c[k];
+    for (k = 0; k < (long)g.ncls * g.N; k++) out[0] += c[k];   /* every size class */
     if (s)
         for (k = 0; k < g.N; k++) out[1] += s[k];
     if (f)
@@ -879,6 +913,6 @@ int orc_sums(const orc_cfg *cfg, const double *f, const double *c,
             out[2] += r;
         }
     if (dep)
-        for (k = 0; k < g.ncol; k++) out[3] += dep[k];
+        for (k = 0; k < (long)g.ncls * g.ncol; k++) out[3] += dep[k];
     return 0;
 }

@@ -28,6 +28,15 @@
 extern "C" {
 #endif
 
+#define ORC_MAX_CLASSES 8
+
+/* With n_classes >= 2 there are that many particle size classes (eq. 11-12):
+ * each has its own concentration field, settling speed vs_class[i] and
+ * diffusivity kappa_class[i] and obeys the C equation on its own; the force
+ * uses the total concentration, -gp_c * sum_i C_i.  c then holds the class
+ * fields one after the other (n_classes * N values) and the deposit one
+ * counter per class and bottom column (n_classes * ncol).  n_classes 0 or 1:
+ * a single class with vs and kappa_c. */
 typedef struct {
     int32_t q;             /* 9 (D2Q9, 2D) or 19 (D3Q19, 3D) */
     int32_t nx, ny, nz;    /* nz == 1 in 2D */
@@ -36,7 +45,7 @@ typedef struct {
     int32_t scheme_c;      /* 0 WENO5-JS, 1 WENO3-JS, 2 first-order upwind */
     int32_t has_s;         /* second scalar S (upwind, forward Euler) */
     int32_t shifted;       /* populations stored as g_i = f_i - w_i */
-    int32_t reserved;
+    int32_t n_classes;     /* particle size classes, 0..ORC_MAX_CLASSES (0, 1: one) */
     double tau;            /* BGK relaxation time, > 1/2 */
     double body_force[3];  /* constant force density */
     double u_top[3];       /* top-wall velocity (moving lid) */
@@ -44,6 +53,8 @@ typedef struct {
     double kappa_c, gp_c;  /* C diffusivity; vertical force -gp_c*C */
     double kappa_s, gp_s;  /* S diffusivity; vertical force -gp_s*S */
     double weno_eps;       /* WENO regularisation epsilon */
+    double vs_class[ORC_MAX_CLASSES];    /* per-class settling speed (n_classes >= 2) */
+    double kappa_class[ORC_MAX_CLASSES]; /* per-class diffusivity (n_classes >= 2) */
 } orc_cfg;
 
 /* Lattice table in the documented order: c[q][3], w[q], opp[q]. */
@@ -61,8 +72,8 @@ int orc_moments(const orc_cfg *cfg, const double *f, const double *c,
 int orc_rhs_c(const orc_cfg *cfg, const double *a, const double *u,
               double *out, double *outflow);
 
-/* Advance nsteps coupled steps in place.  dep has one entry per bottom
- * column (nx in 2D, nx*ny in 3D).  u_in is read in frozen mode; u_out
+/* Advance nsteps coupled steps in place.  dep has one entry per size class
+ * and bottom column (nx in 2D, nx*ny in 3D).  u_in is read in frozen mode; u_out
  * (optional) receives the node velocity used by the last step. */
 int orc_run(const orc_cfg *cfg, double *f, double *c, double *s, double *dep,
             const double *u_in, double *u_out, int32_t nsteps);
@@ -74,23 +85,26 @@ int orc_run(const orc_cfg *cfg, double *f, double *c, double *s, double *dep,
  * adjoints of f^n and C^n) and *vs_bar += dJ/dVs of this step.  In frozen
  * mode u_in is the node velocity and fbar/fbar_next are not used.  The upwind
  * side of every face is held at its forward choice. */
+/* (One size class only.) */
 int orc_adjoint_step(const orc_cfg *cfg, const double *f_n, const double *c_n,
                      const double *u_in, const double *fbar_next, const double *cbar_next,
                      double dep_bar, double *fbar, double *cbar, double *vs_bar);
 
-/* out[0..3] = sum C, sum S, sum rho, sum dep (plain sequential sums). */
+/* out[0..3] = sum C, sum S, sum rho, sum dep (plain sequential sums; C and
+ * dep over every size class). */
 int orc_sums(const orc_cfg *cfg, const double *f, const double *c,
              const double *s, const double *dep, double *out);
 
 /* Front of the particle field per bottom column (section "Comparison of
  * model results with predictions from linear stability analysis"): the
- * lowest height where C reaches thr, measured from the bottom wall (cell v
+ * lowest height where C (the total over the size classes) reaches thr, measured from the bottom wall (cell v
  * has its centre at height v + 1/2), linear between the two cells that
  * straddle thr; 0 if the bottom cell already holds C >= thr, the domain
  * height if no cell does.  out[ncol]. */
 int orc_front_height(const orc_cfg *cfg, const double *c, double thr, double *out);
 
-/* Particle mass (sum of C) in the planes below plane index `plane`, i.e. in
+/* Particle mass (sum of C, every size class) in the planes below plane
+ * index `plane`, i.e. in
  * the cells with vertical index v < plane (the mass whose change gives the
  * flux through a horizontal plane, eq. for J in section "Particle mass flux,
  * particle concentration in the lower layer and accumulation rate"). */

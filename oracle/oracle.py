@@ -33,17 +33,22 @@ def build() -> str:
     return _LIB
 
 
+MAX_CLASSES = 8
+
+
 class _Cfg(ctypes.Structure):
     _fields_ = [
         ("q", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
         ("nz", ctypes.c_int32), ("vert_periodic", ctypes.c_int32),
         ("frozen", ctypes.c_int32), ("scheme_c", ctypes.c_int32),
         ("has_s", ctypes.c_int32), ("shifted", ctypes.c_int32),
-        ("reserved", ctypes.c_int32), ("tau", ctypes.c_double),
+        ("n_classes", ctypes.c_int32), ("tau", ctypes.c_double),
         ("body_force", ctypes.c_double * 3), ("u_top", ctypes.c_double * 3),
         ("vs", ctypes.c_double), ("kappa_c", ctypes.c_double), ("gp_c", ctypes.c_double),
         ("kappa_s", ctypes.c_double), ("gp_s", ctypes.c_double),
         ("weno_eps", ctypes.c_double),
+        ("vs_class", ctypes.c_double * MAX_CLASSES),
+        ("kappa_class", ctypes.c_double * MAX_CLASSES),
     ]
 
 
@@ -70,6 +75,16 @@ class OracleConfig:
     kappa_s: float = 0.0
     gp_s: float = 0.0
     weno_eps: float = 1e-6
+    # particle size classes (eq. 11-12): with n_classes >= 2 class i settles
+    # at vs_class[i] and diffuses with kappa_class[i]; c is then
+    # c[n_classes, nz, ny, nx] and the deposit dep[n_classes, ncol]
+    n_classes: int = 1
+    vs_class: tuple = ()
+    kappa_class: tuple = ()
+
+    @property
+    def ncls(self) -> int:
+        return max(1, self.n_classes)
 
     @property
     def dim(self) -> int:
@@ -96,6 +111,14 @@ class OracleConfig:
         c.u_top = (ctypes.c_double * 3)(*self.u_top)
         c.vs, c.kappa_c, c.gp_c = self.vs, self.kappa_c, self.gp_c
         c.kappa_s, c.gp_s, c.weno_eps = self.kappa_s, self.gp_s, self.weno_eps
+        if not 0 <= self.n_classes <= MAX_CLASSES:
+            raise ValueError(f"n_classes must lie in [0, {MAX_CLASSES}]")
+        c.n_classes = self.n_classes if self.n_classes > 1 else 0
+        if self.n_classes > 1:
+            if len(self.vs_class) != self.n_classes or len(self.kappa_class) != self.n_classes:
+                raise ValueError("vs_class and kappa_class need one value per class")
+            c.vs_class = (ctypes.c_double * MAX_CLASSES)(*self.vs_class)
+            c.kappa_class = (ctypes.c_double * MAX_CLASSES)(*self.kappa_class)
         return c
 
 
@@ -177,7 +200,10 @@ def run(cfg: OracleConfig, f, c, s=None, dep=None, u_in=None, nsteps=1, want_u=F
     f = None if f is None else np.ascontiguousarray(f, np.float64).copy()
     c = np.ascontiguousarray(c, np.float64).copy()
     s = None if s is None else np.ascontiguousarray(s, np.float64).copy()
-    dep = np.zeros(cfg.ncol, np.float64) if dep is None else np.ascontiguousarray(dep, np.float64).copy()
+    dep_shape = (cfg.ncol,) if cfg.ncls == 1 else (cfg.ncls, cfg.ncol)
+    dep = np.zeros(dep_shape, np.float64) if dep is None else np.ascontiguousarray(dep, np.float64).copy()
+    if c.size != cfg.ncls * cfg.nx * cfg.ny * cfg.nz or dep.size != cfg.ncls * cfg.ncol:
+        raise ValueError("c needs n_classes fields and dep n_classes * ncol counters")
     u_in = None if u_in is None else np.ascontiguousarray(u_in, np.float64)
     u_out = np.zeros((cfg.dim,) + cfg.shape, np.float64) if want_u else None
     if f is None:
