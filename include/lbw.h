@@ -64,7 +64,8 @@
 extern "C" {
 #endif
 
-#define LBW_ABI_VERSION 1
+#define LBW_ABI_VERSION 2
+#define LBW_MAX_CLASSES 8   /* particle size classes per run */
 
 enum {
     LBW_OK = 0,
@@ -94,7 +95,12 @@ typedef struct {
                               the populations are not touched) */
     int32_t scheme_c;      /* LBW_WENO5 | LBW_WENO3 | LBW_UPWIND1 for C */
     int32_t has_s;         /* 1: transport S and add its buoyancy */
-    int32_t reserved;      /* must be 0 */
+    int32_t n_classes;     /* particle size classes (eq. 11-12): 0 or 1 for one
+                              class with vs and kappa_c; 2..LBW_MAX_CLASSES:
+                              class i settles at vs_class[i] and diffuses with
+                              kappa_class[i] (vs and kappa_c must then be 0),
+                              each obeys the C equation on its own, and the
+                              buoyancy is that of the total, -gp_c sum_i C_i */
     double tau;            /* BGK relaxation time, > 1/2 (eq. 21) */
     double body_force[3];  /* constant force density */
     double u_top[3];       /* top-wall velocity (moving lid) */
@@ -102,6 +108,8 @@ typedef struct {
     double kappa_c, gp_c;  /* C diffusivity; vertical force -gp_c*C */
     double kappa_s, gp_s;  /* S diffusivity; vertical force -gp_s*S */
     double weno_eps;       /* WENO regularisation, > 0 (1e-6 typical) */
+    double vs_class[LBW_MAX_CLASSES];    /* n_classes >= 2: settling speeds */
+    double kappa_class[LBW_MAX_CLASSES]; /* n_classes >= 2: diffusivities */
 } lbw_config;
 
 /* One run's device buffers (caller-owned, element type per precision:
@@ -109,14 +117,15 @@ typedef struct {
  * double).  Unused pointers may be NULL. */
 typedef struct {
     void *f;           /* Q*N populations (in place, AA order) */
-    void *c;           /* N: C */
-    void *c_s1;        /* N: RK stage work buffer */
-    void *c_s2;        /* N: RK stage work buffer */
+    void *c;           /* N per size class, class after class: C_i */
+    void *c_s1;        /* N per size class: RK stage work buffer */
+    void *c_s2;        /* N per size class: RK stage work buffer */
     void *s;           /* N: S (has_s) */
     void *s_tmp;       /* N: S work buffer (has_s) */
     void *u;           /* dim*N: node velocity of the last step; input when
                           fluid_mode = LBW_FLUID_FROZEN */
-    double *deposit;   /* ncol: settled mass per bottom column (FP64) */
+    double *deposit;   /* ncol per size class, class after class: settled
+                          mass per bottom column (FP64) */
     void *scratch;     /* reduction partials, >= lbw_scratch_bytes() bytes */
     size_t scratch_bytes;
 } lbw_buffers;
@@ -133,8 +142,8 @@ typedef struct {
                               vertical axis is cut into slabs and the
                               collide-stream of step n+1 on a slab runs on a
                               second stream, overlapping the transport of step
-                              n on the slabs above it (single run with walls;
-                              a periodic vertical axis takes variant 0) */
+                              n on the slabs above it (single run with walls
+                              and one size class; other runs take variant 0) */
     int32_t graph;         /* 1: lbw_step replays a captured HIP graph of two
                               steps (needs a non-null stream; the graph is
                               runtime-owned and rebuilt after lbw_set_launch) */
@@ -193,8 +202,9 @@ int lbw_steps_done(const lbw_handle *h, int64_t *out);
 
 /* Copy field `field` of run `run` in canonical layout into the device buffer
  * dst (populations: pre-collision f_i(x, t) -- or g_i for the shifted forms --
- * in f[q][k] order; u: the last step's node velocity; STAGE1, STAGE2: the
- * last step's first and second RK stages of C; deposit: FP64 ncol).
+ * in f[q][k] order; C: every size class, class after class; u: the last
+ * step's node velocity; STAGE1, STAGE2: the last step's first and second RK
+ * stages of C, every class; deposit: FP64 ncol per class).
  * Asynchronous on the handle's stream. */
 int lbw_export(lbw_handle *h, int32_t run, int32_t field, void *dst);
 
@@ -219,16 +229,18 @@ int lbw_import(lbw_handle *h, int32_t run, int32_t field, const void *src);
  * stream).  Returns LBW_ERR_INVAL for any other field. */
 int lbw_rebind(lbw_handle *h, int32_t run, int32_t field, void *ptr);
 
-/* FP64 sums per run into out_host[nbatch]: LBW_MASS_C (sum C), LBW_MASS_S
- * (sum S), LBW_MASS_FLUID (sum rho), LBW_DEPOSIT (sum of the deposit
- * counters), the particle mass and deposited mass m_b of section 4.2.3.
+/* FP64 sums per run into out_host[nbatch]: LBW_MASS_C (sum C over every
+ * size class), LBW_MASS_S (sum S), LBW_MASS_FLUID (sum rho), LBW_DEPOSIT
+ * (sum of the deposit counters of every class), the particle mass and
+ * deposited mass m_b of section 4.2.3.
  * Wavefront shuffles, per-block partials, then a fixed-order final pass:
  * the result is bitwise reproducible.  Synchronises the stream.  Returns
  * LBW_ERR_NONFINITE if any sum is NaN or Inf (the values are still written). */
 int lbw_reduce(lbw_handle *h, int32_t what, double *out_host);
 
 /* Particle mass below a horizontal plane, per run, into out_host[nbatch]:
- * the FP64 sum of C over the cells whose vertical index v is below `plane`
+ * the FP64 sum of C (every size class) over the cells whose vertical index
+ * v is below `plane`
  * (the first plane * ncol nodes, planes being the slowest axis).  Its change
  * over an interval divided by the plane's area and the interval gives the
  * particle mass flux J through that plane (section "Particle mass flux,
@@ -242,7 +254,8 @@ int lbw_mass_below(lbw_handle *h, int32_t plane, double *out_host);
 /* Height of the particle front in every bottom column of run `run`, into the
  * caller's device array out_dev[ncol] (FP64; ncol = nx in 2D, nx*ny in 3D,
  * column index x + nx*y): scanning each column upward from the bottom wall,
- * the height where C first reaches `threshold`, measured from the wall with
+ * the height where C (the total over the size classes, summed in FP64 in
+ * class order) first reaches `threshold`, measured from the wall with
  * the centre of cell v at v + 1/2 and linear between the two cells that
  * straddle the threshold; 0 if the bottom cell already reaches it and the
  * domain height nv if no cell does.  Its lateral Fourier modes give the
@@ -294,7 +307,8 @@ int lbw_adjoint_work_bytes(const lbw_handle *h, int32_t run, size_t *out_bytes);
  *                FP64 per-node accumulator of dJ/dVs across steps;
  *   vs_bar_dev   NULL, or a device FP64 scalar: the accumulator is then
  *                summed in a fixed order, added to *vs_bar_dev and cleared.
- * WENO5 without S only (LBW_ERR_UNSUPPORTED otherwise).  In frozen mode the
+ * WENO5 without S and with one size class only (LBW_ERR_UNSUPPORTED
+ * otherwise).  In frozen mode the
  * run's u buffer is the (constant) velocity and the population arguments may
  * be NULL.  Asynchronous on the handle's stream; independent of the handle's
  * own state buffers apart from that velocity. */

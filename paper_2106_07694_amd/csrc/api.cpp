@@ -40,10 +40,12 @@ struct lbw_handle {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool sflip = false;              // S currently lives in s_tmp
     int num_cu = 256;
-    // batched mode (nbatch > 1): tables in run 0's scratch
-    lbw::RunDev *d_runs = nullptr;
+    // batched mode (nbatch > 1): tables in run 0's scratch.  The transport
+    // walks one entry per run and size class (`views`).
+    lbw::RunDev *d_runs = nullptr, *d_views = nullptr;
     int *d_blk = nullptr, *d_tiles = nullptr;
     std::vector<int> blk_start, tile_start;
+    std::vector<lbw::RunDev> views;
     int grid_lbm = 0, grid_tr = 0;
     // graph replay
     hipGraph_t graph = nullptr;
@@ -73,23 +75,33 @@ int hip_fail(hipError_t e, const char *what) {
 size_t elem_size(int precision) { return precision == LBW_FP32_SHIFTED ? 4 : 8; }
 
 struct ScratchLayout {
-    size_t out, runs, blk, tiles, total;
+    size_t out, runs, blk, views, tiles, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-ScratchLayout scratch_layout(int nbatch) {
+int classes_of(const lbw_config &c) { return c.n_classes > 1 ? c.n_classes : 1; }
+
+// nviews: runs times their size classes (the transport's work items)
+ScratchLayout scratch_layout(int nbatch, int nviews) {
     ScratchLayout L;
     L.out = sizeof(double) * (size_t)nbatch * lbw::kReduceBlocks;
     L.runs = align256(L.out + sizeof(double) * nbatch);
     if (nbatch > 1) {
         L.blk = align256(L.runs + sizeof(lbw::RunDev) * nbatch);
-        L.tiles = align256(L.blk + sizeof(int) * (nbatch + 1));
-        L.total = align256(L.tiles + sizeof(int) * (nbatch + 1));
+        L.views = align256(L.blk + sizeof(int) * (nbatch + 1));
+        L.tiles = align256(L.views + sizeof(lbw::RunDev) * nviews);
+        L.total = align256(L.tiles + sizeof(int) * (nviews + 1));
     } else {
-        L.blk = L.tiles = L.total = L.runs;
+        L.blk = L.views = L.tiles = L.total = L.runs;
     }
     return L;
+}
+
+int count_views(const lbw_config *cfgs, int nbatch) {
+    int n = 0;
+    for (int b = 0; b < nbatch; ++b) n += classes_of(cfgs[b]);
+    return n;
 }
 
 // The run as the kernels must see it now (S and its work buffer swap roles
@@ -98,6 +110,25 @@ lbw::RunDev current(const lbw_handle *h, int b) {
     lbw::RunDev r = h->run[b];
     if (h->sflip) std::swap(r.s, r.s2);
     return r;
+}
+
+// Size class i of a run as the transport kernels see it: its C field and
+// RK stage buffers, its deposit counters, its settling speed and
+// diffusivity; the S update rides with class 0 only.  Classes share nothing
+// they write, so the batched transport runs them all in one launch.
+lbw::RunDev class_view(const lbw_handle *h, const lbw::RunDev &r, int b, int i) {
+    if (r.ncls <= 1) return r;
+    const lbw_config &c = h->cfg[b];
+    lbw::RunDev v = r;
+    const size_t off = (size_t)i * r.N * (h->precision == LBW_FP32_SHIFTED ? 4 : 8);
+    v.c = (char *)r.c + off;
+    v.c1 = (char *)r.c1 + off;
+    v.c2 = (char *)r.c2 + off;
+    v.dep = r.dep + (size_t)i * r.ncol;
+    v.vs = c.vs_class[i];
+    v.kappa_c = c.kappa_class[i];
+    if (i > 0) v.has_s = 0;
+    return v;
 }
 
 void release_graph(lbw_handle *h) {
@@ -113,25 +144,35 @@ int upload_tables(lbw_handle *h) {
     if (h->nbatch < 2) return LBW_OK;
     const int block = h->launch.lbm_block;
     h->blk_start.assign(h->nbatch + 1, 0);
-    h->tile_start.assign(h->nbatch + 1, 0);
+    h->views.clear();
     for (int b = 0; b < h->nbatch; ++b) {
         const int64_t nb = (h->run[b].N + block - 1) / block;
-        const int64_t nt = lbw::transport_tiles(h->dim, h->run[b], h->launch);
-        if ((int64_t)h->blk_start[b] + nb > 0x7fffffff || (int64_t)h->tile_start[b] + nt > 0x7fffffff)
+        if ((int64_t)h->blk_start[b] + nb > 0x7fffffff)
             return fail(LBW_ERR_INVAL, "batched work list too large");
         h->blk_start[b + 1] = h->blk_start[b] + (int)nb;
-        h->tile_start[b + 1] = h->tile_start[b] + (int)nt;
+        for (int i = 0; i < h->run[b].ncls; ++i) h->views.push_back(class_view(h, h->run[b], b, i));
+    }
+    const int nviews = (int)h->views.size();
+    h->tile_start.assign(nviews + 1, 0);
+    for (int v = 0; v < nviews; ++v) {
+        const int64_t nt = lbw::transport_tiles(h->dim, h->views[v], h->launch);
+        if ((int64_t)h->tile_start[v] + nt > 0x7fffffff)
+            return fail(LBW_ERR_INVAL, "batched work list too large");
+        h->tile_start[v + 1] = h->tile_start[v] + (int)nt;
     }
     const int per_cu_lbm = 2048 / block;
     h->grid_lbm = std::min(h->blk_start[h->nbatch], h->num_cu * per_cu_lbm);
-    h->grid_tr = std::min(h->tile_start[h->nbatch], h->num_cu * 8);
+    h->grid_tr = std::min(h->tile_start[nviews], h->num_cu * 8);
     hipError_t e = hipMemcpyAsync(h->d_runs, h->run.data(), sizeof(lbw::RunDev) * h->nbatch,
                                   hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(h->d_blk, h->blk_start.data(), sizeof(int) * (h->nbatch + 1),
                            hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(h->d_tiles, h->tile_start.data(), sizeof(int) * (h->nbatch + 1),
+        e = hipMemcpyAsync(h->d_views, h->views.data(), sizeof(lbw::RunDev) * nviews,
+                           hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->d_tiles, h->tile_start.data(), sizeof(int) * (nviews + 1),
                            hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // host tables may change later
     return e == hipSuccess ? LBW_OK : hip_fail(e, "upload of the batched work lists");
@@ -142,7 +183,8 @@ int validate(const lbw_config &c, const lbw_buffers &b, int idx) {
         return fail(LBW_ERR_INVAL, "run %d: lattice must be LBW_D2Q9 or LBW_D3Q19", idx);
     if (c.precision != LBW_FP64 && c.precision != LBW_FP32_SHIFTED && c.precision != LBW_FP64_SHIFTED)
         return fail(LBW_ERR_INVAL, "run %d: unknown precision %d", idx, c.precision);
-    if (c.reserved != 0) return fail(LBW_ERR_INVAL, "run %d: reserved field must be 0", idx);
+    if (c.n_classes < 0 || c.n_classes > LBW_MAX_CLASSES)
+        return fail(LBW_ERR_INVAL, "run %d: n_classes must lie in [0, %d]", idx, LBW_MAX_CLASSES);
     if (c.nx < 1 || c.ny < 1 || c.nz < 1) return fail(LBW_ERR_INVAL, "run %d: grid sizes must be >= 1", idx);
     const int dim = c.lattice == LBW_D2Q9 ? 2 : 3;
     if (dim == 2 && c.nz != 1) return fail(LBW_ERR_INVAL, "run %d: D2Q9 needs nz == 1", idx);
@@ -163,6 +205,17 @@ int validate(const lbw_config &c, const lbw_buffers &b, int idx) {
     const double kmax = 1.0 / (2.0 * dim);
     if (!(c.kappa_c >= 0.0) || c.kappa_c > kmax)
         return fail(LBW_ERR_INVAL, "run %d: kappa_c must lie in [0, %g]", idx, kmax);
+    if (c.n_classes > 1) {
+        if (c.vs != 0.0 || c.kappa_c != 0.0)
+            return fail(LBW_ERR_INVAL, "run %d: with size classes set vs_class and kappa_class "
+                                       "(vs and kappa_c must be 0)", idx);
+        for (int i = 0; i < c.n_classes; ++i) {
+            if (!(c.vs_class[i] >= 0.0) || c.vs_class[i] > 1.0)
+                return fail(LBW_ERR_INVAL, "run %d: vs_class[%d] must lie in [0, 1] (CFL)", idx, i);
+            if (!(c.kappa_class[i] >= 0.0) || c.kappa_class[i] > kmax)
+                return fail(LBW_ERR_INVAL, "run %d: kappa_class[%d] must lie in [0, %g]", idx, i, kmax);
+        }
+    }
     if (c.has_s && (!(c.kappa_s >= 0.0) || c.kappa_s > kmax))
         return fail(LBW_ERR_INVAL, "run %d: kappa_s must lie in [0, %g]", idx, kmax);
     if (!(c.weno_eps > 0.0)) return fail(LBW_ERR_INVAL, "run %d: weno_eps must be > 0", idx);
@@ -199,6 +252,7 @@ lbw::RunDev make_run(const lbw_config &c, const lbw_buffers &b) {
     r.ncol = c.lattice == LBW_D2Q9 ? c.nx : (int64_t)c.nx * c.ny;
     r.has_s = c.has_s ? 1 : 0;
     r.scheme = c.scheme_c;
+    r.ncls = classes_of(c);
     r.tau = c.tau;
     r.omega = 1.0 / c.tau;
     r.guo = 1.0 - 0.5 / c.tau;
@@ -231,7 +285,7 @@ const char *lbw_last_error(void) { return g_err.c_str(); }
 
 int lbw_scratch_bytes(const lbw_config *cfgs, int32_t nbatch, size_t *out_bytes) {
     if (!cfgs || nbatch < 1 || !out_bytes) return fail(LBW_ERR_INVAL, "bad arguments");
-    *out_bytes = scratch_layout(nbatch).total;
+    *out_bytes = scratch_layout(nbatch, count_views(cfgs, nbatch)).total;
     return LBW_OK;
 }
 
@@ -270,7 +324,7 @@ int lbw_create(const lbw_config *cfgs, const lbw_buffers *bufs, int32_t nbatch, 
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
         h->num_cu = ncu;
     if (nbatch > 1) {
-        const ScratchLayout L = scratch_layout(nbatch);
+        const ScratchLayout L = scratch_layout(nbatch, count_views(cfgs, nbatch));
         if (!bufs[0].scratch || bufs[0].scratch_bytes < L.total) {
             delete h;
             return fail(LBW_ERR_INVAL, "batched runs need %zu bytes of scratch in run 0", L.total);
@@ -278,6 +332,7 @@ int lbw_create(const lbw_config *cfgs, const lbw_buffers *bufs, int32_t nbatch, 
         char *base = (char *)bufs[0].scratch;
         h->d_runs = (lbw::RunDev *)(base + L.runs);
         h->d_blk = (int *)(base + L.blk);
+        h->d_views = (lbw::RunDev *)(base + L.views);
         h->d_tiles = (int *)(base + L.tiles);
         const int rc = upload_tables(h);
         if (rc) {
@@ -411,10 +466,10 @@ int enqueue_step(lbw_handle *h) {
     sp = span_open(h, LBW_PHASE_TRANSPORT, h->stream);
     if (h->nbatch > 1 && h->launch.variant == 0) {
         lbw::BatchArgs a;
-        a.runs = h->d_runs;
+        a.runs = h->d_views;
         a.tile_start = h->d_tiles;
-        a.host_runs = h->run.data();
-        a.nbatch = h->nbatch;
+        a.host_runs = h->views.data();
+        a.nbatch = (int)h->views.size();
         a.chunk = lbw::resolve_tile_shape(h->dim, h->launch).chunk;
         a.sflip = h->sflip ? 1 : 0;
         a.grid = h->grid_tr;
@@ -422,8 +477,12 @@ int enqueue_step(lbw_handle *h) {
         if (e != hipSuccess) return hip_fail(e, "batched transport launch");
     } else {
         for (int b = 0; b < h->nbatch; ++b) {
-            hipError_t e = lbw::launch_transport(h->dim, h->precision, current(h, b), h->launch, h->stream);
-            if (e != hipSuccess) return hip_fail(e, "transport launch");
+            const lbw::RunDev r = current(h, b);
+            for (int i = 0; i < r.ncls; ++i) {
+                hipError_t e = lbw::launch_transport(h->dim, h->precision, class_view(h, r, b, i),
+                                                     h->launch, h->stream);
+                if (e != hipSuccess) return hip_fail(e, "transport launch");
+            }
         }
     }
     if ((rc = span_close(h, sp, h->stream))) return rc;
@@ -564,7 +623,7 @@ int lbw_step(lbw_handle *h, int32_t nsteps) {
     int rc;
     // the slab order assumes walls: a periodic vertical axis couples the first
     // and last slabs, so such runs take the sequential order
-    if (h->launch.variant == 2 && !h->run[0].vper && nsteps > 0) {
+    if (h->launch.variant == 2 && !h->run[0].vper && h->run[0].ncls == 1 && nsteps > 0) {
         if ((rc = ensure_pipeline(h, 1))) return rc;
         // B starts after everything already queued on A, A ends after B
         hipError_t e = hipEventRecord(h->ev_fork, h->stream);
@@ -606,8 +665,8 @@ int lbw_adjoint_step(lbw_handle *h, int32_t run, const void *f_n, const void *c_
                      void *cbar, double *vs_bar_dev, void *work, size_t work_bytes) {
     int rc = check_run(h, run);
     if (rc) return rc;
-    if (h->scheme != LBW_WENO5 || h->has_s)
-        return fail(LBW_ERR_UNSUPPORTED, "the adjoint covers WENO5 transport without S");
+    if (h->scheme != LBW_WENO5 || h->has_s || h->run[run].ncls > 1)
+        return fail(LBW_ERR_UNSUPPORTED, "the adjoint covers WENO5 transport without S, one size class");
     const bool frozen = h->fluid_mode == LBW_FLUID_FROZEN;
     if (!c_n || !cbar_next || !cbar || !work) return fail(LBW_ERR_INVAL, "NULL required argument");
     if ((a1_n == nullptr) != (a2_n == nullptr))
@@ -675,7 +734,9 @@ int lbw_export(lbw_handle *h, int32_t run, int32_t field, void *dst) {
             if (h->fluid_mode != LBW_FLUID_LBM) return fail(LBW_ERR_INVAL, "frozen fluid has no populations");
             e = lbw::launch_export_f(h->q, h->precision, r, h->odd, dst, h->stream);
             break;
-        case LBW_FIELD_C: e = hipMemcpyAsync(dst, r.c, r.N * es, hipMemcpyDeviceToDevice, h->stream); break;
+        case LBW_FIELD_C:
+            e = hipMemcpyAsync(dst, r.c, r.ncls * r.N * es, hipMemcpyDeviceToDevice, h->stream);
+            break;
         case LBW_FIELD_S:
             if (!h->has_s) return fail(LBW_ERR_INVAL, "run has no S");
             e = hipMemcpyAsync(dst, current(h, run).s, r.N * es, hipMemcpyDeviceToDevice, h->stream);
@@ -684,10 +745,15 @@ int lbw_export(lbw_handle *h, int32_t run, int32_t field, void *dst) {
             e = hipMemcpyAsync(dst, r.u, (size_t)h->dim * r.N * es, hipMemcpyDeviceToDevice, h->stream);
             break;
         case LBW_FIELD_DEPOSIT:
-            e = hipMemcpyAsync(dst, r.dep, r.ncol * sizeof(double), hipMemcpyDeviceToDevice, h->stream);
+            e = hipMemcpyAsync(dst, r.dep, r.ncls * r.ncol * sizeof(double), hipMemcpyDeviceToDevice,
+                               h->stream);
             break;
-        case LBW_FIELD_STAGE1: e = hipMemcpyAsync(dst, r.c1, r.N * es, hipMemcpyDeviceToDevice, h->stream); break;
-        case LBW_FIELD_STAGE2: e = hipMemcpyAsync(dst, r.c2, r.N * es, hipMemcpyDeviceToDevice, h->stream); break;
+        case LBW_FIELD_STAGE1:
+            e = hipMemcpyAsync(dst, r.c1, r.ncls * r.N * es, hipMemcpyDeviceToDevice, h->stream);
+            break;
+        case LBW_FIELD_STAGE2:
+            e = hipMemcpyAsync(dst, r.c2, r.ncls * r.N * es, hipMemcpyDeviceToDevice, h->stream);
+            break;
         default: return fail(LBW_ERR_INVAL, "unknown field %d", field);
     }
     return e == hipSuccess ? LBW_OK : hip_fail(e, "export");
@@ -728,7 +794,9 @@ int lbw_import(lbw_handle *h, int32_t run, int32_t field, const void *src) {
             if (h->fluid_mode != LBW_FLUID_LBM) return fail(LBW_ERR_INVAL, "frozen fluid has no populations");
             e = lbw::launch_import_f(h->q, h->precision, r, h->odd, src, h->stream);
             break;
-        case LBW_FIELD_C: e = hipMemcpyAsync(r.c, src, r.N * es, hipMemcpyDeviceToDevice, h->stream); break;
+        case LBW_FIELD_C:
+            e = hipMemcpyAsync(r.c, src, r.ncls * r.N * es, hipMemcpyDeviceToDevice, h->stream);
+            break;
         case LBW_FIELD_S:
             if (!h->has_s) return fail(LBW_ERR_INVAL, "run has no S");
             e = hipMemcpyAsync(current(h, run).s, src, r.N * es, hipMemcpyDeviceToDevice, h->stream);
@@ -737,7 +805,8 @@ int lbw_import(lbw_handle *h, int32_t run, int32_t field, const void *src) {
             e = hipMemcpyAsync(r.u, src, (size_t)h->dim * r.N * es, hipMemcpyDeviceToDevice, h->stream);
             break;
         case LBW_FIELD_DEPOSIT:
-            e = hipMemcpyAsync(r.dep, src, r.ncol * sizeof(double), hipMemcpyDeviceToDevice, h->stream);
+            e = hipMemcpyAsync(r.dep, src, r.ncls * r.ncol * sizeof(double), hipMemcpyDeviceToDevice,
+                               h->stream);
             break;
         default: return fail(LBW_ERR_INVAL, "unknown field %d", field);
     }
@@ -760,7 +829,7 @@ int reduce_impl(lbw_handle *h, int32_t what, double *out_host, int plane) {
     hipError_t e = lbw::launch_reduce(h->q, h->precision, cur.data(), h->nbatch, what, h->odd,
                                       scratch, h->stream, plane);
     if (e != hipSuccess) return hip_fail(e, "reduce launch");
-    e = hipMemcpyAsync(out_host, (char *)b0.scratch + scratch_layout(h->nbatch).out,
+    e = hipMemcpyAsync(out_host, (char *)b0.scratch + scratch_layout(h->nbatch, 0).out,
                        sizeof(double) * h->nbatch, hipMemcpyDeviceToHost, h->stream);
     if (e != hipSuccess) return hip_fail(e, "reduce copy");
     e = hipStreamSynchronize(h->stream);

@@ -133,11 +133,14 @@ __device__ __forceinline__ void lbm_rho_u(const T (&fi)[Q], const T F[3], T &rho
 }
 
 // Force density at node k: body force plus the linear buoyancy of C (and S)
-// on the vertical axis (eq. 10 linearised).
+// on the vertical axis (eq. 10 linearised); with several particle size
+// classes C is their total, summed in class order (eq. 11-12).
 template <int D, typename T>
 __device__ __forceinline__ void lbm_force(const RunDev &r, const T *__restrict__ c,
                                           const T *__restrict__ s, int64_t k, T F[3]) {
-    T fv = -(T)r.gp_c * c[k];
+    T ctot = c[k];
+    for (int i = 1; i < r.ncls; ++i) ctot += c[k + (int64_t)i * r.N];
+    T fv = -(T)r.gp_c * ctot;
     if (r.has_s) fv -= (T)r.gp_s * s[k];
     F[0] = (T)r.body[0];
     F[1] = (T)r.body[1] + (D == 2 ? fv : (T)0);

@@ -55,6 +55,8 @@ struct RunDev {
     int64_t ncol;        // bottom columns
     int32_t has_s;
     int32_t scheme;
+    int32_t ncls;        // particle size classes: c holds ncls fields of N,
+    int32_t pad_;        // dep ncls * ncol counters, class after class
     double tau, omega, guo;          // 1/tau and 1 - 1/(2 tau)
     double body[3], utop[3];
     double vs, kappa_c, gp_c, kappa_s, gp_s, eps;
@@ -65,12 +67,14 @@ struct TileShape {
     int tx, ty, chunk;
 };
 
-// Arguments of the batched (persistent, work-list) transport launch.
+// Arguments of the batched (persistent, work-list) transport launch.  Its
+// entries are runs, or size classes of runs (one entry per class, the S
+// update carried by the first).
 struct BatchArgs {
-    const RunDev *runs;        // device copy of the run table
-    const int *tile_start;     // device prefix sum of tiles per run (nbatch + 1)
+    const RunDev *runs;        // device copy of the entry table
+    const int *tile_start;     // device prefix sum of tiles per entry (nbatch + 1)
     const RunDev *host_runs;   // host copy of the same table
-    int nbatch;
+    int nbatch;                // entries
     int chunk;
     int sflip;                 // 1: S and its work buffer are swapped
     int grid;                  // persistent grid size
@@ -117,11 +121,12 @@ hipError_t launch_adjoint(int q, int precision, const RunDev &r, bool frozen, co
 // (the first plane * ncol nodes of each run); -1: all nodes.
 hipError_t launch_reduce(int q, int precision, const RunDev *runs, int nbatch, int what,
                          bool odd, double *scratch, hipStream_t st, int plane = -1);
-// Front of the particle field per bottom column into out (device, ncol).
 // Power spectral density of a front height (device, ncol values) along
 // lateral axis `axis` for slice `index` (-1: mean over slices); out[len/2+1].
 hipError_t launch_front_psd(const RunDev &r, int dim, const double *h, int axis, int index,
                             double *out, hipStream_t st);
+// Front of the particle field (total over the classes) per bottom column
+// into out (device, ncol).
 hipError_t launch_front_height(int precision, const RunDev &r, int dim, double thr, double *out,
                                hipStream_t st);
 

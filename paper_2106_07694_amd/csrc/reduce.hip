@@ -53,11 +53,12 @@ template <int Q, typename T>
 __global__ void __launch_bounds__(1024) k_partial(RunDev r, int what, bool odd, bool shifted,
                                                   int plane, double *__restrict__ part) {
     double acc = 0.0;
-    int64_t n = (what == LBW_DEPOSIT) ? r.ncol : r.N;
+    // the deposit counters of every size class are contiguous
+    int64_t n = (what == LBW_DEPOSIT) ? r.ncol * r.ncls : r.N;
     if (plane >= 0 && (what == LBW_MASS_C || what == LBW_MASS_S) && (int64_t)plane * r.ncol < n)
         n = (int64_t)plane * r.ncol;   // planes are the slowest axis
     if (what == LBW_MASS_C) {
-        acc = strided_sum((const T *)r.c, n);
+        for (int i = 0; i < r.ncls; ++i) acc += strided_sum((const T *)r.c + (int64_t)i * r.N, n);
     } else if (what == LBW_MASS_S) {
         acc = strided_sum((const T *)r.s, n);
     } else if (what == LBW_DEPOSIT) {
@@ -109,9 +110,12 @@ hipError_t reduce_t(const RunDev *runs, int nbatch, int what, bool odd, bool shi
 // flight, and the lowest hit of the round over the W waves ends the column.
 // The scan thus stops within one round of the front, with W * U loads per
 // column in flight instead of one dependent load at a time.
-template <typename T, int W, int U>
+//
+// With several particle size classes (MULTI) C is their total, summed in
+// FP64 in class order; c then holds ncls fields of N values.
+template <typename T, int W, int U, bool MULTI>
 __global__ void __launch_bounds__(64 * W) k_front_height(const T *__restrict__ c, int64_t ncol,
-                                                         int nv, double thr,
+                                                         int nv, int ncls, int64_t N, double thr,
                                                          double *__restrict__ out) {
     __shared__ int hit[W][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -121,14 +125,22 @@ __global__ void __launch_bounds__(64 * W) k_front_height(const T *__restrict__ c
         int first = INT_MAX;
         if (!done) {
             const int v0 = base + w * U;
-            T cv[U];
+            double cv[U];
             // unconditional loads (the index clamped into the column): a
             // guarded load would make the compiler wait for each one in turn
 #pragma unroll
-            for (int u = 0; u < U; ++u) cv[u] = c[col + (int64_t)min(v0 + u, nv - 1) * ncol];
+            for (int u = 0; u < U; ++u) cv[u] = (double)c[col + (int64_t)min(v0 + u, nv - 1) * ncol];
+            if constexpr (MULTI) {
+                for (int i = 1; i < ncls; ++i) {
+                    const T *ci = c + (int64_t)i * N;
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        cv[u] += (double)ci[col + (int64_t)min(v0 + u, nv - 1) * ncol];
+                }
+            }
 #pragma unroll
             for (int u = U - 1; u >= 0; --u)
-                if (v0 + u < nv && (double)cv[u] >= thr) first = v0 + u;
+                if (v0 + u < nv && cv[u] >= thr) first = v0 + u;
         }
         hit[w][lane] = first;
         __syncthreads();
@@ -139,8 +151,14 @@ __global__ void __launch_bounds__(64 * W) k_front_height(const T *__restrict__ c
             if (w == 0) {
                 double h = 0.0;
                 if (v > 0) {
-                    const double cv = (double)c[col + (int64_t)v * ncol];
-                    const double cb = (double)c[col + (int64_t)(v - 1) * ncol];
+                    double cv = (double)c[col + (int64_t)v * ncol];
+                    double cb = (double)c[col + (int64_t)(v - 1) * ncol];
+                    if constexpr (MULTI) {
+                        for (int i = 1; i < ncls; ++i) {
+                            cv += (double)c[(int64_t)i * N + col + (int64_t)v * ncol];
+                            cb += (double)c[(int64_t)i * N + col + (int64_t)(v - 1) * ncol];
+                        }
+                    }
                     h = (double)(v - 1) + 0.5 + (thr - cb) / (cv - cb);
                 }
                 out[col] = h;
@@ -165,24 +183,32 @@ hipError_t launch_reduce(int q, int precision, const RunDev *runs, int nbatch, i
                   : reduce_t<19, double>(runs, nbatch, what, odd, sh, scratch, st, plane);
 }
 
-template <typename T>
-static void front_height_t(const T *c, int64_t ncol, int nv, double thr, double *out,
-                           hipStream_t st) {
+template <typename T, bool MULTI>
+static void front_height_t(const T *c, int64_t ncol, int nv, int ncls, int64_t N, double thr,
+                           double *out, hipStream_t st) {
     const unsigned grid = (unsigned)((ncol + 63) / 64);
     // few columns (2D grids): more waves per column keep enough loads in flight
     if (ncol >= 16384)
-        k_front_height<T, 4, 16><<<grid, 256, 0, st>>>(c, ncol, nv, thr, out);
+        k_front_height<T, 4, 16, MULTI><<<grid, 256, 0, st>>>(c, ncol, nv, ncls, N, thr, out);
     else
-        k_front_height<T, 16, 8><<<grid, 1024, 0, st>>>(c, ncol, nv, thr, out);
+        k_front_height<T, 16, 8, MULTI><<<grid, 1024, 0, st>>>(c, ncol, nv, ncls, N, thr, out);
+}
+
+template <typename T>
+static void front_height_c(const RunDev &r, int nv, double thr, double *out, hipStream_t st) {
+    if (r.ncls > 1)
+        front_height_t<T, true>((const T *)r.c, r.ncol, nv, r.ncls, r.N, thr, out, st);
+    else
+        front_height_t<T, false>((const T *)r.c, r.ncol, nv, 1, r.N, thr, out, st);
 }
 
 hipError_t launch_front_height(int precision, const RunDev &r, int dim, double thr, double *out,
                                hipStream_t st) {
     const int nv = dim == 2 ? r.ny : r.nz;
     if (precision == LBW_FP32_SHIFTED)
-        front_height_t((const float *)r.c, r.ncol, nv, thr, out, st);
+        front_height_c<float>(r, nv, thr, out, st);
     else
-        front_height_t((const double *)r.c, r.ncol, nv, thr, out, st);
+        front_height_c<double>(r, nv, thr, out, st);
     return hipGetLastError();
 }
 

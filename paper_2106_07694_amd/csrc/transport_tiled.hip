@@ -506,6 +506,7 @@ hipError_t stages_batched(const BatchArgs &a, hipStream_t st) {
     if (a.host_runs[0].has_s) {
         for (int b = 0; b < a.nbatch; ++b) {
             RunDev r = a.host_runs[b];
+            if (!r.has_s) continue;       // size classes after the first of a run
             if (a.sflip) { void *t = r.s; r.s = r.s2; r.s2 = t; }
             e = launch_s_update(D, sizeof(T) == 4 ? LBW_FP32_SHIFTED : LBW_FP64, r, st);
             if (e != hipSuccess) return e;

@@ -40,17 +40,22 @@ class LbwError(RuntimeError):
         self.code = code
 
 
+MAX_CLASSES = 8
+
+
 class CConfig(ctypes.Structure):
     _fields_ = [
         ("lattice", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
         ("vert_periodic", ctypes.c_int32), ("fluid_mode", ctypes.c_int32),
-        ("scheme_c", ctypes.c_int32), ("has_s", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("scheme_c", ctypes.c_int32), ("has_s", ctypes.c_int32), ("n_classes", ctypes.c_int32),
         ("tau", ctypes.c_double), ("body_force", ctypes.c_double * 3),
         ("u_top", ctypes.c_double * 3), ("vs", ctypes.c_double),
         ("kappa_c", ctypes.c_double), ("gp_c", ctypes.c_double),
         ("kappa_s", ctypes.c_double), ("gp_s", ctypes.c_double),
         ("weno_eps", ctypes.c_double),
+        ("vs_class", ctypes.c_double * MAX_CLASSES),
+        ("kappa_class", ctypes.c_double * MAX_CLASSES),
     ]
 
 
@@ -138,6 +143,24 @@ class RunConfig:
     kappa_s: float = 0.0
     gp_s: float = 0.0
     weno_eps: float = 1e-6
+    # particle size classes (eq. 11-12): with n_classes >= 2, class i settles
+    # at vs_class[i] and diffuses with kappa_class[i] (vs and kappa_c stay 0);
+    # C is then c[n_classes, nz, ny, nx] and the deposit dep[n_classes, ncol]
+    n_classes: int = 1
+    vs_class: tuple = ()
+    kappa_class: tuple = ()
+
+    @property
+    def ncls(self) -> int:
+        return max(1, self.n_classes)
+
+    @property
+    def c_shape(self) -> tuple:
+        return self.shape if self.ncls == 1 else (self.ncls,) + self.shape
+
+    @property
+    def deposit_shape(self) -> tuple:
+        return (self.ncol,) if self.ncls == 1 else (self.ncls, self.ncol)
 
     @property
     def dim(self) -> int:
@@ -160,7 +183,15 @@ class RunConfig:
         c.lattice, c.precision = self.lattice, PRECISIONS[self.precision]
         c.nx, c.ny, c.nz = self.nx, self.ny, self.nz
         c.vert_periodic, c.fluid_mode = int(self.vert_periodic), int(self.fluid_mode)
-        c.scheme_c, c.has_s, c.reserved = SCHEMES[self.scheme_c], int(self.has_s), 0
+        c.scheme_c, c.has_s = SCHEMES[self.scheme_c], int(self.has_s)
+        if not 0 <= self.n_classes <= MAX_CLASSES:
+            raise ValueError(f"n_classes must lie in [0, {MAX_CLASSES}]")
+        c.n_classes = self.n_classes if self.n_classes > 1 else 0
+        if self.n_classes > 1:
+            if len(self.vs_class) != self.n_classes or len(self.kappa_class) != self.n_classes:
+                raise ValueError("vs_class and kappa_class need one value per class")
+            c.vs_class = (ctypes.c_double * MAX_CLASSES)(*self.vs_class)
+            c.kappa_class = (ctypes.c_double * MAX_CLASSES)(*self.kappa_class)
         c.tau = self.tau
         c.body_force = (ctypes.c_double * 3)(*self.body_force)
         c.u_top = (ctypes.c_double * 3)(*self.u_top)
@@ -217,11 +248,11 @@ class Solver:
             z = lambda *shape, dt=self.dtype: torch.zeros(shape, dtype=dt, device=self.device)
             t = {
                 "f": z(c.lattice, *c.shape) if c.fluid_mode == FLUID_LBM else None,
-                "c": z(*c.shape), "c_s1": z(*c.shape), "c_s2": z(*c.shape),
+                "c": z(*c.c_shape), "c_s1": z(*c.c_shape), "c_s2": z(*c.c_shape),
                 "s": z(*c.shape) if c.has_s else None,
                 "s_tmp": z(*c.shape) if c.has_s else None,
                 "u": z(c.dim, *c.shape),
-                "deposit": z(c.ncol, dt=torch.float64),
+                "deposit": z(*c.deposit_shape, dt=torch.float64),
                 "scratch": z((scratch_bytes + 7) // 8, dt=torch.float64) if i == 0 else None,
             }
             self.tensors.append(t)
@@ -274,8 +305,8 @@ class Solver:
         """Canonical copy of a field as a new device tensor."""
         import torch
         c = self.cfgs[run]
-        shapes = {"f": (c.lattice, *c.shape), "c": c.shape, "s": c.shape, "u": (c.dim, *c.shape),
-                  "deposit": (c.ncol,), "stage1": c.shape, "stage2": c.shape}
+        shapes = {"f": (c.lattice, *c.shape), "c": c.c_shape, "s": c.shape, "u": (c.dim, *c.shape),
+                  "deposit": c.deposit_shape, "stage1": c.c_shape, "stage2": c.c_shape}
         fid = self._FIELDS[name]
         dt = torch.float64 if name == "deposit" else self.dtype
         with torch.cuda.stream(self.stream):

@@ -27,7 +27,34 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_version():
-    assert lbw.load().lbw_version() == 1
+    assert lbw.load().lbw_version() == 2
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of lbw_config, lbw_buffers and lbw_launch have the
+    header's size and field offsets (checked by a C program built from the
+    header alone)."""
+    import os
+    import subprocess
+
+    structs = {"lbw_config": lbw.CConfig, "lbw_buffers": lbw.CBuffers, "lbw_launch": lbw.CLaunch}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lbw.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", inc, "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
 
 
 def _fake_buffers(cfg: lbw.RunConfig) -> lbw.CBuffers:
@@ -69,6 +96,9 @@ def test_valid_config_creates():
     (dict(u_top=(2.0, 0, 0)), "lid"),
     (dict(nx=0), "grid"),
     (dict(lattice=19, nx=32768, ny=16384, nz=6), "horizontal plane"),
+    (dict(n_classes=2, vs=1e-3, vs_class=(1e-3, 2e-3), kappa_class=(0.0, 0.0)), "vs_class"),
+    (dict(n_classes=2, vs_class=(1e-3, 2.0), kappa_class=(0.0, 0.0)), "vs_class[1]"),
+    (dict(n_classes=3, vs_class=(0.0,) * 3, kappa_class=(0.0, 0.0, 0.3)), "kappa_class[2]"),
 ])
 def test_invalid_configs_rejected(bad, frag):
     rc, msg = _create([lbw.RunConfig(**bad)])
@@ -84,7 +114,9 @@ def test_bad_precision_and_scheme_codes():
     assert lib.lbw_create(ctypes.byref(c), ctypes.byref(b), 1, None, ctypes.byref(h)) == lbw.ERR_INVAL
     assert not h
     c = lbw.RunConfig().to_c()
-    c.reserved = 1
+    c.n_classes = lbw.MAX_CLASSES + 1
+    assert lib.lbw_create(ctypes.byref(c), ctypes.byref(b), 1, None, ctypes.byref(h)) == lbw.ERR_INVAL
+    c.n_classes = -1
     assert lib.lbw_create(ctypes.byref(c), ctypes.byref(b), 1, None, ctypes.byref(h)) == lbw.ERR_INVAL
 
 

@@ -1,0 +1,201 @@
+"""GPU parity of the particle size classes (eq. 11-12) against the FP64
+oracle: N concentration fields with their own settling speed and
+diffusivity, one fluid driven by the buoyancy of their total, a deposit
+counter per class and column.
+
+FP64: every field within 1e-12 of the oracle (the velocity with the
+population-scale floor of the single-class parity tests); FP32 shifted: the
+FP32 bounds of the single-class tests.  Exact relations of the oracle pins
+hold on the GPU too: an empty class changes nothing, two halves of a field
+under the linear flux reproduce the single-class run bit for bit, batched
+runs with different class counts equal the same runs alone.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2106_07694_amd import lbw
+
+from parity import as_input, compare, oracle_cfg, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+TOL64 = 1e-12
+
+
+def _cfg(n, lattice=9, **kw):
+    vs = (4e-3, 1.5e-3, 5e-4, 2.5e-3)[:n]
+    kap = (2e-3, 1e-3, 5e-4, 1.5e-3)[:n]
+    base = dict(lattice=lattice, tau=0.6 if lattice == 9 else 0.55, gp_c=3e-4, n_classes=n,
+                vs_class=vs, kappa_class=kap)
+    base.update(dict(nx=37, ny=29) if lattice == 9 else dict(nx=11, ny=9, nz=14))
+    base.update(kw)
+    return lbw.RunConfig(**base)
+
+
+def _fields(cfg, seed):
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0, 1, cfg.c_shape)
+    s = rng.uniform(0, 1, cfg.shape) if cfg.has_s else None
+    return as_input(c, cfg), as_input(s, cfg)
+
+
+def _check(cfg, nsteps, c0, s0=None, u=None, tol=TOL64, launch=None):
+    g = run_gpu(cfg, c0, s0, u, None, nsteps, launch=launch)
+    o = run_oracle(cfg, c0, s0, u, None, nsteps)
+    errs = compare(g, o)
+    print(f"\n{cfg.n_classes} classes {cfg.precision} {cfg.nx}x{cfg.ny}x{cfg.nz}: {errs}")
+    assert g["c"].shape == o["c"].shape == cfg.c_shape
+    assert g["deposit"].shape == o["deposit"].shape == cfg.deposit_shape
+    bad = {k: v for k, v in errs.items() if k != "u" and not v <= tol}
+    assert not bad, errs
+    if "f" in o:
+        du = float(np.max(np.abs(g["u"] - o["u"])))
+        bound = tol * float(np.max(np.abs(o["u"]))) + 64 * np.finfo(np.float64).eps * float(np.max(np.abs(o["f"])))
+        assert du <= bound, (du, bound)
+    # with a bottom wall every class deposits, by its own settling speed
+    if not cfg.vert_periodic:
+        assert np.all(o["deposit"].sum(axis=-1) > 0)
+    return g, o
+
+
+@pytest.mark.parametrize("kw", [
+    dict(n=2),
+    dict(n=3, has_s=True, kappa_s=1e-3, gp_s=-1e-4),
+    dict(n=4, vert_periodic=True),
+    dict(n=2, scheme_c="weno3", u_top=(0.02, 0, 0)),
+    dict(n=3, precision="fp64_shifted"),
+    dict(n=2, lattice=19),
+    dict(n=3, lattice=19, has_s=True, kappa_s=1e-3, gp_s=1e-4, body_force=(1e-5, 0, 0)),
+])
+def test_classes_match_oracle_fp64(kw):
+    n = kw.pop("n")
+    lattice = kw.pop("lattice", 9)
+    cfg = _cfg(n, lattice, **kw)
+    c0, s0 = _fields(cfg, 11)
+    _check(cfg, 20, c0, s0)
+
+
+@pytest.mark.parametrize("lattice", [9, 19])
+def test_classes_frozen_flow(lattice):
+    cfg = _cfg(3, lattice, fluid_mode=lbw.FLUID_FROZEN)
+    c0, _ = _fields(cfg, 12)
+    u = as_input(0.05 * np.random.default_rng(13).standard_normal((cfg.dim,) + cfg.shape), cfg)
+    _check(cfg, 12, c0, None, u)
+
+
+@pytest.mark.parametrize("lattice", [9, 19])
+def test_classes_fp32_shifted(lattice):
+    cfg = _cfg(3, lattice, precision="fp32_shifted", has_s=True, kappa_s=1e-3, gp_s=1e-4)
+    c0, s0 = _fields(cfg, 14)
+    g = run_gpu(cfg, c0, s0, None, None, 50)
+    o = run_oracle(cfg, c0, s0, None, None, 50)
+    errs = compare(g, o)
+    print(f"\nfp32 {lattice}: {errs}")
+    bounds = {"c": 3e-5, "u": 1e-4, "s": 1e-5, "f": 1e-4, "deposit": 1e-5}
+    assert all(errs[k] <= bounds[k] for k in errs), errs
+
+
+@pytest.mark.parametrize("launch", [dict(variant=1), dict(tile_x=64, tile_y=5),
+                                    dict(variant=2, slabs=3)])
+def test_classes_every_transport_form(launch):
+    """The plain and tiled transports agree with the oracle for several
+    classes; the pipelined variant runs such runs in the sequential order."""
+    cfg = _cfg(2, 9, nx=150, ny=37)
+    c0, _ = _fields(cfg, 15)
+    _check(cfg, 9, c0, launch=launch)
+
+
+def test_empty_class_changes_nothing_bitwise():
+    one = lbw.RunConfig(nx=40, ny=33, tau=0.6, gp_c=3e-4, vs=4e-3, kappa_c=2e-3)
+    two = _cfg(2, 9, nx=40, ny=33, vs_class=(4e-3, 1e-3), kappa_class=(2e-3, 5e-4))
+    c0 = np.random.default_rng(16).uniform(0, 1, one.shape)
+    g1 = run_gpu(one, c0, nsteps=15)
+    g2 = run_gpu(two, np.stack([c0, np.zeros_like(c0)]), nsteps=15)
+    assert np.array_equal(g1["f"], g2["f"]) and np.array_equal(g1["u"], g2["u"])
+    assert np.array_equal(g1["c"], g2["c"][0]) and not g2["c"][1].any()
+    assert np.array_equal(g1["deposit"], g2["deposit"][0]) and not g2["deposit"][1].any()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_shifted"])
+def test_two_halves_reproduce_one_class_bitwise(precision):
+    """First-order flux: every operation is exact under halving, so two equal
+    classes of C/2 give the single-class run bit for bit: the fluid feels
+    the total."""
+    kw = dict(nx=40, ny=33, tau=0.6, gp_c=3e-4, scheme_c="upwind1", precision=precision)
+    one = lbw.RunConfig(vs=4e-3, kappa_c=2e-3, **kw)
+    two = lbw.RunConfig(n_classes=2, vs_class=(4e-3, 4e-3), kappa_class=(2e-3, 2e-3), **kw)
+    c0 = as_input(np.random.default_rng(17).uniform(0, 1, one.shape), one)
+    g1 = run_gpu(one, c0, nsteps=15)
+    g2 = run_gpu(two, np.stack([0.5 * c0, 0.5 * c0]), nsteps=15)
+    assert np.array_equal(g1["f"], g2["f"])
+    for i in range(2):
+        assert np.array_equal(g2["c"][i], 0.5 * g1["c"]) and np.array_equal(g2["deposit"][i], 0.5 * g1["deposit"])
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+def test_batch_of_different_class_counts(graph):
+    """One, two and three classes in one batch (persistent transport over the
+    (run, class) entries): bitwise the runs alone; graph replays equal eager."""
+    import torch
+
+    cfgs = [lbw.RunConfig(nx=24, ny=30, tau=0.6, gp_c=3e-4, vs=2e-3, kappa_c=1e-3, precision="fp32_shifted"),
+            _cfg(2, 9, nx=40, ny=24, precision="fp32_shifted"),
+            _cfg(3, 9, nx=16, ny=36, precision="fp32_shifted")]
+    fields = [as_input(np.random.default_rng(20 + i).uniform(0, 1, c.c_shape), c) for i, c in enumerate(cfgs)]
+    sol = lbw.Solver(cfgs, stream=torch.cuda.Stream())      # graphs need a stream of their own
+    sol.set_launch(graph=graph)
+    for r, c in enumerate(fields):
+        sol.set_field("c", c, run=r)
+        sol.init_equilibrium(run=r)
+    sol.step(10)
+    torch.cuda.synchronize()
+    got = [{k: sol.field(k, run=r).cpu().numpy() for k in ("f", "c", "deposit")} for r in range(3)]
+    sums = sol.reduce(lbw.MASS_C) + sol.reduce(lbw.DEPOSIT)
+    sol.close()
+    for r, cfg in enumerate(cfgs):
+        alone = run_gpu(cfg, fields[r], nsteps=10)
+        for k in ("f", "c", "deposit"):
+            assert np.array_equal(got[r][k], alone[k].astype(got[r][k].dtype)), (r, k)
+        # particle budget over every class
+        assert abs(sums[r] - fields[r].sum()) <= 1e-5 * fields[r].sum(), r
+
+
+def test_reductions_and_diagnostics_see_every_class():
+    import torch
+
+    cfg = _cfg(3, 19, nx=20, ny=18, nz=24)
+    c0, _ = _fields(cfg, 21)
+    sol = lbw.Solver(cfg)
+    sol.set_field("c", c0)
+    sol.init_equilibrium()
+    sol.step(7)
+    o = run_oracle(cfg, c0, None, None, None, 7)
+    ocfg = oracle_cfg(cfg)
+    want = oracle.sums(ocfg, o["f"], o["c"], None, o["deposit"])
+    got = [sol.reduce(w)[0] for w in (lbw.MASS_C, lbw.MASS_FLUID, lbw.DEPOSIT)]
+    for g, w in zip(got, (want[0], want[2], want[3])):
+        assert abs(g - w) <= TOL64 * abs(w), (g, w)
+    for plane in (0, 7, 24):
+        m = sol.mass_below(plane)[0]
+        mw = oracle.mass_below(ocfg, o["c"], plane)
+        assert abs(m - mw) <= TOL64 * max(abs(mw), 1e-300), plane
+    # the front of the total on the same (seeded) field, bit for bit
+    sol.set_field("c", c0)
+    h = sol.front_height(1.5)
+    torch.cuda.synchronize()
+    assert np.array_equal(h.cpu().numpy().ravel(), oracle.front_height(ocfg, c0, 1.5))
+    sol.close()
+
+
+def test_adjoint_rejects_several_classes():
+    import torch
+
+    cfg = _cfg(2, 9, nx=16, ny=12)
+    sol = lbw.Solver(cfg)
+    z = torch.zeros(cfg.c_shape, dtype=torch.float64, device="cuda")
+    f = torch.zeros((cfg.lattice,) + cfg.shape, dtype=torch.float64, device="cuda")
+    work = torch.zeros(8, dtype=torch.float64, device="cuda")
+    with pytest.raises(lbw.LbwError) as e:
+        sol.adjoint_step(f, z, f, z, 1.0, f.clone(), z.clone(), None, work)
+    assert e.value.code == lbw.ERR_UNSUPPORTED
+    sol.close()
