@@ -30,12 +30,13 @@ PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 def _alg_bytes(wl) -> dict:
     """Algorithmic bytes per cell update (minimum the method must move).
 
-    step: read + write every population and every transported scalar once.
+    step: read + write every population and every transported scalar once
+    (each particle size class is a transported scalar).
     collide_stream kernel: read + write every population, read the scalars
     that set the buoyancy force.
     """
     s = 4 if wl.precision == "fp32_shifted" else 8
-    nsc = 2 if wl.has_s else 1
+    nsc = max(1, wl.n_classes) + (1 if wl.has_s else 0)
     return {"step": 2 * wl.q * s + 2 * nsc * s,
             "collide_stream": 2 * wl.q * s + nsc * s}
 
@@ -69,13 +70,15 @@ def _traffic(wl_name: str, kernel: str):
     return e.get("bytes_per_launch")
 
 
-def run_gpu(wl, steps: int, warmup: int) -> dict:
+def run_gpu(wl, steps: int, warmup: int, diagnostics: bool = True, tuned_as=None) -> dict:
+    """tuned_as: the workload whose autotuned launch shapes to use (default
+    wl itself)."""
     import torch
     from paper_2106_07694_amd import lbw
 
     cfg = lbw.RunConfig.from_workload(wl)
     sol = lbw.Solver(cfg)
-    tuned = _tuned_launch(wl)
+    tuned = _tuned_launch(tuned_as or wl)
     if tuned:
         sol.set_launch(**tuned)
     sol.setup_workload(wl)
@@ -93,7 +96,7 @@ def run_gpu(wl, steps: int, warmup: int) -> dict:
     phases = sol.timing_end()
     # untimed sanity: the particle budget must close
     mass = sol.reduce(lbw.MASS_C)[0] + sol.reduce(lbw.DEPOSIT)[0]
-    diag = run_diagnostics(sol, wl)
+    diag = run_diagnostics(sol, wl) if diagnostics else None
     sol.close()
     cells = wl.cells
     ab = _alg_bytes(wl)
@@ -360,6 +363,8 @@ def main() -> int:
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=5000)
+    ap.add_argument("--no-classes", action="store_true",
+                    help="skip the four-size-class run of the 3D workload")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the FP32-vs-FP64 error report of the 2D workload")
     ap.add_argument("--precision-steps", type=int, default=20000)
@@ -405,6 +410,15 @@ def main() -> int:
         adj = run_adjoint(args.adjoint_steps)
         print(f"[bench] adjoint: forward {adj['forward_s']:.3f} s, backward {adj['backward_s']:.3f} s "
               f"(ratio {adj['adjoint_forward_ratio']:.2f})", file=sys.stderr, flush=True)
+    poly = None
+    if not args.no_classes and main_wl.dim == 3:
+        p = run_gpu(W.C6, min(args.steps, 200), args.warmup, diagnostics=False, tuned_as=W.C3)
+        poly = {"workload": W.C6.name, "classes": W.C6.n_classes, "value": p["mlups"],
+                "unit": "MLUPS", "ms_per_step": p["ms_per_step"],
+                "phase_ms_per_step": p["phase_ms_per_step"], "step_alg_gbs": p["step_alg_gbs"],
+                "step_alg_bytes_per_cell": _alg_bytes(W.C6)["step"],
+                "collide_stream_alg_gbs": p["roofline"]["achieved"]}
+        print(f"[bench] {W.C6.name}: {p['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
     prec = None
     if not args.no_precision:
         prec = run_precision(args.precision_steps)
@@ -445,6 +459,7 @@ def main() -> int:
         "sweep": sweep,
         "adjoint": adj,
         "fp32_vs_fp64": prec,
+        "size_classes": poly,
         "copy_calibration": copy,
     }
     print(json.dumps(line))

@@ -40,6 +40,11 @@ class Workload:
     gp_s: float = 0.0        # vertical force per unit S is -gp_s (S heavier: gp_s > 0)
     steps: int = 1000
     seed: int = 1000
+    # particle size classes (eq. 11-12): with n_classes >= 2 the upper layer
+    # holds c0 / n_classes of each class, class i settling at vs_class[i]
+    n_classes: int = 1
+    vs_class: tuple = ()
+    kappa_class: tuple = ()
 
     @property
     def dim(self) -> int:
@@ -78,6 +83,12 @@ C3 = Workload("3d_d3q19_fp32_256x256x512", q=19, nx=256, ny=256, nz=512,
 C5 = Workload("2d_fp32_adjoint_512x1024", q=9, nx=512, ny=1024, nz=1,
               precision="fp32_shifted", tau=0.6, vs=1e-3, kappa_c=1e-3, gp_c=1e-5,
               steps=5000, seed=1004)
+# The 3D workload with four particle size classes sharing the same total
+# (settling speeds spread around the single-class one).
+C6 = Workload("3d_d3q19_fp32_256x256x512_4classes", q=19, nx=256, ny=256, nz=512,
+              precision="fp32_shifted", tau=0.55, vs=0.0, kappa_c=0.0, gp_c=1e-5,
+              steps=2000, seed=1005, n_classes=4, vs_class=(2.5e-4, 5e-4, 7.5e-4, 1e-3),
+              kappa_class=(5e-4, 5e-4, 5e-4, 5e-4))
 SWEEP_GRIDS = ((128, 256), (256, 512), (512, 1024))
 SWEEP_RUNS = 64
 SWEEP_STEPS = 5000
@@ -110,14 +121,18 @@ def initial_scalars(wl: Workload, seed: int | None = None):
     """(C, S) as float64 arrays of shape (nz, ny, nx); S is None without S.
 
     C = C0 * (1 + tanh((v - v_i)/width))/2 + amp * U(-1, 1), v_i = (n_v - 1)/2,
-    S = (1 - tanh((v - v_i)/width))/2.
+    S = (1 - tanh((v - v_i)/width))/2.  With n_classes >= 2, C has shape
+    (n_classes, nz, ny, nx): each class holds C0 / n_classes of the profile
+    plus its own noise of amplitude amp / n_classes.
     """
     rng = np.random.default_rng(wl.seed if seed is None else seed)
     v = _vertical_coordinate(wl)
     vi = 0.5 * (wl.nvert - 1)
     profile = 0.5 * (1.0 + np.tanh((v - vi) / wl.width))
-    c = wl.c0 * np.broadcast_to(profile, wl.shape).copy()
-    c += wl.amp * rng.uniform(-1.0, 1.0, size=wl.shape)
+    n = max(1, wl.n_classes)
+    shape = wl.shape if n == 1 else (n,) + wl.shape
+    c = (wl.c0 / n) * np.broadcast_to(profile, shape).copy()
+    c += (wl.amp / n) * rng.uniform(-1.0, 1.0, size=shape)
     s = None
     if wl.has_s:
         s = np.broadcast_to(1.0 - profile, wl.shape).copy()
