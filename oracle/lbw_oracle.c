@@ -104,6 +104,7 @@ static int setup(const orc_cfg *cfg, grid_t *g)
     if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1) return -1;
     if (g->n[g->vert] < 6) return -1;
     if (cfg->n_classes < 0 || cfg->n_classes > ORC_MAX_CLASSES) return -1;
+    if ((cfg->vs_s != 0.0 || cfg->phi_c != 0.0) && !cfg->has_s) return -1;
     g->ncls = cfg->n_classes > 1 ? cfg->n_classes : 1;
     g->N = (long)cfg->nx * cfg->ny * cfg->nz;
     g->ncol = (g->dim == 2) ? cfg->nx : (long)cfg->nx * cfg->ny;
@@ -129,8 +130,8 @@ static long column_of(const grid_t *g, const int p[3])
 
 /* ----------------------------------------------------------------------- */
 /* Moments, eq. 19-20 with the Guo shift rho u = sum f c + F/2 (eq. 22).    */
-/* Force (eq. 10, linearised in C and S): F = body + e_vert(-gp_c C - gp_s S) */
-/* with C the total over the size classes (eq. 11-12).                      */
+/* Force (eq. 10, linear in C and S): F = body + e_vert(-gp_c C -         */
+/* gp_s S (1 - phi_c C)), C the total over the size classes (eq. 11-12).  */
 /* ----------------------------------------------------------------------- */
 static void force_at(const grid_t *g, const orc_cfg *cfg, const double *c,
                      const double *s, long k, double F[3])
@@ -140,7 +141,9 @@ static void force_at(const grid_t *g, const orc_cfg *cfg, const double *c,
     for (d = 0; d < 3; d++) F[d] = cfg->body_force[d];
     for (i = 0; i < g->ncls; i++) ctot += c[(long)i * g->N + k];
     F[g->vert] += -cfg->gp_c * ctot;
-    if (cfg->has_s) F[g->vert] += -cfg->gp_s * s[k];
+    /* the fluid's density anomaly acts on the fluid fraction 1 - phi,
+       phi = phi_c * C (eq. 10) */
+    if (cfg->has_s) F[g->vert] += -cfg->gp_s * (s[k] * (1.0 - cfg->phi_c * ctot));
 }
 
 static void moments_at(const grid_t *g, const orc_cfg *cfg, const double *f,
@@ -225,25 +228,36 @@ static long displaced(const grid_t *g, const orc_cfg *cfg, const int p[3],
     return node_index(g, r);
 }
 
-/* Transport velocity along ax at a node: u_ax - vs on the vertical axis.
+/* Settling speed at node k: vs, or with vs_s != 0 the Stokes speed in the
+ * local fluid density (eq. 13 with rho linear in S), vs (1 - vs_s S_k).
+ * s is NULL for a scalar that does not settle by S. */
+static double settling_at(const orc_cfg *cfg, const double *s, double vs, long k)
+{
+    if (!s || cfg->vs_s == 0.0) return vs;
+    return vs * (1.0 - cfg->vs_s * s[k]);
+}
+
+/* Transport velocity along ax at a node: u_ax - Vs on the vertical axis.
  * Beyond a wall the vertical fluid velocity is mirrored with a sign change
- * (no penetration), while settling keeps its direction. */
-static double transport_velocity(const grid_t *g, const double *u, long k,
-                                 int ax, int ghost, double vs)
+ * (no penetration), while settling keeps its direction (k is the mirrored
+ * node, so a variable settling speed sees the mirrored S). */
+static double transport_velocity(const grid_t *g, const orc_cfg *cfg, const double *u,
+                                 const double *s, long k, int ax, int ghost, double vs)
 {
     double ua = u[(long)ax * g->N + k];
     if (ax == g->vert) {
         if (ghost) ua = -ua;
-        return ua - vs;
+        return ua - settling_at(cfg, s, vs, k);
     }
     return ua;
 }
 
 /* Face flux through the face between p and p + e_ax for scheme `scheme`,
- * diffusivity kappa, settling vs (0 for S). */
+ * diffusivity kappa, settling vs (0 for S; s: the S field that sets a
+ * variable settling speed, or NULL). */
 static double interior_face_flux(const grid_t *g, const orc_cfg *cfg,
                                  int scheme, double kappa, double vs,
-                                 const double *a, const double *u,
+                                 const double *a, const double *u, const double *s,
                                  const int p[3], int ax)
 {
     double hv[6], av[6], wv[6];
@@ -254,7 +268,7 @@ static double interior_face_flux(const grid_t *g, const orc_cfg *cfg,
     for (m = 0; m < 6; m++) {
         k = displaced(g, cfg, p, ax, m - 2, &gh);
         av[m] = a[k];
-        wv[m] = transport_velocity(g, u, k, ax, gh, vs);
+        wv[m] = transport_velocity(g, cfg, u, s, k, ax, gh, vs);
         hv[m] = wv[m] * av[m];
     }
     /* upwind direction: sign of the face velocity, ties go left (R11) */
@@ -286,8 +300,8 @@ static double interior_face_flux(const grid_t *g, const orc_cfg *cfg,
  * (outflow per column returned); otherwise walls carry no flux. */
 static void spatial_operator(const grid_t *g, const orc_cfg *cfg, int scheme,
                              double kappa, double vs, int absorbing,
-                             const double *a, const double *u, double *L,
-                             double *outflow)
+                             const double *a, const double *u, const double *s,
+                             double *L, double *outflow)
 {
     double *phi = (double *)malloc(sizeof(double) * (size_t)g->dim * g->N);
     long k;
@@ -301,7 +315,7 @@ static void spatial_operator(const grid_t *g, const orc_cfg *cfg, int scheme,
                 phi[(long)d * g->N + k] = 0.0; /* top wall: no flux */
             else
                 phi[(long)d * g->N + k] =
-                    interior_face_flux(g, cfg, scheme, kappa, vs, a, u, p, d);
+                    interior_face_flux(g, cfg, scheme, kappa, vs, a, u, s, p, d);
         }
     }
 #pragma omp parallel for schedule(static)
@@ -312,7 +326,7 @@ static void spatial_operator(const grid_t *g, const orc_cfg *cfg, int scheme,
         for (d = 0; d < g->dim; d++) {
             double right = phi[(long)d * g->N + k], left;
             if (d == g->vert && !cfg->vert_periodic && p[d] == 0) {
-                left = absorbing ? -vs * a[k] : 0.0; /* bottom wall face */
+                left = absorbing ? -settling_at(cfg, s, vs, k) * a[k] : 0.0; /* bottom wall face */
             } else {
                 long km = displaced(g, cfg, p, d, -1, &gh);
                 left = phi[(long)d * g->N + km];
@@ -327,7 +341,7 @@ static void spatial_operator(const grid_t *g, const orc_cfg *cfg, int scheme,
             for (k = 0; k < g->N; k++) {
                 int p[3];
                 node_coords(g, k, p);
-                if (p[g->vert] == 0) outflow[column_of(g, p)] = vs * a[k];
+                if (p[g->vert] == 0) outflow[column_of(g, p)] = settling_at(cfg, s, vs, k) * a[k];
             }
         }
     }
@@ -465,7 +479,7 @@ int orc_rhs_c(const orc_cfg *cfg, const double *a, const double *u,
 {
     grid_t g;
     if (setup(cfg, &g)) return -1;
-    spatial_operator(&g, cfg, cfg->scheme_c, cfg->kappa_c, cfg->vs, 1, a, u,
+    spatial_operator(&g, cfg, cfg->scheme_c, cfg->kappa_c, cfg->vs, 1, a, u, NULL,
                      out, outflow);
     return 0;
 }
@@ -477,6 +491,7 @@ int orc_run(const orc_cfg *cfg, double *f, double *c, double *s, double *dep,
     long k, N;
     int step, d, i;
     double *rho, *u, *F, *a1, *a2, *L, *cn, *out0, *out1, *out2, *fnew;
+    const double *sn = cfg->has_s ? s : NULL;   /* S at level n sets Vs (eq. 13) */
     if (setup(cfg, &g)) return -1;
     if (cfg->tau <= 0.5 || nsteps < 0) return -1;
     if (cfg->frozen && !u_in) return -1;
@@ -511,16 +526,17 @@ int orc_run(const orc_cfg *cfg, double *f, double *c, double *s, double *dep,
             }
         }
         /* 2. each size class C_i: TVD-RK3 (S21-S23) with its own settling
-              speed and diffusivity, velocity frozen over the substeps; the
-              force above already holds the classes at level n */
+              speed and diffusivity, velocity (and a settling speed set by
+              S) frozen at level n over the substeps; the force above
+              already holds the classes at level n */
         for (i = 0; i < g.ncls; i++) {
             double *ci = c + (long)i * N;
             const double vs = class_vs(cfg, i), kappa = class_kappa(cfg, i);
-            spatial_operator(&g, cfg, cfg->scheme_c, kappa, vs, 1, ci, u, L, out0);
+            spatial_operator(&g, cfg, cfg->scheme_c, kappa, vs, 1, ci, u, sn, L, out0);
             for (k = 0; k < N; k++) a1[k] = ci[k] + L[k];
-            spatial_operator(&g, cfg, cfg->scheme_c, kappa, vs, 1, a1, u, L, out1);
+            spatial_operator(&g, cfg, cfg->scheme_c, kappa, vs, 1, a1, u, sn, L, out1);
             for (k = 0; k < N; k++) a2[k] = 0.75 * ci[k] + 0.25 * a1[k] + 0.25 * L[k];
-            spatial_operator(&g, cfg, cfg->scheme_c, kappa, vs, 1, a2, u, L, out2);
+            spatial_operator(&g, cfg, cfg->scheme_c, kappa, vs, 1, a2, u, sn, L, out2);
             for (k = 0; k < N; k++)
                 cn[k] = ci[k] / 3.0 + 2.0 / 3.0 * a2[k] + 2.0 / 3.0 * L[k];
             if (dep)
@@ -530,7 +546,7 @@ int orc_run(const orc_cfg *cfg, double *f, double *c, double *s, double *dep,
         }
         /* 3. S: forward Euler, first-order upwind, no settling, closed walls */
         if (cfg->has_s) {
-            spatial_operator(&g, cfg, 2, cfg->kappa_s, 0.0, 0, s, u, L, NULL);
+            spatial_operator(&g, cfg, 2, cfg->kappa_s, 0.0, 0, s, u, NULL, L, NULL);
             for (k = 0; k < N; k++) s[k] = s[k] + L[k];
         }
         /* 4-5. collide and stream */
@@ -631,7 +647,7 @@ static void spatial_operator_reverse(const grid_t *g, const orc_cfg *cfg, const 
             for (m = 0; m < 6; m++) {
                 idx[m] = displaced(g, cfg, p, d, m - 2, &ghost[m]);
                 av[m] = a[idx[m]];
-                wv[m] = transport_velocity(g, u, idx[m], d, ghost[m], vs);
+                wv[m] = transport_velocity(g, cfg, u, NULL, idx[m], d, ghost[m], vs);
                 hv[m] = wv[m] * av[m];
                 hbar[m] = 0.0;
                 abar_l[m] = 0.0;
@@ -702,9 +718,9 @@ int orc_adjoint_step(const orc_cfg *cfg, const double *f_n, const double *c_n,
             for (d = 0; d < 3; d++) { u[(long)d * N + k] = uk[d]; F[(long)d * N + k] = Fk[d]; }
         }
     }
-    spatial_operator(&g, cfg, 0, cfg->kappa_c, vs, 1, c_n, u, L, NULL);
+    spatial_operator(&g, cfg, 0, cfg->kappa_c, vs, 1, c_n, u, NULL, L, NULL);
     for (k = 0; k < N; k++) a1[k] = c_n[k] + L[k];
-    spatial_operator(&g, cfg, 0, cfg->kappa_c, vs, 1, a1, u, L, NULL);
+    spatial_operator(&g, cfg, 0, cfg->kappa_c, vs, 1, a1, u, NULL, L, NULL);
     for (k = 0; k < N; k++) a2[k] = 0.75 * c_n[k] + 0.25 * a1[k] + 0.25 * L[k];
 
     /* reverse of C+ = C/3 + 2/3 a2 + 2/3 L(a2) and of the deposit update */

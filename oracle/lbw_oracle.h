@@ -55,6 +55,15 @@ typedef struct {
     double weno_eps;       /* WENO regularisation epsilon */
     double vs_class[ORC_MAX_CLASSES];    /* per-class settling speed (n_classes >= 2) */
     double kappa_class[ORC_MAX_CLASSES]; /* per-class diffusivity (n_classes >= 2) */
+    /* The full force and settling of the paper (need has_s; 0 = off):
+     * vs_s: the Stokes settling speed in fluid of density rho(S) (eq. 13,
+     *   rho linear in S): every class settles at Vs (1 - vs_s S) with S at
+     *   the node, so the conservative flux carries the -phi d(Vs)/dz term of
+     *   eq. 7;
+     * phi_c: particle volume fraction per unit C; the buoyancy of S acts on
+     *   the fluid fraction, -gp_s S (1 - phi_c C) (eq. 10). */
+    double vs_s;
+    double phi_c;
 } orc_cfg;
 
 /* Lattice table in the documented order: c[q][3], w[q], opp[q]. */
@@ -67,8 +76,9 @@ int orc_equilibrium(const orc_cfg *cfg, const double *rho, const double *u, doub
 int orc_moments(const orc_cfg *cfg, const double *f, const double *c,
                 const double *s, double *rho, double *u);
 
-/* Spatial operator of the C equation for node velocity u[dim][N]:
- * out[N] = L(a); outflow[columns] = settling flux through the bottom wall. */
+/* Spatial operator of the C equation for node velocity u[dim][N] and the
+ * constant settling speed vs: out[N] = L(a); outflow[columns] = settling
+ * flux through the bottom wall. */
 int orc_rhs_c(const orc_cfg *cfg, const double *a, const double *u,
               double *out, double *outflow);
 
