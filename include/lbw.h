@@ -64,7 +64,7 @@
 extern "C" {
 #endif
 
-#define LBW_ABI_VERSION 2
+#define LBW_ABI_VERSION 3
 #define LBW_MAX_CLASSES 8   /* particle size classes per run */
 
 enum {
@@ -110,6 +110,16 @@ typedef struct {
     double weno_eps;       /* WENO regularisation, > 0 (1e-6 typical) */
     double vs_class[LBW_MAX_CLASSES];    /* n_classes >= 2: settling speeds */
     double kappa_class[LBW_MAX_CLASSES]; /* n_classes >= 2: diffusivities */
+    /* The paper's full force and settling (both need has_s; 0 = off):
+     * vs_s   every class settles at its speed times (1 - vs_s S), S at the
+     *        node: the Stokes speed in fluid of density rho(S) (eq. 13, rho
+     *        linear in S).  The conservative face fluxes then carry the
+     *        -phi d(Vs)/dz term of eq. 7.  The caller keeps |Vs| <= 1 over
+     *        the S values the run reaches (S stays within its initial range);
+     * phi_c  particle volume fraction per unit C: the buoyancy of S acts on
+     *        the fluid fraction, -gp_s S (1 - phi_c C) (eq. 10). */
+    double vs_s;
+    double phi_c;
 } lbw_config;
 
 /* One run's device buffers (caller-owned, element type per precision:
@@ -142,8 +152,9 @@ typedef struct {
                               vertical axis is cut into slabs and the
                               collide-stream of step n+1 on a slab runs on a
                               second stream, overlapping the transport of step
-                              n on the slabs above it (single run with walls
-                              and one size class; other runs take variant 0) */
+                              n on the slabs above it (single run with walls,
+                              one size class and a constant settling speed;
+                              other runs take variant 0) */
     int32_t graph;         /* 1: lbw_step replays a captured HIP graph of two
                               steps (needs a non-null stream; the graph is
                               runtime-owned and rebuilt after lbw_set_launch) */

@@ -18,8 +18,8 @@ LIB = os.path.join(HERE, "liblbw.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["lbm.hip", "transport.hip", "transport_tiled.hip", "reduce.hip", "adjoint.hip",
-           "api.cpp"]
+SOURCES = ["lbm.hip", "transport.hip", "transport_tiled.hip", "transport_tiled_vs.hip",
+           "reduce.hip", "adjoint.hip", "api.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

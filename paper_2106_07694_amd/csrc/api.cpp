@@ -225,6 +225,10 @@ int validate(const lbw_config &c, const lbw_buffers &b, int idx) {
     }
     if (!std::isfinite(c.gp_c) || !std::isfinite(c.gp_s))
         return fail(LBW_ERR_INVAL, "run %d: buoyancy coefficients must be finite", idx);
+    if (!std::isfinite(c.vs_s) || !std::isfinite(c.phi_c))
+        return fail(LBW_ERR_INVAL, "run %d: vs_s and phi_c must be finite", idx);
+    if ((c.vs_s != 0.0 || c.phi_c != 0.0) && !c.has_s)
+        return fail(LBW_ERR_INVAL, "run %d: vs_s and phi_c act through S (has_s = 1)", idx);
     if (c.fluid_mode == LBW_FLUID_LBM && !b.f) return fail(LBW_ERR_INVAL, "run %d: f is NULL", idx);
     if (!b.c || !b.c_s1 || !b.c_s2) return fail(LBW_ERR_INVAL, "run %d: C buffers are NULL", idx);
     if (!b.u) return fail(LBW_ERR_INVAL, "run %d: u is NULL", idx);
@@ -266,6 +270,8 @@ lbw::RunDev make_run(const lbw_config &c, const lbw_buffers &b) {
     r.kappa_s = c.kappa_s;
     r.gp_s = c.gp_s;
     r.eps = c.weno_eps;
+    r.vs_s = c.vs_s;
+    r.phi_c = c.phi_c;
     return r;
 }
 
@@ -623,7 +629,8 @@ int lbw_step(lbw_handle *h, int32_t nsteps) {
     int rc;
     // the slab order assumes walls: a periodic vertical axis couples the first
     // and last slabs, so such runs take the sequential order
-    if (h->launch.variant == 2 && !h->run[0].vper && h->run[0].ncls == 1 && nsteps > 0) {
+    if (h->launch.variant == 2 && !h->run[0].vper && h->run[0].ncls == 1 && h->run[0].vs_s == 0.0 &&
+        nsteps > 0) {
         if ((rc = ensure_pipeline(h, 1))) return rc;
         // B starts after everything already queued on A, A ends after B
         hipError_t e = hipEventRecord(h->ev_fork, h->stream);

@@ -132,16 +132,18 @@ __device__ __forceinline__ void lbm_rho_u(const T (&fi)[Q], const T F[3], T &rho
     u[2] = (L::D == 3) ? (mz + (T)0.5 * F[2]) * inv : (T)0;
 }
 
-// Force density at node k: body force plus the linear buoyancy of C (and S)
-// on the vertical axis (eq. 10 linearised); with several particle size
-// classes C is their total, summed in class order (eq. 11-12).
+// Force density at node k: body force plus the buoyancy of C and S on the
+// vertical axis (eq. 10, linear in C and S), -gp_c C - gp_s S (1 - phi_c C):
+// the density anomaly of the fluid acts on its fraction 1 - phi, phi =
+// phi_c C (phi_c = 0: the linear form).  With several particle size classes
+// C is their total, summed in class order (eq. 11-12).
 template <int D, typename T>
 __device__ __forceinline__ void lbm_force(const RunDev &r, const T *__restrict__ c,
                                           const T *__restrict__ s, int64_t k, T F[3]) {
     T ctot = c[k];
     for (int i = 1; i < r.ncls; ++i) ctot += c[k + (int64_t)i * r.N];
     T fv = -(T)r.gp_c * ctot;
-    if (r.has_s) fv -= (T)r.gp_s * s[k];
+    if (r.has_s) fv -= (T)r.gp_s * (s[k] * ((T)1 - (T)r.phi_c * ctot));
     F[0] = (T)r.body[0];
     F[1] = (T)r.body[1] + (D == 2 ? fv : (T)0);
     F[2] = (T)r.body[2] + (D == 3 ? fv : (T)0);

@@ -60,6 +60,8 @@ struct RunDev {
     double tau, omega, guo;          // 1/tau and 1 - 1/(2 tau)
     double body[3], utop[3];
     double vs, kappa_c, gp_c, kappa_s, gp_s, eps;
+    double vs_s;         // settling speed Vs (1 - vs_s S) (eq. 13), 0: constant
+    double phi_c;        // volume fraction per unit C in the (1 - phi) of eq. 10
 };
 
 // Tile shape of the tiled transport kernels for a launch choice.
@@ -104,6 +106,10 @@ TileShape resolve_tile_shape(int dim, const lbw_launch &l);
 int64_t transport_tiles(int dim, const RunDev &r, const lbw_launch &l);
 hipError_t launch_transport_batched(int dim, int precision, const BatchArgs &b, const lbw_launch &l,
                                     hipStream_t st);
+// The tiled stages of runs whose settling speed depends on S (b: batched
+// entries, or NULL for the single run r).
+hipError_t launch_transport_tiled_vs(int dim, int precision, const RunDev &r, const lbw_launch &l,
+                                     hipStream_t st, const BatchArgs *b);
 // nodes: total nodes of the batch (chooses the cache policy of the
 // population accesses)
 hipError_t launch_collide_stream_batched(int q, int precision, const RunDev *runs, const int *blk_start,

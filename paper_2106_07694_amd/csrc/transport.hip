@@ -35,8 +35,17 @@ __device__ __forceinline__ void node_coords(const RunDev &r, int64_t k, int &x, 
     }
 }
 
-// L(a) at node k.  absorbing: bottom wall face carries -vs*a_0 (C); otherwise
-// the walls are closed (S).
+// Settling speed of C at node k: vs, or Vs (1 - vs_s S_k) when the speed is
+// set by the local fluid density (eq. 13 with rho linear in S).
+template <typename T>
+__device__ __forceinline__ T settling_at(const RunDev &r, T vs, int64_t k) {
+    if (r.vs_s == 0.0) return vs;
+    return vs * ((T)1 - (T)r.vs_s * ((const T *)r.s)[k]);
+}
+
+// L(a) at node k.  absorbing: bottom wall face carries -Vs*a_0 (C, with the
+// settling speed of settling_at); otherwise the walls are closed and nothing
+// settles (S).
 template <typename T, int D, int SCHEME, bool ABSORB>
 __device__ T spatial_op(const RunDev &r, const T *__restrict__ a, const T *__restrict__ u,
                         int64_t k, int x, int y, int z, T vs, T kappa, T eps) {
@@ -66,10 +75,10 @@ __device__ T spatial_op(const RunDev &r, const T *__restrict__ a, const T *__res
             av[m] = a[kk];
             T uu = u[(int64_t)ax * r.N + kk];
             if (ghost) uu = -uu;
-            wv[m] = vert ? uu - vs : uu;
+            wv[m] = vert ? uu - (ABSORB ? settling_at<T>(r, vs, kk) : vs) : uu;
         }
         const T Fp = (walls && j == n - 1) ? (T)0 : face_flux<T, SCHEME>(av + 1, wv + 1, kappa, eps);
-        const T Fm = (walls && j == 0) ? (ABSORB ? -vs * av[3] : (T)0)
+        const T Fm = (walls && j == 0) ? (ABSORB ? -settling_at<T>(r, vs, k) * av[3] : (T)0)
                                        : face_flux<T, SCHEME>(av, wv, kappa, eps);
         L -= (Fp - Fm);
     }
@@ -97,9 +106,10 @@ __global__ void __launch_bounds__(256) k_rk_stage(RunDev r) {
         const int v = (D == 2) ? y : z;
         if (!r.vper && v == 0) {
             // settled mass through the bottom face over the three stages
-            const double o0 = r.vs * (double)c0;
-            const double o1 = r.vs * (double)((const T *)r.c1)[k];
-            const double o2 = r.vs * (double)a;
+            const double vsd = r.vs * (1.0 - r.vs_s * (r.vs_s == 0.0 ? 0.0 : (double)((const T *)r.s)[k]));
+            const double o0 = vsd * (double)c0;
+            const double o1 = vsd * (double)((const T *)r.c1)[k];
+            const double o2 = vsd * (double)a;
             const int64_t col = (D == 2) ? x : (int64_t)x + (int64_t)r.nx * y;
             r.dep[col] += o0 / 6.0 + o1 / 6.0 + 2.0 / 3.0 * o2;
         }

@@ -1,542 +1,8 @@
-// transport_tiled.hip -- RK3 stage kernels of the particle transport, tiled
-// for CDNA: a block owns a TX x TY tile of vertical columns and marches up a
-// chunk of the vertical axis.  Per plane:
-//   * the plane of the stage input a, with a three-cell lateral halo, and the
-//     lateral velocities sit in LDS; each lateral face flux is computed once
-//     into LDS and differenced by the two cells that share it;
-//   * each thread keeps its own column's six-node vertical stencil of a and
-//     of the vertical transport velocity in registers, computes the face
-//     above its cell and carries it down as the face below the next cell;
-//   * the next plane's global loads are issued before the current plane is
-//     computed (software pipelining).
-// Arithmetic and wall rules are those of the plain kernels (transport.hip):
-// WENO face fluxes from the upwind side, central diffusion, mirror ghosts
-// with a sign flip of the vertical fluid velocity, closed top, absorbing
-// bottom feeding the deposit counter.  In single precision the weights use
-// the hardware reciprocal.
-#include "transport_device.h"
+// transport_tiled.hip -- launchers of the tiled RK3 stage kernels
+// (transport_tiled.h) and the kernels with a constant settling speed.
+#include "transport_tiled.h"
 
 namespace lbw {
-namespace {
-
-template <typename T> __device__ __forceinline__ T fast_rcp(T x) { return (T)1 / x; }
-template <> __device__ __forceinline__ float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
-
-// WENO5-JS face value (the formula of weno5_face) rearranged for issue
-// count, with one reciprocal.  The normalised weights are ratios, so every
-// indicator may be scaled by one constant and every ideal weight by another:
-// with e_k = (12/13)(eps + beta_k) = t_k^2 + (3/13) s_k^2 + (12/13) eps
-// (t_k the second difference, s_k the one-sided first difference of
-// sub-stencil k, both built from the four first differences) and the
-// weights multiplied through by 10 e_0^2 e_1^2 e_2^2, the face value is
-//   (P q_0 + Q q_1' + R q_2') / (P + 6 Q + 3 R),
-//   P = e_1^2 e_2^2, Q = e_0^2 e_2^2, R = e_0^2 e_1^2,
-// where q_0 is the first candidate and q_1' = 6 q_1, q_2' = 3 q_2.
-// eps12 is (12/13) eps.  With e_k >= eps12 and concentrations of order one
-// every product stays far inside the single-precision range.
-template <typename T>
-__device__ __forceinline__ T weno5_rcp(T h0, T h1, T h2, T h3, T h4, T a0, T a1, T a2, T a3, T a4,
-                                       T eps12) {
-    const T g0 = a1 - a0, g1 = a2 - a1, g2 = a3 - a2, g3 = a4 - a3;
-    const T t0 = g1 - g0, t1 = g2 - g1, t2 = g3 - g2;
-    const T s0 = t0 + (T)2 * g1;          // a0 - 4 a1 + 3 a2
-    const T s1 = g1 + g2;                 // a3 - a1
-    const T s2 = t2 - (T)2 * g2;          // 3 a2 - 4 a3 + a4
-    constexpr T k = (T)(3.0 / 13.0);
-    const T e0 = t0 * t0 + (k * s0 * s0 + eps12);
-    const T e1 = t1 * t1 + (k * s1 * s1 + eps12);
-    const T e2 = t2 * t2 + (k * s2 * s2 + eps12);
-    const T S0 = e0 * e0, S1 = e1 * e1, S2 = e2 * e2;
-    const T P = S1 * S2, Q = S0 * S2, R = S0 * S1;
-    const T q0 = (T)(1.0 / 3.0) * h0 - (T)(7.0 / 6.0) * h1 + (T)(11.0 / 6.0) * h2;
-    const T q1 = (T)5 * h2 - h1 + (T)2 * h3;
-    const T q2 = h2 + (T)2.5 * h3 - (T)0.5 * h4;
-    return (P * q0 + Q * q1 + R * q2) * fast_rcp<T>(P + (T)6 * Q + (T)3 * R);
-}
-
-template <typename T>
-__device__ __forceinline__ T weno3_rcp(T h0, T h1, T h2, T a0, T a1, T a2, T eps) {
-    const T qu = (T)0.5 * ((T)3 * h1 - h0);
-    const T qc = (T)0.5 * (h1 + h2);
-    const T eu = eps + (a1 - a0) * (a1 - a0);
-    const T ec = eps + (a2 - a1) * (a2 - a1);
-    const T au = (T)(1.0 / 3.0) * fast_rcp<T>(eu * eu);
-    const T ac = (T)(2.0 / 3.0) * fast_rcp<T>(ec * ec);
-    return (au * qu + ac * qc) * fast_rcp<T>(au + ac);
-}
-
-// Face flux from six nodes j-2..j+3 (a and w given as separate scalars):
-// the upwind side is chosen by selects, not branches, so lanes of a wave
-// with different face-velocity signs do not diverge.
-template <typename T, int SCHEME>
-__device__ __forceinline__ T face6(T a0, T a1, T a2, T a3, T a4, T a5, T w0, T w1, T w2, T w3,
-                                   T w4, T w5, T kappa, T eps) {
-    const bool pos = (w2 + w3) >= (T)0;
-    T hh;
-    if constexpr (SCHEME == LBW_WENO5) {
-        const T A0 = pos ? a0 : a5, A1 = pos ? a1 : a4, A2 = pos ? a2 : a3, A3 = pos ? a3 : a2,
-                A4 = pos ? a4 : a1;
-        const T W0 = pos ? w0 : w5, W1 = pos ? w1 : w4, W2 = pos ? w2 : w3, W3 = pos ? w3 : w2,
-                W4 = pos ? w4 : w1;
-        hh = weno5_rcp<T>(W0 * A0, W1 * A1, W2 * A2, W3 * A3, W4 * A4, A0, A1, A2, A3, A4,
-                          (T)(12.0 / 13.0) * eps);
-    } else if constexpr (SCHEME == LBW_WENO3) {
-        const T A0 = pos ? a1 : a4, A1 = pos ? a2 : a3, A2 = pos ? a3 : a2;
-        const T W0 = pos ? w1 : w4, W1 = pos ? w2 : w3, W2 = pos ? w3 : w2;
-        hh = weno3_rcp<T>(W0 * A0, W1 * A1, W2 * A2, A0, A1, A2, eps);
-    } else {
-        hh = pos ? w2 * a2 : w3 * a3;
-    }
-    return hh - kappa * (a3 - a2);
-}
-
-struct TileGeom {
-    int nx, ny, nv;     // lateral sizes (ny = 1 in 2D) and vertical extent
-    int64_t sv;         // stride of the vertical axis
-    int64_t N;
-    int vper;
-    int chunk;          // vertical planes per block
-    int gx, gy, gz;     // tiles along x, y and vertical chunks launched
-    int bz0;            // first vertical chunk launched
-};
-
-// Position of the block: blocks are dealt round-robin to the 8 XCDs, so the
-// flat index is remapped to give each XCD a contiguous range of tiles whose
-// halos then meet in that XCD's L2.
-__device__ __forceinline__ void block_tile(const TileGeom &g, int &bx, int &by, int &bz) {
-    const int nb = g.gx * g.gy * g.gz;
-    const int b = blockIdx.x;
-    int logical = b;
-    if ((nb & 7) == 0) {
-        const int per = nb >> 3;
-        logical = (b & 7) * per + (b >> 3);
-    }
-    bx = logical % g.gx;
-    const int t = logical / g.gx;
-    by = t % g.gy;
-    bz = g.bz0 + t / g.gy;
-}
-
-// Addressing: a vertical plane's base pointer is the same for the whole
-// block (uniform, held in scalar registers) and each lane adds a 32-bit byte
-// offset within the plane, so the loads and stores need no 64-bit vector
-// arithmetic.  This needs nx * ny * sizeof(T) < 2^32 (checked at creation).
-template <typename T>
-__device__ __forceinline__ const T &at(const void *plane, uint32_t off) {
-    return *(const T *)((const char *)plane + off);
-}
-
-// FULL: the grid is a whole number of tiles, so every lane owns a cell and
-// the store needs no lane mask (a masked store on a path that may be skipped
-// would make every later wait on the load counter drain it completely).
-template <typename T, int D, int SCHEME, int STAGE, int TX, int TY, bool FULL>
-__device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, int bx, int by, int bz) {
-    constexpr int NT = TX * TY;
-    constexpr int AX = TX + 6;                  // a plane row length (x halo 3 + 3)
-    constexpr int AY = (D == 3) ? TY + 6 : 1;   // a plane rows
-    __shared__ T sA[AY * AX];
-    __shared__ T sUx[TY * AX];
-    __shared__ T sUy[(D == 3) ? (TY + 6) * TX : 1];
-    __shared__ T sFx[TY * (TX + 1)];
-    __shared__ T sFy[(D == 3) ? (TY + 1) * TX : 1];
-
-    const int tid = threadIdx.x;
-    const int tx = tid % TX, ty = tid / TX;
-    const int x0 = bx * TX, y0 = by * TY;
-    const int gxl = x0 + tx, gyl = y0 + ty;         // own column (may be outside)
-    const bool active = FULL || (gxl < g.nx && (D == 2 || gyl < g.ny));
-    const int xw = active ? gxl : gxl % g.nx;       // wrapped column for loads
-    const int yw = (D == 3) ? (active ? gyl : gyl % g.ny) : 0;
-    const int col = xw + g.nx * yw;                 // < nx * ny
-    const uint32_t colb = (uint32_t)col * (uint32_t)sizeof(T);
-    const int v0 = bz * g.chunk;
-    const int v1 = min(v0 + g.chunk, g.nv);
-
-    const T *__restrict__ ain = (const T *)(STAGE == 1 ? r.c : (STAGE == 2 ? r.c1 : r.c2));
-    const T *__restrict__ ux = (const T *)r.u;
-    const T *__restrict__ uy = ux + g.N;
-    const T *__restrict__ uv = ux + (int64_t)(D - 1) * g.N;
-    const T vs = (T)r.vs, kap = (T)r.kappa_c, eps = (T)r.eps;
-    const bool walls = !g.vper;
-    auto plane = [&](const void *base, int v) -> const void * {
-        return (const char *)base + (int64_t)v * g.sv * (int64_t)sizeof(T);
-    };
-    auto wplane = [&](void *base, int v) -> void * {
-        return (char *)base + (int64_t)v * g.sv * (int64_t)sizeof(T);
-    };
-
-    // vertical index with the wall/periodic rule; sets flip for mirrored nodes
-    auto vidx = [&](int v, bool &flip) -> int {
-        flip = false;
-        if (!walls) {
-            v %= g.nv;
-            return v < 0 ? v + g.nv : v;
-        }
-        if (v < 0) { flip = true; return -1 - v; }
-        if (v >= g.nv) { flip = true; return 2 * g.nv - 1 - v; }
-        return v;
-    };
-    auto load_av = [&](int v, T &a, T &w) {
-        bool flip;
-        const int vv = vidx(v, flip);
-        a = at<T>(plane(ain, vv), colb);
-        const T u = at<T>(plane(uv, vv), colb);
-        w = (flip ? -u : u) - vs;
-    };
-
-    // lateral halo slots of this thread (fixed over the march), as byte
-    // offsets within a plane and LDS indices (-1: no slot)
-    // a-plane cross: rows ty in [0,TY) x cols [0,AX), plus (3D) y-halo rows
-    constexpr int NA = (D == 3) ? AX * TY + TX * 6 : AX;
-    constexpr int NUX = AX * TY;
-    constexpr int NUY = (D == 3) ? TX * (TY + 6) : 0;
-    constexpr int SA = (NA + NT - 1) / NT, SUX = (NUX + NT - 1) / NT, SUY = (NUY + NT - 1) / NT;
-    uint32_t offA[SA];
-    int ldsA[SA];
-    uint32_t offX[SUX];
-    int ldsX[SUX];
-    uint32_t offY[(SUY > 0) ? SUY : 1];
-    int ldsY[(SUY > 0) ? SUY : 1];
-    auto wrapx = [&](int x) { x %= g.nx; return x < 0 ? x + g.nx : x; };
-    auto wrapy = [&](int y) { y %= g.ny; return y < 0 ? y + g.ny : y; };
-    auto lat = [&](int x, int y) { return (uint32_t)(x + g.nx * y) * (uint32_t)sizeof(T); };
-#pragma unroll
-    for (int s = 0; s < SA; ++s) {
-        const int i = tid + s * NT;
-        ldsA[s] = -1;
-        offA[s] = 0;
-        if (i < NA) {
-            int lx, ly;  // plane-local coords, halo origin at (-3, -3)
-            if (i < AX * TY) { lx = i % AX; ly = (D == 3) ? (i / AX) + 3 : 0; }
-            else { const int j = i - AX * TY; lx = (j % TX) + 3; ly = (j / TX) < 3 ? (j / TX) : (j / TX) + TY; }
-            offA[s] = lat(wrapx(x0 + lx - 3), (D == 3) ? wrapy(y0 + ly - 3) : 0);
-            ldsA[s] = ly * AX + lx;
-        }
-    }
-#pragma unroll
-    for (int s = 0; s < SUX; ++s) {
-        const int i = tid + s * NT;
-        ldsX[s] = -1;
-        offX[s] = 0;
-        if (i < NUX) {
-            const int lx = i % AX, ly = i / AX;
-            offX[s] = lat(wrapx(x0 + lx - 3), (D == 3) ? wrapy(y0 + ly) : 0);
-            ldsX[s] = ly * AX + lx;
-        }
-    }
-#pragma unroll
-    for (int s = 0; s < SUY; ++s) {
-        const int i = tid + s * NT;
-        ldsY[s] = -1;
-        offY[s] = 0;
-        if (i < NUY) {
-            const int lx = i % TX, ly = i / TX;
-            offY[s] = lat(wrapx(x0 + lx), wrapy(y0 + ly - 3));
-            ldsY[s] = ly * TX + lx;
-        }
-    }
-
-    // faces on the far edges of the tile (x faces of column TX, y faces of
-    // row TY), taken by the first lanes in one extra pass with strided LDS
-    // reads, so that the main passes are exactly one face per thread
-    constexpr int NEX = (D == 3) ? TY + TX : 1;
-
-    // vertical windows: a and w at v-2 .. v+3 for the face above v
-    T aw[6], ww[6];
-#pragma unroll
-    for (int m = 0; m < 6; ++m) load_av(v0 - 2 + m, aw[m], ww[m]);
-    // face below the first plane
-    T fbelow;
-    if (walls && v0 == 0) {
-        fbelow = -vs * aw[2];                       // absorbing bottom
-    } else {
-        T ab, wb;
-        load_av(v0 - 3, ab, wb);
-        fbelow = face6<T, SCHEME>(ab, aw[0], aw[1], aw[2], aw[3], aw[4], wb, ww[0], ww[1], ww[2],
-                                  ww[3], ww[4], kap, eps);
-    }
-
-    // deposit of stage 3 (D += Vs (C/6 + a1/6 + 2 a2/3) at the bottom cell),
-    // done before the march so that no load or store sits on a path of its own
-    if constexpr (STAGE == 3) {
-        if (walls && v0 == 0 && active) {
-            const double o0 = r.vs * (double)at<T>(plane(r.c, 0), colb);
-            const double o1 = r.vs * (double)at<T>(plane(r.c1, 0), colb);
-            const double o2 = r.vs * (double)aw[2];
-            r.dep[col] += o0 / 6.0 + o1 / 6.0 + 2.0 / 3.0 * o2;
-        }
-    }
-
-    // prefetch registers for the lateral planes
-    T pA[SA], pX[SUX], pY[(SUY > 0) ? SUY : 1];
-    auto prefetch = [&](int v) {
-        bool flip;
-        const int vv = vidx(v, flip);
-        const void *pa = plane(ain, vv), *px = plane(ux, vv), *py = plane(uy, vv);
-        // unconditional: slots without an LDS target read column 0 (in
-        // bounds) and are dropped at publication, so no load sits behind a
-        // branch
-#pragma unroll
-        for (int s = 0; s < SA; ++s) pA[s] = at<T>(pa, offA[s]);
-#pragma unroll
-        for (int s = 0; s < SUX; ++s) pX[s] = at<T>(px, offX[s]);
-#pragma unroll
-        for (int s = 0; s < SUY; ++s) pY[s] = at<T>(py, offY[s]);
-    };
-    prefetch(v0);
-
-    for (int v = v0; v < v1; ++v) {
-        // publish plane v
-#pragma unroll
-        for (int s = 0; s < SA; ++s) if (ldsA[s] >= 0) sA[ldsA[s]] = pA[s];
-#pragma unroll
-        for (int s = 0; s < SUX; ++s) if (ldsX[s] >= 0) sUx[ldsX[s]] = pX[s];
-#pragma unroll
-        for (int s = 0; s < SUY; ++s) if (ldsY[s] >= 0) sUy[ldsY[s]] = pY[s];
-        __syncthreads();
-        // loads, in the order they are consumed (the load counter drains in
-        // issue order, so waiting for one waits for all issued before it):
-        // this cell's C and the vertical pair at v+4, both used at the end of
-        // this plane, then the next lateral plane, used only after the next
-        // barrier and so in flight across this plane's face computation
-        // (past the chunk it is still a valid plane: the vertical rule maps
-        // it inside)
-        T cown = (T)0;
-        if (STAGE != 1) cown = at<T>(plane(r.c, v), colb);
-        T anext, wnext;
-        load_av(v + 4, anext, wnext);
-        prefetch(v + 1);
-
-        // lateral faces: each thread the x face on the left of its cell and
-        // (3D) the y face below it
-        {
-            const T *ar = sA + ((D == 3) ? (ty + 3) : 0) * AX + tx;   // nodes tx-3 .. tx+2
-            const T *ur = sUx + ty * AX + tx;
-            sFx[ty * (TX + 1) + tx] = face6<T, SCHEME>(ar[0], ar[1], ar[2], ar[3], ar[4], ar[5], ur[0],
-                                                        ur[1], ur[2], ur[3], ur[4], ur[5], kap, eps);
-        }
-        if constexpr (D == 3) {
-            const T *ac = sA + ty * AX + tx + 3;      // rows ty-3+3 .. ty+2+3 of column tx
-            const T *uc = sUy + ty * TX + tx;
-            sFy[ty * TX + tx] = face6<T, SCHEME>(ac[0], ac[AX], ac[2 * AX], ac[3 * AX], ac[4 * AX],
-                                                 ac[5 * AX], uc[0], uc[TX], uc[2 * TX], uc[3 * TX],
-                                                 uc[4 * TX], uc[5 * TX], kap, eps);
-        }
-        for (int e = tid; e < NEX; e += NT) {
-            const bool xf = e < TY;                   // x face of column TX, row e
-            const int fy = xf ? e : TY, fx = xf ? TX : e - TY;
-            const T *ar = xf ? sA + ((D == 3) ? (fy + 3) : 0) * AX + fx : sA + fx + 3;
-            const T *ur = xf ? sUx + fy * AX + fx : sUy + fx;
-            const int sa = xf ? 1 : AX, su = xf ? 1 : TX;
-            if constexpr (D == 3) {
-                if (!xf) { ar += fy * AX; ur += fy * TX; }
-            }
-            const T f = face6<T, SCHEME>(ar[0], ar[sa], ar[2 * sa], ar[3 * sa], ar[4 * sa], ar[5 * sa],
-                                         ur[0], ur[su], ur[2 * su], ur[3 * su], ur[4 * su], ur[5 * su],
-                                         kap, eps);
-            if (xf) sFx[fy * (TX + 1) + fx] = f;
-            else if constexpr (D == 3) sFy[fy * TX + fx] = f;
-        }
-        // vertical face above this cell
-        T fabove;
-        if (walls && v == g.nv - 1)
-            fabove = (T)0;
-        else
-            fabove = face6<T, SCHEME>(aw[0], aw[1], aw[2], aw[3], aw[4], aw[5], ww[0], ww[1], ww[2],
-                                      ww[3], ww[4], ww[5], kap, eps);
-        __syncthreads();
-        T L = -(fabove - fbelow);
-        L -= sFx[ty * (TX + 1) + tx + 1] - sFx[ty * (TX + 1) + tx];
-        if constexpr (D == 3) L -= sFy[(ty + 1) * TX + tx] - sFy[ty * TX + tx];
-        const T a = aw[2];
-        if (active) {
-            if constexpr (STAGE == 1) {
-                *(T *)((char *)wplane(r.c1, v) + colb) = a + L;
-            } else if constexpr (STAGE == 2) {
-                *(T *)((char *)wplane(r.c2, v) + colb) = (T)0.75 * cown + (T)0.25 * a + (T)0.25 * L;
-            } else {
-                *(T *)((char *)wplane(r.c, v) + colb) = (T)(1.0 / 3.0) * cown + (T)(2.0 / 3.0) * a + (T)(2.0 / 3.0) * L;
-            }
-        }
-        fbelow = fabove;
-#pragma unroll
-        for (int m = 0; m < 5; ++m) { aw[m] = aw[m + 1]; ww[m] = ww[m + 1]; }
-        aw[5] = anext;
-        ww[5] = wnext;
-        __syncthreads();
-    }
-}
-
-template <typename T, int D, int SCHEME, int STAGE, int TX, int TY, bool FULL>
-__global__ void __launch_bounds__(TX *TY) k_stage_tiled(RunDev r, TileGeom g) {
-    int bx, by, bz;
-    block_tile(g, bx, by, bz);
-    stage_tile<T, D, SCHEME, STAGE, TX, TY, FULL>(r, g, bx, by, bz);
-}
-
-template <int D>
-__host__ __device__ inline TileGeom make_geom(const RunDev &r, int chunk, int TX, int TY) {
-    TileGeom g;
-    g.nx = r.nx;
-    g.ny = (D == 3) ? r.ny : 1;
-    g.nv = (D == 3) ? r.nz : r.ny;
-    g.sv = (D == 3) ? (int64_t)r.nx * r.ny : (int64_t)r.nx;
-    g.N = r.N;
-    g.vper = r.vper;
-    g.chunk = chunk < g.nv ? chunk : g.nv;
-    g.gx = (r.nx + TX - 1) / TX;
-    g.gy = (D == 3) ? (r.ny + TY - 1) / TY : 1;
-    g.gz = (g.nv + g.chunk - 1) / g.chunk;
-    g.bz0 = 0;
-    return g;
-}
-
-// Batched form: one persistent grid walks the tiles of every run.  Each XCD
-// takes a contiguous range of the global tile list (runs in order, tiles of
-// a run x-fastest), so neighbouring tiles share an L2.  tile_start[b] is the
-// first global tile of run b (prefix sum, nbatch + 1 entries).
-template <typename T, int D, int SCHEME, int STAGE, int TX, int TY>
-__global__ void __launch_bounds__(TX *TY) k_stage_batched(const RunDev *__restrict__ runs,
-                                                          const int *__restrict__ tile_start,
-                                                          int nbatch, int chunk, int sflip) {
-    const int total = tile_start[nbatch];
-    const int G = gridDim.x;
-    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
-    const int per_xcd = (G + 7 - xcd) >> 3;               // blocks on this XCD
-    const int lo = (int)((int64_t)total * xcd / 8), hi = (int)((int64_t)total * (xcd + 1) / 8);
-    for (int w = lo + slot; w < hi; w += per_xcd) {
-        int b = 0;
-        while (tile_start[b + 1] <= w) ++b;                // runs are few; linear scan
-        RunDev r = runs[b];
-        if (sflip) { void *t = r.s; r.s = r.s2; r.s2 = t; }
-        const TileGeom g = make_geom<D>(r, chunk, TX, TY);
-        const int t = w - tile_start[b];
-        const int bx = t % g.gx, rest = t / g.gx;
-        stage_tile<T, D, SCHEME, STAGE, TX, TY, false>(r, g, bx, rest % g.gy, rest / g.gy);
-    }
-}
-
-// The whole-tile form when the grid divides into tiles, else the masked one.
-template <typename T, int D, int SCHEME, int STAGE, int TX, int TY>
-void launch_stage(const RunDev &r, const TileGeom &g, unsigned nb, hipStream_t st) {
-    if (g.nx % TX == 0 && (D == 2 || g.ny % TY == 0))
-        k_stage_tiled<T, D, SCHEME, STAGE, TX, TY, true><<<nb, TX * TY, 0, st>>>(r, g);
-    else
-        k_stage_tiled<T, D, SCHEME, STAGE, TX, TY, false><<<nb, TX * TY, 0, st>>>(r, g);
-}
-
-template <typename T, int D, int SCHEME, int TX, int TY>
-hipError_t stages(const RunDev &r, int chunk, hipStream_t st) {
-    const TileGeom g = make_geom<D>(r, chunk, TX, TY);
-    const int64_t nb = (int64_t)g.gx * g.gy * g.gz;
-    if (nb > 0x7fffffff) return hipErrorInvalidValue;
-    launch_stage<T, D, SCHEME, 1, TX, TY>(r, g, (unsigned)nb, st);
-    launch_stage<T, D, SCHEME, 2, TX, TY>(r, g, (unsigned)nb, st);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (r.has_s) {
-        e = launch_s_update(D, sizeof(T) == 4 ? LBW_FP32_SHIFTED : LBW_FP64, r, st);
-        if (e != hipSuccess) return e;
-    }
-    launch_stage<T, D, SCHEME, 3, TX, TY>(r, g, (unsigned)nb, st);
-    return hipGetLastError();
-}
-
-template <typename T, int D, int SCHEME, int TX, int TY>
-hipError_t stage_slab_t(const RunDev &r, int chunk, int stage, int v_lo, int v_hi, hipStream_t st) {
-    TileGeom g = make_geom<D>(r, chunk, TX, TY);
-    const int c0 = v_lo / g.chunk, c1 = (v_hi + g.chunk - 1) / g.chunk;
-    if (v_lo % g.chunk || c1 > g.gz || c0 >= c1) return hipErrorInvalidValue;
-    g.bz0 = c0;
-    g.gz = c1 - c0;
-    const int64_t nb = (int64_t)g.gx * g.gy * g.gz;
-    if (stage == 1) launch_stage<T, D, SCHEME, 1, TX, TY>(r, g, (unsigned)nb, st);
-    else if (stage == 2) launch_stage<T, D, SCHEME, 2, TX, TY>(r, g, (unsigned)nb, st);
-    else launch_stage<T, D, SCHEME, 3, TX, TY>(r, g, (unsigned)nb, st);
-    return hipGetLastError();
-}
-
-// Calls fn(integral_constant TX, integral_constant TY) for the tile shape:
-// 3D 32x8, 64x4, 128x2 (256 threads), 32x16, 64x8 (512 threads); 2D one row
-// of 64, 128, 256 or 512 columns.
-template <int D, typename F>
-hipError_t with_tile(const TileShape &sh, F &&fn) {
-    using std::integral_constant;
-    if constexpr (D == 3) {
-        if (sh.tx == 64 && sh.ty == 8) return fn(integral_constant<int, 64>{}, integral_constant<int, 8>{});
-        if (sh.tx == 32 && sh.ty == 16) return fn(integral_constant<int, 32>{}, integral_constant<int, 16>{});
-        if (sh.tx == 64) return fn(integral_constant<int, 64>{}, integral_constant<int, 4>{});
-        if (sh.tx == 128) return fn(integral_constant<int, 128>{}, integral_constant<int, 2>{});
-        return fn(integral_constant<int, 32>{}, integral_constant<int, 8>{});
-    } else {
-        if (sh.tx == 64) return fn(integral_constant<int, 64>{}, integral_constant<int, 1>{});
-        if (sh.tx == 128) return fn(integral_constant<int, 128>{}, integral_constant<int, 1>{});
-        if (sh.tx == 512) return fn(integral_constant<int, 512>{}, integral_constant<int, 1>{});
-        return fn(integral_constant<int, 256>{}, integral_constant<int, 1>{});
-    }
-}
-
-template <typename T, int D, int SCHEME>
-hipError_t stage_slab_shape(const RunDev &r, const lbw_launch &l, int stage, int v_lo, int v_hi,
-                            hipStream_t st) {
-    const TileShape sh = resolve_tile_shape(D, l);
-    return with_tile<D>(sh, [&](auto tx, auto ty) {
-        return stage_slab_t<T, D, SCHEME, decltype(tx)::value, decltype(ty)::value>(r, sh.chunk, stage, v_lo,
-                                                                                  v_hi, st);
-    });
-}
-
-template <typename T, int D>
-hipError_t stage_slab_d(const RunDev &r, const lbw_launch &l, int stage, int v_lo, int v_hi,
-                        hipStream_t st) {
-    switch (r.scheme) {
-        case LBW_WENO5: return stage_slab_shape<T, D, LBW_WENO5>(r, l, stage, v_lo, v_hi, st);
-        case LBW_WENO3: return stage_slab_shape<T, D, LBW_WENO3>(r, l, stage, v_lo, v_hi, st);
-        case LBW_UPWIND1: return stage_slab_shape<T, D, LBW_UPWIND1>(r, l, stage, v_lo, v_hi, st);
-    }
-    return hipErrorInvalidValue;
-}
-
-template <typename T, int D, int SCHEME, int TX, int TY>
-hipError_t stages_batched(const BatchArgs &a, hipStream_t st) {
-    k_stage_batched<T, D, SCHEME, 1, TX, TY><<<a.grid, TX * TY, 0, st>>>(a.runs, a.tile_start, a.nbatch, a.chunk, a.sflip);
-    k_stage_batched<T, D, SCHEME, 2, TX, TY><<<a.grid, TX * TY, 0, st>>>(a.runs, a.tile_start, a.nbatch, a.chunk, a.sflip);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (a.host_runs[0].has_s) {
-        for (int b = 0; b < a.nbatch; ++b) {
-            RunDev r = a.host_runs[b];
-            if (!r.has_s) continue;       // size classes after the first of a run
-            if (a.sflip) { void *t = r.s; r.s = r.s2; r.s2 = t; }
-            e = launch_s_update(D, sizeof(T) == 4 ? LBW_FP32_SHIFTED : LBW_FP64, r, st);
-            if (e != hipSuccess) return e;
-        }
-    }
-    k_stage_batched<T, D, SCHEME, 3, TX, TY><<<a.grid, TX * TY, 0, st>>>(a.runs, a.tile_start, a.nbatch, a.chunk, a.sflip);
-    return hipGetLastError();
-}
-
-template <typename T, int D, int SCHEME>
-hipError_t stages_shape(const RunDev &r, const lbw_launch &l, hipStream_t st, const BatchArgs *batch) {
-    const TileShape sh = resolve_tile_shape(D, l);
-    return with_tile<D>(sh, [&](auto tx, auto ty) {
-        constexpr int TX = decltype(tx)::value, TY = decltype(ty)::value;
-        return batch ? stages_batched<T, D, SCHEME, TX, TY>(*batch, st)
-                     : stages<T, D, SCHEME, TX, TY>(r, sh.chunk, st);
-    });
-}
-
-template <typename T, int D>
-hipError_t tiled_d(const RunDev &r, const lbw_launch &l, hipStream_t st, const BatchArgs *b) {
-    switch (r.scheme) {
-        case LBW_WENO5: return stages_shape<T, D, LBW_WENO5>(r, l, st, b);
-        case LBW_WENO3: return stages_shape<T, D, LBW_WENO3>(r, l, st, b);
-        case LBW_UPWIND1: return stages_shape<T, D, LBW_UPWIND1>(r, l, st, b);
-    }
-    return hipErrorInvalidValue;
-}
-
-}  // namespace
 
 TileShape resolve_tile_shape(int dim, const lbw_launch &l) {
     TileShape s;
@@ -560,13 +26,13 @@ int64_t transport_tiles(int dim, const RunDev &r, const lbw_launch &l) {
 
 hipError_t launch_transport_tiled(int dim, int precision, const RunDev &r, const lbw_launch &l,
                                   hipStream_t st) {
-    if (precision == LBW_FP32_SHIFTED)
-        return dim == 2 ? tiled_d<float, 2>(r, l, st, nullptr) : tiled_d<float, 3>(r, l, st, nullptr);
-    return dim == 2 ? tiled_d<double, 2>(r, l, st, nullptr) : tiled_d<double, 3>(r, l, st, nullptr);
+    if (r.vs_s != 0.0) return launch_transport_tiled_vs(dim, precision, r, l, st, nullptr);
+    return tiled_any<false>(dim, precision, r, l, st, nullptr);
 }
 
 hipError_t launch_stage_slab(int dim, int precision, const RunDev &r, const lbw_launch &l,
                              int stage, int v_lo, int v_hi, hipStream_t st) {
+    if (r.vs_s != 0.0) return hipErrorInvalidValue;   // such runs take the sequential order
     if (precision == LBW_FP32_SHIFTED)
         return dim == 2 ? stage_slab_d<float, 2>(r, l, stage, v_lo, v_hi, st)
                         : stage_slab_d<float, 3>(r, l, stage, v_lo, v_hi, st);
@@ -577,9 +43,12 @@ hipError_t launch_stage_slab(int dim, int precision, const RunDev &r, const lbw_
 hipError_t launch_transport_batched(int dim, int precision, const BatchArgs &b, const lbw_launch &l,
                                     hipStream_t st) {
     const RunDev &r = b.host_runs[0];
-    if (precision == LBW_FP32_SHIFTED)
-        return dim == 2 ? tiled_d<float, 2>(r, l, st, &b) : tiled_d<float, 3>(r, l, st, &b);
-    return dim == 2 ? tiled_d<double, 2>(r, l, st, &b) : tiled_d<double, 3>(r, l, st, &b);
+    // one settling form per launch: if any run's settling speed depends on
+    // S, every entry takes that form (vs_s = 0 then gives the constant speed
+    // exactly, and the runs of a batch all carry S)
+    for (int i = 0; i < b.nbatch; ++i)
+        if (b.host_runs[i].vs_s != 0.0) return launch_transport_tiled_vs(dim, precision, r, l, st, &b);
+    return tiled_any<false>(dim, precision, r, l, st, &b);
 }
 
 }  // namespace lbw

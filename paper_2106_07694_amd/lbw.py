@@ -56,6 +56,7 @@ class CConfig(ctypes.Structure):
         ("weno_eps", ctypes.c_double),
         ("vs_class", ctypes.c_double * MAX_CLASSES),
         ("kappa_class", ctypes.c_double * MAX_CLASSES),
+        ("vs_s", ctypes.c_double), ("phi_c", ctypes.c_double),
     ]
 
 
@@ -149,6 +150,11 @@ class RunConfig:
     n_classes: int = 1
     vs_class: tuple = ()
     kappa_class: tuple = ()
+    # the paper's full force and settling (need has_s): settling speed
+    # Vs (1 - vs_s S) (eq. 13) and S buoyancy on the fluid fraction
+    # -gp_s S (1 - phi_c C) (eq. 10)
+    vs_s: float = 0.0
+    phi_c: float = 0.0
 
     @property
     def ncls(self) -> int:
@@ -187,6 +193,7 @@ class RunConfig:
         if not 0 <= self.n_classes <= MAX_CLASSES:
             raise ValueError(f"n_classes must lie in [0, {MAX_CLASSES}]")
         c.n_classes = self.n_classes if self.n_classes > 1 else 0
+        c.vs_s, c.phi_c = self.vs_s, self.phi_c
         if self.n_classes > 1:
             if len(self.vs_class) != self.n_classes or len(self.kappa_class) != self.n_classes:
                 raise ValueError("vs_class and kappa_class need one value per class")

@@ -18,7 +18,8 @@ def oracle_cfg(cfg: lbw.RunConfig) -> OracleConfig:
                         body_force=tuple(cfg.body_force), u_top=tuple(cfg.u_top), vs=cfg.vs,
                         kappa_c=cfg.kappa_c, gp_c=cfg.gp_c, kappa_s=cfg.kappa_s,
                         gp_s=cfg.gp_s, weno_eps=cfg.weno_eps, n_classes=cfg.n_classes,
-                        vs_class=tuple(cfg.vs_class), kappa_class=tuple(cfg.kappa_class))
+                        vs_class=tuple(cfg.vs_class), kappa_class=tuple(cfg.kappa_class),
+                        vs_s=cfg.vs_s, phi_c=cfg.phi_c)
 
 
 def as_input(x, cfg: lbw.RunConfig):

@@ -27,7 +27,7 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_version():
-    assert lbw.load().lbw_version() == 2
+    assert lbw.load().lbw_version() == 3
 
 
 def test_struct_layouts_match_the_header(tmp_path):
@@ -99,6 +99,9 @@ def test_valid_config_creates():
     (dict(n_classes=2, vs=1e-3, vs_class=(1e-3, 2e-3), kappa_class=(0.0, 0.0)), "vs_class"),
     (dict(n_classes=2, vs_class=(1e-3, 2.0), kappa_class=(0.0, 0.0)), "vs_class[1]"),
     (dict(n_classes=3, vs_class=(0.0,) * 3, kappa_class=(0.0, 0.0, 0.3)), "kappa_class[2]"),
+    (dict(vs_s=0.1), "has_s"),
+    (dict(phi_c=0.1), "has_s"),
+    (dict(has_s=True, vs_s=float("inf")), "finite"),
 ])
 def test_invalid_configs_rejected(bad, frag):
     rc, msg = _create([lbw.RunConfig(**bad)])

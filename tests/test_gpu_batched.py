@@ -76,6 +76,33 @@ def test_batched_equals_one_at_a_time(precision, has_s):
     sol.close()
 
 
+@pytest.mark.parametrize("grids", [((24, 30), (40, 24)), ((16, 36), (8, 12), (20, 7))])
+def test_batch_with_fewer_tiles_than_xcds(grids):
+    """A batch whose runs hold fewer transport tiles in total than the chip has
+    XCDs (here 2 and 4 tiles): every tile is still computed, so each run
+    equals itself alone bit for bit."""
+    import torch
+    cfgs = [lbw.RunConfig(precision="fp64", nx=nx, ny=ny, tau=0.6, vs=1e-3 * (i + 1), kappa_c=1e-3,
+                          gp_c=2e-4, has_s=True, kappa_s=1e-3, gp_s=1e-4)
+            for i, (nx, ny) in enumerate(grids)]
+    sol = lbw.Solver(cfgs)
+    _setup(sol, cfgs)
+    sol.step(5)
+    torch.cuda.synchronize()
+    for i, c in enumerate(cfgs):
+        one = lbw.Solver(c)
+        c0, s0 = _inputs(c, 100 + i)
+        one.set_field("c", c0)
+        one.set_field("s", s0)
+        one.init_equilibrium()
+        one.step(5)
+        a, b = _state(sol, i), _state(one, 0)
+        for k in a:
+            assert np.array_equal(a[k], b[k]), (i, k)
+        one.close()
+    sol.close()
+
+
 def test_batched_fp64_matches_oracle():
     import torch
     cfgs = _runs("fp64", has_s=True)

@@ -1,0 +1,172 @@
+"""GPU parity of the paper's full force and settling (eq. 7, 10, 13) against
+the FP64 oracle: a settling speed set by the local fluid density, Vs (1 -
+vs_s S), and the buoyancy of S on the fluid fraction, -gp_s S (1 - phi_c C).
+
+FP64 within 1e-12 of the oracle (velocity with the population-scale floor of
+the other parity tests), FP32 shifted within the FP32 bounds; the closed form
+of the settling-gradient term holds on the GPU; runs that need the variable
+form and runs that do not share a batch bit for bit.
+"""
+import numpy as np
+import pytest
+
+from paper_2106_07694_amd import lbw
+
+from parity import as_input, compare, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+TOL64 = 1e-12
+
+
+def _cfg(lattice=9, **kw):
+    base = dict(lattice=lattice, tau=0.6 if lattice == 9 else 0.55, vs=3e-3, kappa_c=1e-3,
+                gp_c=3e-4, has_s=True, kappa_s=1e-3, gp_s=2e-4, vs_s=0.6, phi_c=0.3)
+    base.update(dict(nx=37, ny=29) if lattice == 9 else dict(nx=11, ny=9, nz=16))
+    base.update(kw)
+    return lbw.RunConfig(**base)
+
+
+def _fields(cfg, seed):
+    """C uniform-random; S stratified (heavier below) with noise, so the
+    settling speed varies in space."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0, 1, cfg.c_shape)
+    nv = cfg.ny if cfg.dim == 2 else cfg.nz
+    v = np.arange(nv, dtype=np.float64)
+    v = v[None, :, None] if cfg.dim == 2 else v[:, None, None]
+    s = (1.0 - v / nv) * np.ones(cfg.shape) + 0.1 * rng.uniform(-1, 1, cfg.shape)
+    return as_input(c, cfg), as_input(s, cfg)
+
+
+def _check(cfg, nsteps, launch=None, seed=31):
+    c0, s0 = _fields(cfg, seed)
+    g = run_gpu(cfg, c0, s0, None, None, nsteps, launch=launch)
+    o = run_oracle(cfg, c0, s0, None, None, nsteps)
+    errs = compare(g, o)
+    print(f"\n{cfg.lattice} {cfg.precision} vs_s={cfg.vs_s} phi_c={cfg.phi_c}: {errs}")
+    bad = {k: v for k, v in errs.items() if k != "u" and not v <= TOL64}
+    assert not bad, errs
+    if "f" in o:
+        du = float(np.max(np.abs(g["u"] - o["u"])))
+        bound = TOL64 * float(np.max(np.abs(o["u"]))) + 64 * np.finfo(np.float64).eps * float(np.max(np.abs(o["f"])))
+        assert du <= bound, (du, bound)
+    return g, o
+
+
+@pytest.mark.parametrize("kw", [
+    dict(),
+    dict(phi_c=0.0),
+    dict(vs_s=0.0),
+    dict(scheme_c="weno3"),
+    dict(scheme_c="upwind1", vert_periodic=True),
+    dict(precision="fp64_shifted", u_top=(0.02, 0, 0)),
+    dict(n_classes=2, vs=0.0, kappa_c=0.0, vs_class=(3e-3, 1e-3), kappa_class=(1e-3, 5e-4)),
+    dict(lattice=19),
+    dict(lattice=19, n_classes=3, vs=0.0, kappa_c=0.0, vs_class=(3e-3, 2e-3, 5e-4),
+         kappa_class=(1e-3, 1e-3, 0.0)),
+])
+def test_full_force_matches_oracle_fp64(kw):
+    lattice = kw.pop("lattice", 9)
+    _check(_cfg(lattice, **kw), 20)
+
+
+@pytest.mark.parametrize("launch", [dict(variant=1), dict(tile_x=64, tile_y=5),
+                                    dict(variant=2, slabs=3)])
+def test_every_transport_form(launch):
+    """Plain and tiled kernels agree with the oracle; the pipelined variant
+    runs such a run in the sequential order."""
+    _check(_cfg(9, nx=150, ny=37), 9, launch=launch)
+
+
+@pytest.mark.parametrize("launch", [dict(), dict(tile_x=64, tile_rows=8, tile_y=4), dict(variant=1)])
+def test_every_transport_form_3d(launch):
+    _check(_cfg(19, nx=40, ny=10, nz=14), 8, launch=launch)
+
+
+@pytest.mark.parametrize("lattice", [9, 19])
+def test_full_force_fp32_shifted(lattice):
+    cfg = _cfg(lattice, precision="fp32_shifted")
+    c0, s0 = _fields(cfg, 32)
+    g = run_gpu(cfg, c0, s0, None, None, 50)
+    o = run_oracle(cfg, c0, s0, None, None, 50)
+    errs = compare(g, o)
+    print(f"\nfp32 {lattice}: {errs}")
+    bounds = {"c": 3e-5, "u": 1e-4, "s": 1e-5, "f": 1e-4, "deposit": 1e-5}
+    assert all(errs[k] <= bounds[k] for k in errs), errs
+
+
+@pytest.mark.parametrize("lattice", [9, 19])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_shifted"])
+def test_settling_gradient_closed_form(lattice, precision):
+    """At rest, no diffusion, S linear in height, C uniform: every cell three
+    stencils clear of the walls grows by 1 + lam + lam^2/2 + lam^3/6 per
+    step, lam = -vs vs_s dS/dz (the -phi d(Vs)/dz term of eq. 7)."""
+    vs, vs_s, s_b, c0 = 4e-3, 0.5, -0.02, 0.7
+    kw = dict(nx=8, ny=40) if lattice == 9 else dict(nx=5, ny=4, nz=40)
+    cfg = lbw.RunConfig(lattice=lattice, precision=precision, fluid_mode=lbw.FLUID_FROZEN,
+                        vs=vs, vs_s=vs_s, has_s=True, **kw)
+    nv = 40
+    v = np.arange(nv, dtype=np.float64)
+    v = v[None, :, None] if cfg.dim == 2 else v[:, None, None]
+    s = as_input(0.9 + s_b * v * np.ones(cfg.shape), cfg)
+    u = np.zeros((cfg.dim,) + cfg.shape)
+    g = run_gpu(cfg, np.full(cfg.shape, c0), s, u, None, 1)
+    lam = -vs * vs_s * s_b
+    want = c0 * (1 + lam + lam**2 / 2 + lam**3 / 6)
+    zz = v * np.ones(cfg.shape)
+    sel = (zz >= 9) & (zz <= nv - 10)
+    tol = 1e-14 if precision == "fp64" else 5e-7     # a few ulps of C in FP32
+    err = np.max(np.abs(g["c"][sel] - want))
+    assert err <= tol, err
+    assert np.array_equal(g["s"], s)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_shifted"])
+def test_uniform_s_is_the_scaled_constant_speed_bitwise(precision):
+    """S uniform (and kept so by a uniform lateral flow): Vs (1 - vs_s S) with
+    exactly representable factors equals the constant speed it scales to."""
+    vs, vs_s, s0 = 2.0 ** -8, 0.5, 0.5
+    kw = dict(lattice=19, nx=10, ny=8, nz=12, precision=precision, fluid_mode=lbw.FLUID_FROZEN,
+              kappa_c=1e-3, has_s=True, kappa_s=1e-3)
+    var = lbw.RunConfig(vs=vs, vs_s=vs_s, **kw)
+    const = lbw.RunConfig(vs=vs * (1 - vs_s * s0), **kw)
+    c0 = as_input(np.random.default_rng(33).uniform(0, 1, var.shape), var)
+    s = np.full(var.shape, s0)
+    u = np.zeros((3,) + var.shape)
+    u[0] = 0.03
+    g1 = run_gpu(var, c0, s, u, None, 10)
+    g2 = run_gpu(const, c0, s, u, None, 10)
+    for k in ("c", "deposit", "s"):
+        assert np.array_equal(g1[k], g2[k]), k
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+def test_batch_mixing_settling_forms(graph):
+    """A run with a variable settling speed and one without share a batch:
+    the batch takes the variable form for every entry, and each run equals
+    itself alone bit for bit."""
+    import torch
+
+    cfgs = [_cfg(9, nx=24, ny=30, precision="fp32_shifted"),
+            _cfg(9, nx=40, ny=24, precision="fp32_shifted", vs_s=0.0, phi_c=0.0),
+            _cfg(9, nx=16, ny=36, precision="fp32_shifted", n_classes=2, vs=0.0, kappa_c=0.0,
+                 vs_class=(3e-3, 1e-3), kappa_class=(1e-3, 5e-4))]
+    fields = [_fields(c, 40 + i) for i, c in enumerate(cfgs)]
+    sol = lbw.Solver(cfgs, stream=torch.cuda.Stream())
+    sol.set_launch(graph=graph)
+    for r, (c, s) in enumerate(fields):
+        sol.set_field("c", c, run=r)
+        sol.set_field("s", s, run=r)
+        sol.init_equilibrium(run=r)
+    sol.step(10)
+    torch.cuda.synchronize()
+    got = [{k: sol.field(k, run=r).cpu().numpy() for k in ("f", "c", "s", "deposit")} for r in range(3)]
+    sol.close()
+    diffs = {}
+    for r, cfg in enumerate(cfgs):
+        alone = run_gpu(cfg, fields[r][0], fields[r][1], nsteps=10)
+        for k in ("f", "c", "s", "deposit"):
+            d = np.abs(got[r][k].astype(np.float64) - alone[k])
+            diffs[(r, k)] = (float(d.max()), int((d > 0).sum()))
+    print("\nbatch - alone (max, count):", diffs)
+    assert all(v[0] == 0.0 for v in diffs.values()), diffs
