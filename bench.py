@@ -365,6 +365,8 @@ def main() -> int:
     ap.add_argument("--adjoint-steps", type=int, default=5000)
     ap.add_argument("--no-classes", action="store_true",
                     help="skip the four-size-class run of the 3D workload")
+    ap.add_argument("--no-full-force", action="store_true",
+                    help="skip the 2D two-scalar run with the full force and settling")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the FP32-vs-FP64 error report of the 2D workload")
     ap.add_argument("--precision-steps", type=int, default=20000)
@@ -419,6 +421,13 @@ def main() -> int:
                 "step_alg_bytes_per_cell": _alg_bytes(W.C6)["step"],
                 "collide_stream_alg_gbs": p["roofline"]["achieved"]}
         print(f"[bench] {W.C6.name}: {p['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+    full = None
+    if not args.no_full_force:
+        p = run_gpu(W.C7, min(args.steps, 500), args.warmup, diagnostics=False, tuned_as=W.C2)
+        full = {"workload": W.C7.name, "vs_s": W.C7.vs_s, "phi_c": W.C7.phi_c, "value": p["mlups"],
+                "unit": "MLUPS", "ms_per_step": p["ms_per_step"],
+                "phase_ms_per_step": p["phase_ms_per_step"], "step_alg_gbs": p["step_alg_gbs"]}
+        print(f"[bench] {W.C7.name}: {p['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
     prec = None
     if not args.no_precision:
         prec = run_precision(args.precision_steps)
@@ -460,6 +469,7 @@ def main() -> int:
         "adjoint": adj,
         "fp32_vs_fp64": prec,
         "size_classes": poly,
+        "full_force": full,
         "copy_calibration": copy,
     }
     print(json.dumps(line))

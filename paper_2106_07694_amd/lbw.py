@@ -211,7 +211,8 @@ class RunConfig:
         kw = dict(lattice=wl.q, precision=wl.precision, nx=wl.nx, ny=wl.ny, nz=wl.nz,
                   tau=wl.tau, vs=wl.vs, kappa_c=wl.kappa_c, gp_c=wl.gp_c, has_s=wl.has_s,
                   kappa_s=wl.kappa_s, gp_s=wl.gp_s, n_classes=wl.n_classes,
-                  vs_class=tuple(wl.vs_class), kappa_class=tuple(wl.kappa_class))
+                  vs_class=tuple(wl.vs_class), kappa_class=tuple(wl.kappa_class),
+                  vs_s=wl.vs_s, phi_c=wl.phi_c)
         kw.update(over)
         return RunConfig(**kw)
 

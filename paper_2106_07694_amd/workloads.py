@@ -45,6 +45,10 @@ class Workload:
     n_classes: int = 1
     vs_class: tuple = ()
     kappa_class: tuple = ()
+    # full force and settling (eq. 10, 13): Vs (1 - vs_s S), S buoyancy on
+    # the fluid fraction 1 - phi_c C
+    vs_s: float = 0.0
+    phi_c: float = 0.0
 
     @property
     def dim(self) -> int:
@@ -89,6 +93,9 @@ C6 = Workload("3d_d3q19_fp32_256x256x512_4classes", q=19, nx=256, ny=256, nz=512
               precision="fp32_shifted", tau=0.55, vs=0.0, kappa_c=0.0, gp_c=1e-5,
               steps=2000, seed=1005, n_classes=4, vs_class=(2.5e-4, 5e-4, 7.5e-4, 1e-3),
               kappa_class=(5e-4, 5e-4, 5e-4, 5e-4))
+# The 2D two-scalar workload with the full force and settling: particles
+# settle at half speed in the sugar layer (S = 1) and phi = 1e-3 C.
+C7 = C2.replace(name="2d_fp32_shifted_s_1024x2048_full_force", vs_s=0.5, phi_c=1e-3, seed=1006)
 SWEEP_GRIDS = ((128, 256), (256, 512), (512, 1024))
 SWEEP_RUNS = 64
 SWEEP_STEPS = 5000
