@@ -21,6 +21,15 @@ import torch
 from . import lbw
 
 
+def check_supported(cfg: lbw.RunConfig) -> None:
+    """The adjoint kernels cover the WENO5 transport of one particle class
+    without S (so without the S-dependent settling and force either); raise
+    before any step is taken otherwise."""
+    if cfg.scheme_c != "weno5" or cfg.has_s or cfg.ncls > 1:
+        raise ValueError("the adjoint covers WENO5 transport of one particle class without S "
+                         f"(got scheme {cfg.scheme_c}, has_s {cfg.has_s}, {cfg.ncls} classes)")
+
+
 def default_segment(nsteps: int) -> int:
     return max(1, int(round(math.sqrt(nsteps))))
 
@@ -56,6 +65,7 @@ def forward_with_checkpoints(cfg, c0: torch.Tensor, vs: float, nsteps: int, seg:
     """Run nsteps from C = c0 and the fluid at rest (or the canonical
     populations f0; or, for a frozen fluid, the velocity u); return
     (J, solver, checkpoints {step: (f, c)})."""
+    check_supported(cfg)
     sol = _solver(cfg, vs, launch)
     sol.set_field("c", c0)
     frozen = cfg.fluid_mode == lbw.FLUID_FROZEN

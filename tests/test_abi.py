@@ -237,3 +237,14 @@ def test_scratch_bytes():
     assert lib.lbw_scratch_bytes(arr, 3, ctypes.byref(n)) == 0
     assert n.value >= 3 * 8
     assert lib.lbw_scratch_bytes(arr, 0, ctypes.byref(n)) == lbw.ERR_INVAL
+
+
+def test_adjoint_wrapper_refuses_what_the_kernels_do_not_cover():
+    """The autograd wrapper checks its configuration before the forward sweep
+    (host logic only)."""
+    from paper_2106_07694_amd import adjoint
+    adjoint.check_supported(lbw.RunConfig(vs=1e-3, kappa_c=1e-3))
+    for bad in (dict(scheme_c="weno3"), dict(has_s=True),
+                dict(n_classes=2, vs_class=(1e-3, 2e-3), kappa_class=(0.0, 0.0))):
+        with pytest.raises(ValueError):
+            adjoint.check_supported(lbw.RunConfig(**bad))
