@@ -52,12 +52,17 @@ def _samples(wl, n, seed):
     return pts
 
 
-@pytest.mark.parametrize("wl", [W.C3, W.C2], ids=["3d_256x256x512", "2d_1024x2048_s"])
-def test_full_size_one_step_samples(wl):
+# (workload, the workload whose tuned launch bench.py times it with)
+FULL = [(W.C3, W.C3), (W.C2, W.C2), (W.C6, W.C3), (W.C7, W.C2)]
+
+
+@pytest.mark.parametrize("wl,tuned", FULL, ids=["3d_256x256x512", "2d_1024x2048_s",
+                                                "3d_256x256x512_4classes", "2d_1024x2048_s_full_force"])
+def test_full_size_one_step_samples(wl, tuned):
     K = 3
     cfg = lbw.RunConfig.from_workload(wl)
     sol = lbw.Solver(cfg)
-    launch = autotune.lookup(wl.name)
+    launch = autotune.lookup(tuned.name)
     if launch:
         sol.set_launch(**launch)
     sol.setup_workload(wl)
@@ -119,17 +124,19 @@ def test_full_size_one_step_samples(wl):
             sl = (iv, R, R)
             gsl = (v, lat[0], lat[1])
             col_g, col_b = lat[0] * wl.nx + lat[1], R * (2 * R + 1) + R
+        cls = (slice(None),) if cfg.ncls > 1 else ()     # every size class at the node
         scale_g = np.max(np.abs(st["f"]))
         e = {
             "f": float(np.max(np.abs(nx["f"][(slice(None),) + gsl] - f1[(slice(None),) + sl]))) / scale_g,
-            "c": float(abs(nx["c"][gsl] - c1[sl])) / max(wl.c0, 1e-30),
+            "c": float(np.max(np.abs(nx["c"][cls + gsl] - c1[cls + sl]))) / max(wl.c0, 1e-30),
             "u": float(np.max(np.abs(nx["u"][(slice(None),) + gsl] - u1[(slice(None),) + sl]))),
         }
         if wl.has_s:
             e["s"] = float(abs(nx["s"][gsl] - s1[sl]))
         if v == 0:
-            inc_g = nx["deposit"][col_g] - st["deposit"][col_g]
-            e["deposit_step"] = float(abs(inc_g - dep1[col_b])) / (wl.vs * wl.c0)
+            inc_g = nx["deposit"][cls + (col_g,)] - st["deposit"][cls + (col_g,)]
+            vs_max = max((wl.vs,) + tuple(wl.vs_class))
+            e["deposit_step"] = float(np.max(np.abs(inc_g - dep1[cls + (col_b,)]))) / (vs_max * wl.c0)
         for k, val in e.items():
             worst[k] = max(worst.get(k, 0.0), val)
     print(f"\n{wl.name}: worst sampled one-step errors after {K} steps: {worst}")
