@@ -221,7 +221,11 @@ int lbw_export(lbw_handle *h, int32_t run, int32_t field, void *dst);
 
 /* Overwrite field `field` of run `run` from the canonical device buffer src
  * (same layouts as lbw_export).  Importing populations resets the streaming
- * parity and the step counter.  Asynchronous on the handle's stream. */
+ * parity and the step counter.  A state exported after an even number of
+ * steps and imported into a fresh handle continues bit for bit as the
+ * uninterrupted run; after an odd number the two continue with different
+ * kernels of the in-place pair and agree to rounding.  Asynchronous on the
+ * handle's stream. */
 int lbw_import(lbw_handle *h, int32_t run, int32_t field, const void *src);
 
 /* Point the buffer the step writes field `field` of run `run` into at the
