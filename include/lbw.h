@@ -253,6 +253,15 @@ int lbw_rebind(lbw_handle *h, int32_t run, int32_t field, void *ptr);
  * LBW_ERR_NONFINITE if any sum is NaN or Inf (the values are still written). */
 int lbw_reduce(lbw_handle *h, int32_t what, double *out_host);
 
+/* The sums of lbw_reduce for one particle size class, per run, into
+ * out_host[nbatch]: LBW_MASS_C (sum of C_cls) or LBW_DEPOSIT (the class's
+ * deposit counters), i.e. the suspended and deposited mass of that class
+ * (eq. 11-12; with one class, cls = 0 gives the lbw_reduce values).  Same
+ * deterministic reduction; synchronises the stream.  LBW_ERR_INVAL for
+ * another `what` or a class some run of the batch does not have;
+ * LBW_ERR_NONFINITE as lbw_reduce. */
+int lbw_reduce_class(lbw_handle *h, int32_t what, int32_t cls, double *out_host);
+
 /* Particle mass below a horizontal plane, per run, into out_host[nbatch]:
  * the FP64 sum of C (every size class) over the cells whose vertical index
  * v is below `plane`

@@ -824,7 +824,7 @@ namespace {
 
 // The sums of lbw_reduce, over the cells below a horizontal plane of each run
 // (plane >= 0) or over all cells (-1).
-int reduce_impl(lbw_handle *h, int32_t what, double *out_host, int plane) {
+int reduce_impl(lbw_handle *h, int32_t what, double *out_host, int plane, int cls = -1) {
     size_t need = 0;
     lbw_scratch_bytes(h->cfg.data(), h->nbatch, &need);
     const lbw_buffers &b0 = h->buf[0];
@@ -834,7 +834,7 @@ int reduce_impl(lbw_handle *h, int32_t what, double *out_host, int plane) {
     std::vector<lbw::RunDev> cur(h->nbatch);
     for (int b = 0; b < h->nbatch; ++b) cur[b] = current(h, b);
     hipError_t e = lbw::launch_reduce(h->q, h->precision, cur.data(), h->nbatch, what, h->odd,
-                                      scratch, h->stream, plane);
+                                      scratch, h->stream, plane, cls);
     if (e != hipSuccess) return hip_fail(e, "reduce launch");
     e = hipMemcpyAsync(out_host, (char *)b0.scratch + scratch_layout(h->nbatch, 0).out,
                        sizeof(double) * h->nbatch, hipMemcpyDeviceToHost, h->stream);
@@ -855,6 +855,16 @@ int lbw_reduce(lbw_handle *h, int32_t what, double *out_host) {
     if (what == LBW_MASS_FLUID && h->fluid_mode != LBW_FLUID_LBM)
         return fail(LBW_ERR_INVAL, "frozen fluid has no populations");
     return reduce_impl(h, what, out_host, -1);
+}
+
+int lbw_reduce_class(lbw_handle *h, int32_t what, int32_t cls, double *out_host) {
+    if (!h || !out_host) return fail(LBW_ERR_INVAL, "NULL argument");
+    if (what != LBW_MASS_C && what != LBW_DEPOSIT)
+        return fail(LBW_ERR_INVAL, "per-class sums exist for LBW_MASS_C and LBW_DEPOSIT (got %d)", what);
+    for (int b = 0; b < h->nbatch; ++b)
+        if (cls < 0 || cls >= h->run[b].ncls)
+            return fail(LBW_ERR_INVAL, "run %d: class %d outside [0, %d)", b, cls, h->run[b].ncls);
+    return reduce_impl(h, what, out_host, -1, cls);
 }
 
 int lbw_mass_below(lbw_handle *h, int32_t plane, double *out_host) {

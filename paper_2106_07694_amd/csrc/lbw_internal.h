@@ -124,9 +124,11 @@ hipError_t launch_adjoint(int q, int precision, const RunDev &r, bool frozen, co
                           double dep_bar, void *fbar, void *cbar, double *vs_bar, void *work,
                           const lbw_launch &l, hipStream_t st);
 // plane >= 0: MASS_C / MASS_S sum only the cells below that horizontal plane
-// (the first plane * ncol nodes of each run); -1: all nodes.
+// (the first plane * ncol nodes of each run); -1: all nodes.  cls >= 0:
+// MASS_C and DEPOSIT of that particle size class only; -1: every class.
 hipError_t launch_reduce(int q, int precision, const RunDev *runs, int nbatch, int what,
-                         bool odd, double *scratch, hipStream_t st, int plane = -1);
+                         bool odd, double *scratch, hipStream_t st, int plane = -1,
+                         int cls = -1);
 // Power spectral density of a front height (device, ncol values) along
 // lateral axis `axis` for slice `index` (-1: mean over slices); out[len/2+1].
 hipError_t launch_front_psd(const RunDev &r, int dim, const double *h, int axis, int index,

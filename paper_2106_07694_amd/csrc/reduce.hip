@@ -49,20 +49,22 @@ __device__ __forceinline__ double strided_sum(const V *__restrict__ x, int64_t n
     return (a0 + a1) + (a2 + a3);
 }
 
+// cls >= 0: MASS_C and DEPOSIT of that size class only; -1: every class.
 template <int Q, typename T>
 __global__ void __launch_bounds__(1024) k_partial(RunDev r, int what, bool odd, bool shifted,
-                                                  int plane, double *__restrict__ part) {
+                                                  int plane, int cls, double *__restrict__ part) {
     double acc = 0.0;
-    // the deposit counters of every size class are contiguous
-    int64_t n = (what == LBW_DEPOSIT) ? r.ncol * r.ncls : r.N;
+    const int c0 = cls < 0 ? 0 : cls, c1 = cls < 0 ? r.ncls : cls + 1;
+    // the deposit counters of the size classes are contiguous
+    int64_t n = (what == LBW_DEPOSIT) ? r.ncol * (c1 - c0) : r.N;
     if (plane >= 0 && (what == LBW_MASS_C || what == LBW_MASS_S) && (int64_t)plane * r.ncol < n)
         n = (int64_t)plane * r.ncol;   // planes are the slowest axis
     if (what == LBW_MASS_C) {
-        for (int i = 0; i < r.ncls; ++i) acc += strided_sum((const T *)r.c + (int64_t)i * r.N, n);
+        for (int i = c0; i < c1; ++i) acc += strided_sum((const T *)r.c + (int64_t)i * r.N, n);
     } else if (what == LBW_MASS_S) {
         acc = strided_sum((const T *)r.s, n);
     } else if (what == LBW_DEPOSIT) {
-        acc = strided_sum(r.dep, n);
+        acc = strided_sum(r.dep + (int64_t)c0 * r.ncol, n);
     } else {
         using L = Lattice<Q>;
         const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -90,9 +92,9 @@ __global__ void __launch_bounds__(256) k_final(const double *__restrict__ part, 
 
 template <int Q, typename T>
 hipError_t reduce_t(const RunDev *runs, int nbatch, int what, bool odd, bool shifted,
-                    double *scratch, hipStream_t st, int plane) {
+                    double *scratch, hipStream_t st, int plane, int cls) {
     for (int b = 0; b < nbatch; ++b)
-        k_partial<Q, T><<<kReduceBlocks, 1024, 0, st>>>(runs[b], what, odd, shifted, plane,
+        k_partial<Q, T><<<kReduceBlocks, 1024, 0, st>>>(runs[b], what, odd, shifted, plane, cls,
                                                         scratch + (int64_t)b * kReduceBlocks);
     k_final<<<nbatch, 256, 0, st>>>(scratch, kReduceBlocks, scratch + (int64_t)nbatch * kReduceBlocks);
     return hipGetLastError();
@@ -174,13 +176,13 @@ __global__ void __launch_bounds__(64 * W) k_front_height(const T *__restrict__ c
 }  // namespace
 
 hipError_t launch_reduce(int q, int precision, const RunDev *runs, int nbatch, int what, bool odd,
-                         double *scratch, hipStream_t st, int plane) {
+                         double *scratch, hipStream_t st, int plane, int cls) {
     const bool sh = precision != LBW_FP64;
     if (precision == LBW_FP32_SHIFTED)
-        return q == 9 ? reduce_t<9, float>(runs, nbatch, what, odd, sh, scratch, st, plane)
-                      : reduce_t<19, float>(runs, nbatch, what, odd, sh, scratch, st, plane);
-    return q == 9 ? reduce_t<9, double>(runs, nbatch, what, odd, sh, scratch, st, plane)
-                  : reduce_t<19, double>(runs, nbatch, what, odd, sh, scratch, st, plane);
+        return q == 9 ? reduce_t<9, float>(runs, nbatch, what, odd, sh, scratch, st, plane, cls)
+                      : reduce_t<19, float>(runs, nbatch, what, odd, sh, scratch, st, plane, cls);
+    return q == 9 ? reduce_t<9, double>(runs, nbatch, what, odd, sh, scratch, st, plane, cls)
+                  : reduce_t<19, double>(runs, nbatch, what, odd, sh, scratch, st, plane, cls);
 }
 
 template <typename T, bool MULTI>

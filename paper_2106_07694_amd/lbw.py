@@ -31,7 +31,7 @@ EXPORTED = ("lbw_version", "lbw_last_error", "lbw_scratch_bytes", "lbw_create", 
             "lbw_set_launch", "lbw_get_launch", "lbw_init_equilibrium", "lbw_step",
             "lbw_steps_done", "lbw_export", "lbw_import", "lbw_rebind", "lbw_reduce", "lbw_timing_begin",
             "lbw_timing_end", "lbw_adjoint_work_bytes", "lbw_adjoint_step", "lbw_mass_below",
-            "lbw_front_height", "lbw_front_psd")
+            "lbw_front_height", "lbw_front_psd", "lbw_reduce_class")
 
 
 class LbwError(RuntimeError):
@@ -105,6 +105,7 @@ def load() -> ctypes.CDLL:
     lib.lbw_rebind.argtypes = [P, I32, I32, P]
     lib.lbw_reduce.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double)]
     lib.lbw_mass_below.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double)]
+    lib.lbw_reduce_class.argtypes = [P, I32, I32, ctypes.POINTER(ctypes.c_double)]
     lib.lbw_front_height.argtypes = [P, I32, ctypes.c_double, P]
     lib.lbw_front_psd.argtypes = [P, I32, P, I32, I32, P]
     lib.lbw_adjoint_work_bytes.argtypes = [P, I32, ctypes.POINTER(ctypes.c_size_t)]
@@ -373,6 +374,12 @@ class Solver:
     def reduce(self, what) -> np.ndarray:
         out = (ctypes.c_double * self.nbatch)()
         check(self._lib.lbw_reduce(self._h, int(what), out))
+        return np.array(out[:], dtype=np.float64)
+
+    def reduce_class(self, what, cls: int) -> np.ndarray:
+        """MASS_C or DEPOSIT of one particle size class, per run (FP64)."""
+        out = (ctypes.c_double * self.nbatch)()
+        check(self._lib.lbw_reduce_class(self._h, int(what), int(cls), out))
         return np.array(out[:], dtype=np.float64)
 
     def mass_below(self, plane: int) -> np.ndarray:

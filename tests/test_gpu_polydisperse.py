@@ -199,3 +199,27 @@ def test_adjoint_rejects_several_classes():
         sol.adjoint_step(f, z, f, z, 1.0, f.clone(), z.clone(), None, work)
     assert e.value.code == lbw.ERR_UNSUPPORTED
     sol.close()
+
+
+def test_per_class_sums():
+    """Suspended and deposited mass of each class equal the oracle's sums of
+    that class's fields; they add up to the totals of lbw_reduce."""
+    cfg = _cfg(3, 19, nx=14, ny=10, nz=20)
+    c0, _ = _fields(cfg, 22)
+    sol = lbw.Solver(cfg)
+    sol.set_field("c", c0)
+    sol.init_equilibrium()
+    sol.step(9)
+    o = run_oracle(cfg, c0, None, None, None, 9)
+    m = [sol.reduce_class(lbw.MASS_C, i)[0] for i in range(3)]
+    d = [sol.reduce_class(lbw.DEPOSIT, i)[0] for i in range(3)]
+    for i in range(3):
+        assert abs(m[i] - o["c"][i].sum()) <= TOL64 * o["c"][i].sum(), i
+        assert abs(d[i] - o["deposit"][i].sum()) <= TOL64 * o["deposit"][i].sum(), i
+    assert d[0] > d[1] > d[2]                 # faster classes deposit more
+    assert abs(sum(m) - sol.reduce(lbw.MASS_C)[0]) <= 1e-13 * sum(m)
+    assert abs(sum(d) - sol.reduce(lbw.DEPOSIT)[0]) <= 1e-13 * sum(d)
+    for bad in ((lbw.MASS_C, 3), (lbw.MASS_C, -1), (lbw.MASS_FLUID, 0)):
+        with pytest.raises(lbw.LbwError):
+            sol.reduce_class(*bad)
+    sol.close()
