@@ -416,7 +416,8 @@ __host__ __device__ inline TileGeom make_geom(const RunDev &r, int chunk, int TX
 template <typename T, int D, int SCHEME, int STAGE, int TX, int TY, bool VSS>
 __global__ void __launch_bounds__(TX *TY) k_stage_batched(const RunDev *__restrict__ runs,
                                                           const int *__restrict__ tile_start,
-                                                          int nbatch, int chunk, int sflip) {
+                                                          int nbatch, int chunk, int sflip,
+                                                          int form) {
     const int total = tile_start[nbatch];
     const int G = gridDim.x;
     // with 8 blocks or more, block i runs on XCD i % 8 and that XCD walks its
@@ -434,6 +435,7 @@ __global__ void __launch_bounds__(TX *TY) k_stage_batched(const RunDev *__restri
         int b = 0;
         while (tile_start[b + 1] <= w) ++b;                // runs are few; linear scan
         RunDev r = runs[b];
+        if (form >= 0 && (r.vs_s != 0.0) != (form == 1)) continue;   // the other form's entry
         if (sflip) { void *t = r.s; r.s = r.s2; r.s2 = t; }
         const TileGeom g = make_geom<D>(r, chunk, TX, TY);
         const int t = w - tile_start[b];
@@ -530,21 +532,24 @@ hipError_t stage_slab_d(const RunDev &r, const lbw_launch &l, int stage, int v_l
 
 template <typename T, int D, int SCHEME, int TX, int TY, bool VSS>
 hipError_t stages_batched(const BatchArgs &a, hipStream_t st) {
-    k_stage_batched<T, D, SCHEME, 1, TX, TY, VSS><<<a.grid, TX * TY, 0, st>>>(a.runs, a.tile_start, a.nbatch, a.chunk, a.sflip);
-    k_stage_batched<T, D, SCHEME, 2, TX, TY, VSS><<<a.grid, TX * TY, 0, st>>>(a.runs, a.tile_start, a.nbatch, a.chunk, a.sflip);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (a.host_runs[0].has_s) {
-        for (int b = 0; b < a.nbatch; ++b) {
-            RunDev r = a.host_runs[b];
-            if (!r.has_s) continue;       // size classes after the first of a run
-            if (a.sflip) { void *t = r.s; r.s = r.s2; r.s2 = t; }
-            e = launch_s_update(D, sizeof(T) == 4 ? LBW_FP32_SHIFTED : LBW_FP64, r, st);
-            if (e != hipSuccess) return e;
-        }
-    }
-    k_stage_batched<T, D, SCHEME, 3, TX, TY, VSS><<<a.grid, TX * TY, 0, st>>>(a.runs, a.tile_start, a.nbatch, a.chunk, a.sflip);
-    return hipGetLastError();
+    auto stage = [&](int k) {
+        if (k == 1)
+            k_stage_batched<T, D, SCHEME, 1, TX, TY, VSS><<<a.grid, TX * TY, 0, st>>>(
+                a.runs, a.tile_start, a.nbatch, a.chunk, a.sflip, a.form);
+        else if (k == 2)
+            k_stage_batched<T, D, SCHEME, 2, TX, TY, VSS><<<a.grid, TX * TY, 0, st>>>(
+                a.runs, a.tile_start, a.nbatch, a.chunk, a.sflip, a.form);
+        else
+            k_stage_batched<T, D, SCHEME, 3, TX, TY, VSS><<<a.grid, TX * TY, 0, st>>>(
+                a.runs, a.tile_start, a.nbatch, a.chunk, a.sflip, a.form);
+        return hipGetLastError();
+    };
+    if (a.stage != 0) return stage(a.stage);
+    hipError_t e = stage(1);
+    if (e == hipSuccess) e = stage(2);
+    if (e == hipSuccess) e = batched_s_updates(D, sizeof(T) == 4 ? LBW_FP32_SHIFTED : LBW_FP64, a, st);
+    if (e == hipSuccess) e = stage(3);
+    return e;
 }
 
 template <typename T, int D, int SCHEME, bool VSS>

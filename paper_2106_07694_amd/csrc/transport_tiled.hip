@@ -40,15 +40,38 @@ hipError_t launch_stage_slab(int dim, int precision, const RunDev &r, const lbw_
                     : stage_slab_d<double, 3>(r, l, stage, v_lo, v_hi, st);
 }
 
+hipError_t batched_s_updates(int dim, int precision, const BatchArgs &b, hipStream_t st) {
+    for (int i = 0; i < b.nbatch; ++i) {
+        RunDev r = b.host_runs[i];
+        if (!r.has_s) continue;               // size classes after the first of a run
+        if (b.sflip) { void *t = r.s; r.s = r.s2; r.s2 = t; }
+        const hipError_t e = launch_s_update(dim, precision, r, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_transport_batched(int dim, int precision, const BatchArgs &b, const lbw_launch &l,
                                     hipStream_t st) {
     const RunDev &r = b.host_runs[0];
-    // one settling form per launch: if any run's settling speed depends on
-    // S, every entry takes that form (vs_s = 0 then gives the constant speed
-    // exactly, and the runs of a batch all carry S)
-    for (int i = 0; i < b.nbatch; ++i)
-        if (b.host_runs[i].vs_s != 0.0) return launch_transport_tiled_vs(dim, precision, r, l, st, &b);
-    return tiled_any<false>(dim, precision, r, l, st, &b);
+    bool any_var = false, any_const = false;
+    for (int i = 0; i < b.nbatch; ++i) (b.host_runs[i].vs_s != 0.0 ? any_var : any_const) = true;
+    if (!any_var) return tiled_any<false>(dim, precision, r, l, st, &b);
+    if (!any_const) return launch_transport_tiled_vs(dim, precision, r, l, st, &b);
+    // both settling forms: each stage runs once per form, each kernel over
+    // its own entries, so every run takes the kernels it takes alone
+    BatchArgs x = b;
+    for (int k = 1; k <= 3; ++k) {
+        hipError_t e = hipSuccess;
+        if (k == 3) e = batched_s_updates(dim, precision, b, st);
+        x.stage = k;
+        x.form = 0;
+        if (e == hipSuccess) e = tiled_any<false>(dim, precision, r, l, st, &x);
+        x.form = 1;
+        if (e == hipSuccess) e = launch_transport_tiled_vs(dim, precision, r, l, st, &x);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace lbw

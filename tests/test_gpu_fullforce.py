@@ -143,8 +143,8 @@ def test_uniform_s_is_the_scaled_constant_speed_bitwise(precision):
 @pytest.mark.parametrize("graph", [0, 1])
 def test_batch_mixing_settling_forms(graph):
     """A run with a variable settling speed and one without share a batch:
-    the batch takes the variable form for every entry, and each run equals
-    itself alone bit for bit."""
+    each settling form runs over its own entries, so each run takes the
+    kernels it takes alone and equals itself alone bit for bit."""
     import torch
 
     cfgs = [_cfg(9, nx=24, ny=30, precision="fp32_shifted"),
