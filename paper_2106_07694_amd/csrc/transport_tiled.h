@@ -158,7 +158,7 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
     const int xw = active ? gxl : gxl % g.nx;       // wrapped column for loads
     const int yw = (D == 3) ? (active ? gyl : gyl % g.ny) : 0;
     const int col = xw + g.nx * yw;                 // < nx * ny
-    const uint32_t colb = (uint32_t)col * (uint32_t)sizeof(T);
+    uint32_t colb = (uint32_t)col * (uint32_t)sizeof(T);
     const int v0 = bz * g.chunk;
     const int v1 = min(v0 + g.chunk, g.nv);
 
@@ -183,10 +183,9 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
     // vertical index with the wall/periodic rule; sets flip for mirrored nodes
     auto vidx = [&](int v, bool &flip) -> int {
         flip = false;
-        if (!walls) {
-            v %= g.nv;
-            return v < 0 ? v + g.nv : v;
-        }
+        // the march reaches at most three planes below and four above the
+        // axis (v in [-3, nv + 3]) and nv >= 6, so one wrap suffices
+        if (!walls) return v < 0 ? v + g.nv : (v >= g.nv ? v - g.nv : v);
         if (v < 0) { flip = true; return -1 - v; }
         if (v >= g.nv) { flip = true; return 2 * g.nv - 1 - v; }
         return v;
@@ -303,85 +302,107 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
     };
     prefetch(v0);
 
-    for (int v = v0; v < v1; ++v) {
-        // publish plane v
+    // The march is unrolled six planes at a time with the window slots
+    // rotating: at phase ph, window position m lives in slot (ph + m) % 6,
+    // and the node entering at v + 4 takes the slot position 0 leaves, so no
+    // register moves shift the window from plane to plane.
+    for (int vb = v0; vb < v1; vb += 6) {
 #pragma unroll
-        for (int s = 0; s < SA; ++s) if (ldsA[s] >= 0) sA[ldsA[s]] = pA[s];
+        for (int ph = 0; ph < 6; ++ph) {
+            const int v = vb + ph;
+            if (v >= v1) break;
+            // window position m (node v - 2 + m) of this phase
+            auto A = [&](int m) -> T & { return aw[(ph + m) % 6]; };
+            auto W = [&](int m) -> T & { return ww[(ph + m) % 6]; };
+            // the lane offsets pass through an empty asm every plane: the
+            // compiler can then no longer fold them into per-lane 64-bit
+            // pointers hoisted out of the march (each plane's offset would be
+            // added to those in vector instructions), and the loads keep the
+            // scalar-base plus 32-bit-offset form
+            asm volatile("" : "+v"(colb));
 #pragma unroll
-        for (int s = 0; s < SUX; ++s) if (ldsX[s] >= 0) sUx[ldsX[s]] = pX[s];
+            for (int s = 0; s < SA; ++s) asm volatile("" : "+v"(offA[s]));
 #pragma unroll
-        for (int s = 0; s < SUY; ++s) if (ldsY[s] >= 0) sUy[ldsY[s]] = pY[s];
-        __syncthreads();
-        // loads, in the order they are consumed (the load counter drains in
-        // issue order, so waiting for one waits for all issued before it):
-        // this cell's C and the vertical pair at v+4, both used at the end of
-        // this plane, then the next lateral plane, used only after the next
-        // barrier and so in flight across this plane's face computation
-        // (past the chunk it is still a valid plane: the vertical rule maps
-        // it inside)
-        T cown = (T)0;
-        if (STAGE != 1) cown = at<T>(plane(r.c, v), colb);
-        T anext, wnext;
-        load_av(v + 4, anext, wnext);
-        prefetch(v + 1);
+            for (int s = 0; s < SUX; ++s) asm volatile("" : "+v"(offX[s]));
+#pragma unroll
+            for (int s = 0; s < SUY; ++s) asm volatile("" : "+v"(offY[s]));
+            // publish plane v
+#pragma unroll
+            for (int s = 0; s < SA; ++s) if (ldsA[s] >= 0) sA[ldsA[s]] = pA[s];
+#pragma unroll
+            for (int s = 0; s < SUX; ++s) if (ldsX[s] >= 0) sUx[ldsX[s]] = pX[s];
+#pragma unroll
+            for (int s = 0; s < SUY; ++s) if (ldsY[s] >= 0) sUy[ldsY[s]] = pY[s];
+            __syncthreads();
+            // loads, in the order they are consumed (the load counter drains in
+            // issue order, so waiting for one waits for all issued before it):
+            // this cell's C and the vertical pair at v+4, both used at the end of
+            // this plane, then the next lateral plane, used only after the next
+            // barrier and so in flight across this plane's face computation
+            // (past the chunk it is still a valid plane: the vertical rule maps
+            // it inside)
+            T cown = (T)0;
+            if (STAGE != 1) cown = at<T>(plane(r.c, v), colb);
+            T anext, wnext;
+            load_av(v + 4, anext, wnext);
+            prefetch(v + 1);
 
-        // lateral faces: each thread the x face on the left of its cell and
-        // (3D) the y face below it
-        {
-            const T *ar = sA + ((D == 3) ? (ty + 3) : 0) * AX + tx;   // nodes tx-3 .. tx+2
-            const T *ur = sUx + ty * AX + tx;
-            sFx[ty * (TX + 1) + tx] = face6<T, SCHEME>(ar[0], ar[1], ar[2], ar[3], ar[4], ar[5], ur[0],
-                                                        ur[1], ur[2], ur[3], ur[4], ur[5], kap, eps);
-        }
-        if constexpr (D == 3) {
-            const T *ac = sA + ty * AX + tx + 3;      // rows ty-3+3 .. ty+2+3 of column tx
-            const T *uc = sUy + ty * TX + tx;
-            sFy[ty * TX + tx] = face6<T, SCHEME>(ac[0], ac[AX], ac[2 * AX], ac[3 * AX], ac[4 * AX],
-                                                 ac[5 * AX], uc[0], uc[TX], uc[2 * TX], uc[3 * TX],
-                                                 uc[4 * TX], uc[5 * TX], kap, eps);
-        }
-        for (int e = tid; e < NEX; e += NT) {
-            const bool xf = e < TY;                   // x face of column TX, row e
-            const int fy = xf ? e : TY, fx = xf ? TX : e - TY;
-            const T *ar = xf ? sA + ((D == 3) ? (fy + 3) : 0) * AX + fx : sA + fx + 3;
-            const T *ur = xf ? sUx + fy * AX + fx : sUy + fx;
-            const int sa = xf ? 1 : AX, su = xf ? 1 : TX;
+            // lateral faces: each thread the x face on the left of its cell and
+            // (3D) the y face below it
+            {
+                const T *ar = sA + ((D == 3) ? (ty + 3) : 0) * AX + tx;   // nodes tx-3 .. tx+2
+                const T *ur = sUx + ty * AX + tx;
+                sFx[ty * (TX + 1) + tx] = face6<T, SCHEME>(ar[0], ar[1], ar[2], ar[3], ar[4], ar[5], ur[0],
+                                                            ur[1], ur[2], ur[3], ur[4], ur[5], kap, eps);
+            }
             if constexpr (D == 3) {
-                if (!xf) { ar += fy * AX; ur += fy * TX; }
+                const T *ac = sA + ty * AX + tx + 3;      // rows ty-3+3 .. ty+2+3 of column tx
+                const T *uc = sUy + ty * TX + tx;
+                sFy[ty * TX + tx] = face6<T, SCHEME>(ac[0], ac[AX], ac[2 * AX], ac[3 * AX], ac[4 * AX],
+                                                     ac[5 * AX], uc[0], uc[TX], uc[2 * TX], uc[3 * TX],
+                                                     uc[4 * TX], uc[5 * TX], kap, eps);
             }
-            const T f = face6<T, SCHEME>(ar[0], ar[sa], ar[2 * sa], ar[3 * sa], ar[4 * sa], ar[5 * sa],
-                                         ur[0], ur[su], ur[2 * su], ur[3 * su], ur[4 * su], ur[5 * su],
-                                         kap, eps);
-            if (xf) sFx[fy * (TX + 1) + fx] = f;
-            else if constexpr (D == 3) sFy[fy * TX + fx] = f;
-        }
-        // vertical face above this cell
-        T fabove;
-        if (walls && v == g.nv - 1)
-            fabove = (T)0;
-        else
-            fabove = face6<T, SCHEME>(aw[0], aw[1], aw[2], aw[3], aw[4], aw[5], ww[0], ww[1], ww[2],
-                                      ww[3], ww[4], ww[5], kap, eps);
-        __syncthreads();
-        T L = -(fabove - fbelow);
-        L -= sFx[ty * (TX + 1) + tx + 1] - sFx[ty * (TX + 1) + tx];
-        if constexpr (D == 3) L -= sFy[(ty + 1) * TX + tx] - sFy[ty * TX + tx];
-        const T a = aw[2];
-        if (active) {
-            if constexpr (STAGE == 1) {
-                *(T *)((char *)wplane(r.c1, v) + colb) = a + L;
-            } else if constexpr (STAGE == 2) {
-                *(T *)((char *)wplane(r.c2, v) + colb) = (T)0.75 * cown + (T)0.25 * a + (T)0.25 * L;
-            } else {
-                *(T *)((char *)wplane(r.c, v) + colb) = (T)(1.0 / 3.0) * cown + (T)(2.0 / 3.0) * a + (T)(2.0 / 3.0) * L;
+            for (int e = tid; e < NEX; e += NT) {
+                const bool xf = e < TY;                   // x face of column TX, row e
+                const int fy = xf ? e : TY, fx = xf ? TX : e - TY;
+                const T *ar = xf ? sA + ((D == 3) ? (fy + 3) : 0) * AX + fx : sA + fx + 3;
+                const T *ur = xf ? sUx + fy * AX + fx : sUy + fx;
+                const int sa = xf ? 1 : AX, su = xf ? 1 : TX;
+                if constexpr (D == 3) {
+                    if (!xf) { ar += fy * AX; ur += fy * TX; }
+                }
+                const T f = face6<T, SCHEME>(ar[0], ar[sa], ar[2 * sa], ar[3 * sa], ar[4 * sa], ar[5 * sa],
+                                             ur[0], ur[su], ur[2 * su], ur[3 * su], ur[4 * su], ur[5 * su],
+                                             kap, eps);
+                if (xf) sFx[fy * (TX + 1) + fx] = f;
+                else if constexpr (D == 3) sFy[fy * TX + fx] = f;
             }
+            // vertical face above this cell
+            T fabove;
+            if (walls && v == g.nv - 1)
+                fabove = (T)0;
+            else
+                fabove = face6<T, SCHEME>(A(0), A(1), A(2), A(3), A(4), A(5), W(0), W(1), W(2), W(3),
+                                          W(4), W(5), kap, eps);
+            __syncthreads();
+            T L = -(fabove - fbelow);
+            L -= sFx[ty * (TX + 1) + tx + 1] - sFx[ty * (TX + 1) + tx];
+            if constexpr (D == 3) L -= sFy[(ty + 1) * TX + tx] - sFy[ty * TX + tx];
+            const T a = A(2);
+            if (active) {
+                if constexpr (STAGE == 1) {
+                    *(T *)((char *)wplane(r.c1, v) + colb) = a + L;
+                } else if constexpr (STAGE == 2) {
+                    *(T *)((char *)wplane(r.c2, v) + colb) = (T)0.75 * cown + (T)0.25 * a + (T)0.25 * L;
+                } else {
+                    *(T *)((char *)wplane(r.c, v) + colb) = (T)(1.0 / 3.0) * cown + (T)(2.0 / 3.0) * a + (T)(2.0 / 3.0) * L;
+                }
+            }
+            fbelow = fabove;
+            A(0) = anext;                     // position 0 leaves, node v + 4 enters
+            W(0) = wnext;
+            __syncthreads();
         }
-        fbelow = fabove;
-#pragma unroll
-        for (int m = 0; m < 5; ++m) { aw[m] = aw[m + 1]; ww[m] = ww[m + 1]; }
-        aw[5] = anext;
-        ww[5] = wnext;
-        __syncthreads();
     }
 }
 

@@ -122,9 +122,13 @@ def test_settling_gradient_closed_form(lattice, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_shifted"])
-def test_uniform_s_is_the_scaled_constant_speed_bitwise(precision):
+def test_uniform_s_is_the_scaled_constant_speed(precision):
     """S uniform (and kept so by a uniform lateral flow): Vs (1 - vs_s S) with
-    exactly representable factors equals the constant speed it scales to."""
+    exactly representable factors equals the constant speed it scales to.
+    The two speeds run in different kernels, which the compiler may contract
+    into fused multiply-adds differently, so C agrees to rounding (the
+    oracle, built without contraction, gives it bit for bit); S and the
+    deposit (FP64 from the exact speed) agree bit for bit."""
     vs, vs_s, s0 = 2.0 ** -8, 0.5, 0.5
     kw = dict(lattice=19, nx=10, ny=8, nz=12, precision=precision, fluid_mode=lbw.FLUID_FROZEN,
               kappa_c=1e-3, has_s=True, kappa_s=1e-3)
@@ -136,7 +140,11 @@ def test_uniform_s_is_the_scaled_constant_speed_bitwise(precision):
     u[0] = 0.03
     g1 = run_gpu(var, c0, s, u, None, 10)
     g2 = run_gpu(const, c0, s, u, None, 10)
-    for k in ("c", "deposit", "s"):
+    dc = float(np.max(np.abs(g1["c"] - g2["c"]))) / float(np.max(np.abs(g2["c"])))
+    print(f"\n{precision}: C differs by {dc:.2e} of max C")
+    eps = np.finfo(np.float64 if precision == "fp64" else np.float32).eps
+    assert dc <= 8 * eps, dc
+    for k in ("deposit", "s"):
         assert np.array_equal(g1[k], g2[k]), k
 
 
