@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(256) k_rk_stage(RunDev r) {
     if constexpr (STAGE == 1) {
         ((T *)r.c1)[k] = a + L;
     } else if constexpr (STAGE == 2) {
-        ((T *)r.c2)[k] = (T)0.75 * C[k] + (T)0.25 * a + (T)0.25 * L;
+        ((T *)r.c2)[k] = rk3_stage2<T>(C[k], a, L);
     } else {
         const T c0 = C[k];
         const int v = (D == 2) ? y : z;
@@ -113,7 +113,7 @@ __global__ void __launch_bounds__(256) k_rk_stage(RunDev r) {
             const int64_t col = (D == 2) ? x : (int64_t)x + (int64_t)r.nx * y;
             r.dep[col] += o0 / 6.0 + o1 / 6.0 + 2.0 / 3.0 * o2;
         }
-        C[k] = c0 / (T)3 + (T)(2.0 / 3.0) * a + (T)(2.0 / 3.0) * L;
+        C[k] = rk3_stage3<T>(c0, a, L);
     }
 }
 

@@ -71,4 +71,21 @@ __device__ __forceinline__ T face_flux(const T *a, const T *w, T kappa, T eps) {
     return hh - kappa * (a[3] - a[2]);
 }
 
+// Combinations of the second and third RK3 stages (S22, S23), given the
+// base value c, the stage input a and its right-hand side L:
+//   3/4 c + 1/4 a + 1/4 L  and  1/3 c + 2/3 a + 2/3 L,
+// written as c plus a small increment.  The stage input differs from c by
+// O(L), so a - c is exact when the two are within a factor of two, and the
+// stored value takes one rounding, at the final add; summing the weighted
+// terms directly rounds each product of an O(1) value and each partial sum,
+// which in single precision is the leading error of the transported field.
+template <typename T>
+__device__ __forceinline__ T rk3_stage2(T c, T a, T L) {
+    return c + (T)0.25 * ((a - c) + L);
+}
+template <typename T>
+__device__ __forceinline__ T rk3_stage3(T c, T a, T L) {
+    return c + (T)(2.0 / 3.0) * ((a - c) + L);
+}
+
 }  // namespace lbw

@@ -393,9 +393,9 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
                 if constexpr (STAGE == 1) {
                     *(T *)((char *)wplane(r.c1, v) + colb) = a + L;
                 } else if constexpr (STAGE == 2) {
-                    *(T *)((char *)wplane(r.c2, v) + colb) = (T)0.75 * cown + (T)0.25 * a + (T)0.25 * L;
+                    *(T *)((char *)wplane(r.c2, v) + colb) = rk3_stage2<T>(cown, a, L);
                 } else {
-                    *(T *)((char *)wplane(r.c, v) + colb) = (T)(1.0 / 3.0) * cown + (T)(2.0 / 3.0) * a + (T)(2.0 / 3.0) * L;
+                    *(T *)((char *)wplane(r.c, v) + colb) = rk3_stage3<T>(cown, a, L);
                 }
             }
             fbelow = fabove;

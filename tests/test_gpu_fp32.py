@@ -6,10 +6,11 @@ stored, relative to max |g|) -- FP32 storage and arithmetic.  The deposit is
 accumulated in FP64 from FP32 concentrations, so its error follows the
 concentration's: it is measured relative to n Vs max|C| (what n steps of a
 full bottom layer would deposit) and bounded by 1e-6.  Measured on MI355X
-(128x256 with S, C0 in {0.5, 1, 2}): C 8e-6 .. 1.05e-5, u <= 4e-6, S <= 4.4e-6,
-deposit <= 2e-9.  C is the most sensitive: with eps = 1e-6 the WENO weights
-respond to smoothness indicators of the 1e-3 seeded noise, which single
-precision differences of O(1) values resolve only to about ten percent.
+(128x256 with S, C0 in {0.5, 1, 2}): C 4.5e-6 .. 6.5e-6, u <= 3.4e-6,
+S <= 4.4e-6, deposit <= 8e-10; 3D 32x32x64: C 2.6e-6.  C is the most
+sensitive: with eps = 1e-6 the WENO weights respond to smoothness
+indicators of the 1e-3 seeded noise, which single precision differences of
+O(1) values resolve only to about ten percent.
 """
 import numpy as np
 import pytest
