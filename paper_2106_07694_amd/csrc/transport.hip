@@ -117,16 +117,49 @@ __global__ void __launch_bounds__(256) k_rk_stage(RunDev r) {
     }
 }
 
+// S update (S5-S6 in conservative form, R13): forward Euler of the
+// first-order upwind flux of h = u S plus central diffusion, closed walls,
+// nothing settles.  One thread per node of a plane, the planes of [v_lo,
+// v_hi) across grid.y (strided when there are more than grid.y of them);
+// coordinates are 32-bit within a plane (a plane holds fewer than 2^29
+// cells, checked at creation) and only the neighbours the first-order flux
+// reads are loaded.
 template <typename T, int D>
-__global__ void __launch_bounds__(256) k_s_euler(RunDev r, int64_t k0, int64_t k1) {
-    const int64_t k = k0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= k1) return;
-    int x, y, z;
-    node_coords<D>(r, k, x, y, z);
+__global__ void __launch_bounds__(256) k_s_update(RunDev r, int v_lo, int v_hi) {
+    const int nx = r.nx, ny = (D == 3) ? r.ny : 1, nv = (D == 3) ? r.nz : r.ny;
+    const int P = nx * ny;
+    const int p = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (p >= P) return;
+    const int x = p % nx, y = (D == 3) ? p / nx : 0;
     const T *__restrict__ s = (const T *)r.s;
-    const T L = spatial_op<T, D, LBW_UPWIND1, false>(r, s, (const T *)r.u, k, x, y, z, (T)0,
-                                                     (T)r.kappa_s, (T)r.eps);
-    ((T *)r.s2)[k] = s[k] + L;
+    const T *__restrict__ ux = (const T *)r.u;
+    const T *__restrict__ uy = ux + r.N;
+    const T *__restrict__ uv = ux + (int64_t)(D - 1) * r.N;
+    const T kap = (T)r.kappa_s;
+    // face between nodes j (a2, w2) and j + 1 (a3, w3)
+    auto face = [&](T a2, T a3, T w2, T w3) -> T {
+        const T hh = ((T)0.5 * (w2 + w3) >= (T)0) ? w2 * a2 : w3 * a3;
+        return hh - kap * (a3 - a2);
+    };
+    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+    for (int v = v_lo + (int)blockIdx.y; v < v_hi; v += (int)gridDim.y) {
+        const int64_t k = (int64_t)v * P + p;
+        const T s0 = s[k];
+        const int64_t kxm = k + (xm - x), kxp = k + (xp - x);
+        T L = -(face(s0, s[kxp], ux[k], ux[kxp]) - face(s[kxm], s0, ux[kxm], ux[k]));
+        if constexpr (D == 3) {
+            const int64_t kym = k + (int64_t)(ym - y) * nx, kyp = k + (int64_t)(yp - y) * nx;
+            L -= face(s0, s[kyp], uy[k], uy[kyp]) - face(s[kym], s0, uy[kym], uy[k]);
+        }
+        const bool top = !r.vper && v == nv - 1, bottom = !r.vper && v == 0;
+        const int vm = v == 0 ? nv - 1 : v - 1, vp = v == nv - 1 ? 0 : v + 1;
+        const int64_t kvm = k + (int64_t)(vm - v) * P, kvp = k + (int64_t)(vp - v) * P;
+        const T Fp = top ? (T)0 : face(s0, s[kvp], uv[k], uv[kvp]);
+        const T Fm = bottom ? (T)0 : face(s[kvm], s0, uv[kvm], uv[k]);
+        L -= Fp - Fm;
+        ((T *)r.s2)[k] = s0 + L;
+    }
 }
 
 template <typename T, int D, int SCHEME>
@@ -135,7 +168,10 @@ hipError_t transport_t(const RunDev &r, hipStream_t st) {
     const dim3 grid((unsigned)((r.N + block - 1) / block));
     k_rk_stage<T, D, SCHEME, 1><<<grid, block, 0, st>>>(r);
     k_rk_stage<T, D, SCHEME, 2><<<grid, block, 0, st>>>(r);
-    if (r.has_s) k_s_euler<T, D><<<grid, block, 0, st>>>(r, 0, r.N);
+    if (r.has_s) {
+        const hipError_t e = launch_s_update(D, sizeof(T) == 4 ? LBW_FP32_SHIFTED : LBW_FP64, r, st);
+        if (e != hipSuccess) return e;
+    }
     k_rk_stage<T, D, SCHEME, 3><<<grid, block, 0, st>>>(r);
     return hipGetLastError();
 }
@@ -156,14 +192,16 @@ hipError_t launch_s_update(int dim, int precision, const RunDev &r, hipStream_t 
                            int64_t k1) {
     if (k1 < 0) k1 = r.N;
     if (k0 >= k1) return hipSuccess;
-    const int block = 256;
-    const dim3 grid((unsigned)((k1 - k0 + block - 1) / block));
+    const int64_t P = (int64_t)r.nx * (dim == 3 ? r.ny : 1);
+    if (k0 % P || k1 % P) return hipErrorInvalidValue;      // whole planes only
+    const int v_lo = (int)(k0 / P), v_hi = (int)(k1 / P);
+    const dim3 grid((unsigned)((P + 255) / 256), (unsigned)std::min(v_hi - v_lo, 65535));
     if (precision == LBW_FP32_SHIFTED) {
-        if (dim == 2) k_s_euler<float, 2><<<grid, block, 0, st>>>(r, k0, k1);
-        else k_s_euler<float, 3><<<grid, block, 0, st>>>(r, k0, k1);
+        if (dim == 2) k_s_update<float, 2><<<grid, 256, 0, st>>>(r, v_lo, v_hi);
+        else k_s_update<float, 3><<<grid, 256, 0, st>>>(r, v_lo, v_hi);
     } else {
-        if (dim == 2) k_s_euler<double, 2><<<grid, block, 0, st>>>(r, k0, k1);
-        else k_s_euler<double, 3><<<grid, block, 0, st>>>(r, k0, k1);
+        if (dim == 2) k_s_update<double, 2><<<grid, 256, 0, st>>>(r, v_lo, v_hi);
+        else k_s_update<double, 3><<<grid, 256, 0, st>>>(r, v_lo, v_hi);
     }
     return hipGetLastError();
 }
