@@ -22,7 +22,7 @@ LBM_BLOCKS = (128, 256, 512, 1024)
 # transport tiles (columns, rows): 256 threads, and 512-thread tiles
 TILES = {2: ((64, 1), (128, 1), (256, 1), (512, 1)),
          3: ((32, 8), (64, 4), (128, 2), (32, 16), (64, 8))}
-CHUNKS = {2: (8, 16, 32, 64, 128), 3: (16, 32, 64, 128)}
+CHUNKS = {2: (2, 3, 4, 6, 8, 16, 32, 64), 3: (8, 16, 32, 64, 128)}
 
 
 def _time_phases(sol, steps: int) -> dict:
