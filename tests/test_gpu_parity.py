@@ -214,3 +214,16 @@ def test_rebound_step_outputs_are_written_in_place(frozen):
         assert torch.equal(bound.field(k), ref.field(k)), k
     for s in sols:
         s.close()
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(vert_periodic=True), dict(precision="fp64_shifted")])
+def test_tall_grid_more_planes_than_one_launch_row(kw):
+    """A vertical extent beyond 65,535 planes: the S update strides its
+    planes over the launch's second grid dimension, and the transport's
+    vertical chunks number in the tens of thousands."""
+    cfg = lbw.RunConfig(nx=3, ny=70001, vs=2e-3, kappa_c=1e-3, has_s=True, kappa_s=1e-3,
+                        fluid_mode=lbw.FLUID_FROZEN, **kw)
+    rng = np.random.default_rng(71)
+    c0, s0 = rng.uniform(0, 1, cfg.shape), rng.uniform(0, 1, cfg.shape)
+    u = 0.05 * rng.standard_normal((cfg.dim,) + cfg.shape)
+    _check(cfg, 3, c0, s0, u, launch=dict(tile_x=64, tile_y=2))
