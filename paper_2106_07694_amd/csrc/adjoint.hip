@@ -469,33 +469,67 @@ __global__ void __launch_bounds__(256) k_adj_stage2d(AdjDev A, const T *__restri
         return p < 0 ? 0 : (p >= ny ? ny - 1 : p);
     };
 
-    // stage the inputs
-    for (int i = tid; i < TY * HX; i += NT) {
+    // stage the inputs.  Every slot is loaded into registers first,
+    // unconditionally (a spare slot repeats the last entry of its array), so
+    // all of the tile's loads are in flight together; a loop that stored
+    // each load to LDS before issuing the next waited for every load in turn
+    constexpr int N1 = TY * HX, N2 = TY * LX, N3 = HY * TX, N4 = LY * TX;
+    constexpr int S1 = (N1 + NT - 1) / NT, S2 = (N2 + NT - 1) / NT, S3 = (N3 + NT - 1) / NT,
+                  S4 = (N4 + NT - 1) / NT;
+    T pA1[S1], pW1[S1], pL2[S2], pA3[S3], pW3[S3], pL4[S4];
+    bool g3[S3];
+#pragma unroll
+    for (int q = 0; q < S1; ++q) {
+        const int i = min(tid + q * NT, N1 - 1);
         const int ly = i / HX, c = i % HX;
         const int gy = min(y0 + ly, ny - 1);
         const int64_t k = (int64_t)wrap_any(x0 - 5 + c, nx) + (int64_t)nx * gy;
-        sAx[i] = a[k];
-        sWx[i] = ux[k];
+        pA1[q] = a[k];
+        pW1[q] = ux[k];
     }
-    for (int i = tid; i < TY * LX; i += NT) {
+#pragma unroll
+    for (int q = 0; q < S2; ++q) {
+        const int i = min(tid + q * NT, N2 - 1);
         const int ly = i / LX, c = i % LX;
         const int gy = min(y0 + ly, ny - 1);
-        sLx[i] = lam[(int64_t)wrap_any(x0 - 3 + c, nx) + (int64_t)nx * gy];
+        pL2[q] = lam[(int64_t)wrap_any(x0 - 3 + c, nx) + (int64_t)nx * gy];
     }
-    for (int i = tid; i < HY * TX; i += NT) {
+#pragma unroll
+    for (int q = 0; q < S3; ++q) {
+        const int i = min(tid + q * NT, N3 - 1);
         const int ry = i / TX, lx = i % TX;
-        bool ghost;
-        const int gy = vrow(y0 - 5 + ry, ghost);
+        const int gy = vrow(y0 - 5 + ry, g3[q]);
         const int64_t k = (int64_t)wrap_any(x0 + lx, nx) + (int64_t)nx * gy;
-        sAy[i] = a[k];
-        const T uu = uy[k];
-        sWy[i] = (ghost ? -uu : uu) - vs;
+        pA3[q] = a[k];
+        pW3[q] = uy[k];
     }
-    for (int i = tid; i < LY * TX; i += NT) {
+#pragma unroll
+    for (int q = 0; q < S4; ++q) {
+        const int i = min(tid + q * NT, N4 - 1);
         const int ry = i / TX, lx = i % TX;
         bool ghost;
         const int gy = vrow(y0 - 3 + ry, ghost);
-        sLy[i] = lam[(int64_t)wrap_any(x0 + lx, nx) + (int64_t)nx * gy];
+        pL4[q] = lam[(int64_t)wrap_any(x0 + lx, nx) + (int64_t)nx * gy];
+    }
+#pragma unroll
+    for (int q = 0; q < S1; ++q) {
+        const int i = tid + q * NT;
+        if (i < N1) { sAx[i] = pA1[q]; sWx[i] = pW1[q]; }
+    }
+#pragma unroll
+    for (int q = 0; q < S2; ++q) {
+        const int i = tid + q * NT;
+        if (i < N2) sLx[i] = pL2[q];
+    }
+#pragma unroll
+    for (int q = 0; q < S3; ++q) {
+        const int i = tid + q * NT;
+        if (i < N3) { sAy[i] = pA3[q]; sWy[i] = (g3[q] ? -pW3[q] : pW3[q]) - vs; }
+    }
+#pragma unroll
+    for (int q = 0; q < S4; ++q) {
+        const int i = tid + q * NT;
+        if (i < N4) sLy[i] = pL4[q];
     }
     __syncthreads();
 
