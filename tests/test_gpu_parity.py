@@ -154,15 +154,19 @@ def test_3d_transport_launches(launch, vper):
     _check(cfg, 8, c0, launch=launch)
 
 
-@pytest.mark.parametrize("q", [9, 19])
+@pytest.mark.parametrize("q", [9, 19, "19s"])
 def test_pipelined_equals_sequential_bitwise(q):
     """The slab-pipelined variant runs the same kernels on the same data in a
-    different order: its results must be identical bit for bit."""
+    different order (the S update slab by slab): its results must be
+    identical bit for bit."""
     if q == 9:
         wl = W.C2.replace(nx=192, ny=160)
         kw = dict(tile_x=64, tile_y=8)
-    else:
+    elif q == 19:
         wl = W.C3.replace(nx=32, ny=24, nz=40)
+        kw = dict(tile_x=32, tile_y=4)
+    else:
+        wl = W.C3.replace(nx=32, ny=24, nz=40, has_s=True, kappa_s=1e-4, gp_s=2e-5)
         kw = dict(tile_x=32, tile_y=4)
     cfg = lbw.RunConfig.from_workload(wl)
     c0, s0 = W.initial_scalars(wl)
