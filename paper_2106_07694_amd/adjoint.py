@@ -42,12 +42,16 @@ def _solver(cfg: lbw.RunConfig, vs: float, launch=None) -> lbw.Solver:
     return sol
 
 
+# The per-step buffers of a replayed segment are views of one allocation per
+# kind (contiguous slices), so a backward pass allocates a handful of blocks
+# rather than several hundred small ones.
 def _state_buffers(sol, count, populations=True):
     cfg = sol.cfgs[0]
+    e = lambda *shape: torch.empty(shape, dtype=sol.dtype, device=sol.device)
     with torch.cuda.stream(sol.stream):
-        return [(torch.empty((cfg.lattice,) + cfg.shape, dtype=sol.dtype, device=sol.device)
-                 if populations else None,
-                 torch.empty(cfg.shape, dtype=sol.dtype, device=sol.device)) for _ in range(count)]
+        f = e(count, cfg.lattice, *cfg.shape) if populations else None
+        c = e(count, *cfg.shape)
+        return [(f[i] if populations else None, c[i]) for i in range(count)]
 
 
 def _step_buffers(sol, count, moments=True):
@@ -56,8 +60,11 @@ def _step_buffers(sol, count, moments=True):
     cfg = sol.cfgs[0]
     e = lambda *shape: torch.empty(shape, dtype=sol.dtype, device=sol.device)
     with torch.cuda.stream(sol.stream):
-        return [(e(cfg.dim, *cfg.shape) if moments else None, e(*cfg.shape) if moments else None,
-                 e(*cfg.shape), e(*cfg.shape)) for _ in range(count)]
+        u = e(count, cfg.dim, *cfg.shape) if moments else None
+        rho = e(count, *cfg.shape) if moments else None
+        a1, a2 = e(count, *cfg.shape), e(count, *cfg.shape)
+        return [(u[i] if moments else None, rho[i] if moments else None, a1[i], a2[i])
+                for i in range(count)]
 
 
 def forward_with_checkpoints(cfg, c0: torch.Tensor, vs: float, nsteps: int, seg: int, launch=None,
