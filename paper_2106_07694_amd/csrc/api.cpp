@@ -577,7 +577,6 @@ int enqueue_step_pipelined(lbw_handle *h, bool primed) {
         if (i >= 2) {
             const int q = i - 2;
             e = lbw::launch_stage_slab(h->dim, h->precision, r, h->launch, 3, lo[q], hi[q], B);
-            if (e == hipSuccess && h->has_s) e = lbw::launch_s_update(h->dim, h->precision, r, B, lo[q] * sv, hi[q] * sv);
             if (e != hipSuccess) return hip_fail(e, "stage 3 launch");
             e = hipEventRecord(h->ev_tr[q], B);
             if (e != hipSuccess) return hip_fail(e, "event record");

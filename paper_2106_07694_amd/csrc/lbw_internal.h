@@ -109,8 +109,6 @@ TileShape resolve_tile_shape(int dim, const lbw_launch &l);
 int64_t transport_tiles(int dim, const RunDev &r, const lbw_launch &l);
 hipError_t launch_transport_batched(int dim, int precision, const BatchArgs &b, const lbw_launch &l,
                                     hipStream_t st);
-// The S update of every run of a batched launch (its entries with has_s).
-hipError_t batched_s_updates(int dim, int precision, const BatchArgs &b, hipStream_t st);
 // The tiled stages of runs whose settling speed depends on S (b: batched
 // entries, or NULL for the single run r).
 hipError_t launch_transport_tiled_vs(int dim, int precision, const RunDev &r, const lbw_launch &l,

@@ -139,8 +139,18 @@ __device__ __forceinline__ const T &at(const void *plane, uint32_t off) {
 // a wall); the conservative face fluxes then carry the -phi d(Vs)/dz term of
 // eq. 7.  S is read at time level n, which the S update of this step does not
 // overwrite (it writes the other S buffer).
-template <typename T, int D, int SCHEME, int STAGE, int TX, int TY, bool FULL, bool VSS>
-__device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, int bx, int by, int bz) {
+// FS (stage 1 only): the S update (S5-S6 in conservative form, the
+// arithmetic and sum order of k_s_update) rides with the march.  It needs the
+// velocity this stage already stages (lateral components in LDS, the
+// vertical one read per plane) plus S on the plane with a one-cell lateral
+// halo and at the next plane of the column; s_entry is false for a batch
+// entry that carries no S (a size class after the first), which then loads
+// C in its place and stores nothing.
+template <typename T, int D, int SCHEME, int STAGE, int TX, int TY, bool FULL, bool VSS,
+          bool FS = false>
+__device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, int bx, int by, int bz,
+                                           bool s_entry = true) {
+    static_assert(!FS || STAGE == 1, "the S update rides with stage 1");
     constexpr int NT = TX * TY;
     constexpr int AX = TX + 6;                  // a plane row length (x halo 3 + 3)
     constexpr int AY = (D == 3) ? TY + 6 : 1;   // a plane rows
@@ -149,6 +159,11 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
     __shared__ T sUy[(D == 3) ? (TY + 6) * TX : 1];
     __shared__ T sFx[TY * (TX + 1)];
     __shared__ T sFy[(D == 3) ? (TY + 1) * TX : 1];
+    constexpr int SXL = TX + 2;                         // S row with a one-cell x halo
+    constexpr int SYL = (D == 3) ? TY + 2 : 1;          // S rows (one-cell y halo in 3D)
+    __shared__ T sS[FS ? SXL * SYL : 1];
+    __shared__ T sGx[FS ? TY * (TX + 1) : 1];           // S face fluxes
+    __shared__ T sGy[(FS && D == 3) ? (TY + 1) * TX : 1];
 
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
@@ -250,6 +265,31 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
         }
     }
 
+    // S slots (FS): the plane's S on the tile with a one-cell halo (the 3D
+    // corners are loaded and not read)
+    constexpr int NSS = FS ? SXL * SYL : 0;
+    constexpr int SSS = (NSS + NT - 1) / NT;
+    uint32_t offS[(SSS > 0) ? SSS : 1];
+    int ldsS[(SSS > 0) ? SSS : 1];
+#pragma unroll
+    for (int s = 0; s < SSS; ++s) {
+        const int i = tid + s * NT;
+        ldsS[s] = -1;
+        offS[s] = 0;
+        if (i < NSS) {
+            const int lx = i % SXL, ly = i / SXL;
+            offS[s] = lat(wrapx(x0 + lx - 1), (D == 3) ? wrapy(y0 + ly - 1) : 0);
+            ldsS[s] = i;
+        }
+    }
+    const T *__restrict__ sin = (const T *)(FS && s_entry ? r.s : r.c);
+    const T kaps = (T)r.kappa_s;
+    // S face between nodes j (a2, w2) and j + 1 (a3, w3)
+    auto sface = [&](T a2, T a3, T w2, T w3) -> T {
+        const T hh = ((T)0.5 * (w2 + w3) >= (T)0) ? w2 * a2 : w3 * a3;
+        return hh - kaps * (a3 - a2);
+    };
+
     // faces on the far edges of the tile (x faces of column TX, y faces of
     // row TY), taken by the first lanes in one extra pass with strided LDS
     // reads, so that the main passes are exactly one face per thread
@@ -270,6 +310,19 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
                                   ww[3], ww[4], kap, eps);
     }
 
+    // S and the raw vertical velocity at this plane of the column, and the S
+    // face below the first plane (closed walls; periodic: wrapped)
+    T s_c = (T)0, us_c = (T)0, gbelow = (T)0;
+    if constexpr (FS) {
+        s_c = at<T>(plane(sin, v0), colb);
+        us_c = at<T>(plane(uv, v0), colb);
+        if (!(walls && v0 == 0)) {
+            bool flip;
+            const int vb = vidx(v0 - 1, flip);
+            gbelow = sface(at<T>(plane(sin, vb), colb), s_c, at<T>(plane(uv, vb), colb), us_c);
+        }
+    }
+
     // deposit of stage 3 (D += Vs (C/6 + a1/6 + 2 a2/3) at the bottom cell),
     // done before the march so that no load or store sits on a path of its own
     if constexpr (STAGE == 3) {
@@ -285,11 +338,13 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
     }
 
     // prefetch registers for the lateral planes
-    T pA[SA], pX[SUX], pY[(SUY > 0) ? SUY : 1];
+    T pA[SA], pX[SUX], pY[(SUY > 0) ? SUY : 1], pS[(SSS > 0) ? SSS : 1];
     auto prefetch = [&](int v) {
         bool flip;
         const int vv = vidx(v, flip);
         const void *pa = plane(ain, vv), *px = plane(ux, vv), *py = plane(uy, vv);
+#pragma unroll
+        for (int s = 0; s < SSS; ++s) pS[s] = at<T>(plane(sin, vv), offS[s]);
         // unconditional: slots without an LDS target read column 0 (in
         // bounds) and are dropped at publication, so no load sits behind a
         // branch
@@ -326,6 +381,8 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
             for (int s = 0; s < SUX; ++s) asm volatile("" : "+v"(offX[s]));
 #pragma unroll
             for (int s = 0; s < SUY; ++s) asm volatile("" : "+v"(offY[s]));
+#pragma unroll
+            for (int s = 0; s < SSS; ++s) asm volatile("" : "+v"(offS[s]));
             // publish plane v
 #pragma unroll
             for (int s = 0; s < SA; ++s) if (ldsA[s] >= 0) sA[ldsA[s]] = pA[s];
@@ -333,6 +390,8 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
             for (int s = 0; s < SUX; ++s) if (ldsX[s] >= 0) sUx[ldsX[s]] = pX[s];
 #pragma unroll
             for (int s = 0; s < SUY; ++s) if (ldsY[s] >= 0) sUy[ldsY[s]] = pY[s];
+#pragma unroll
+            for (int s = 0; s < SSS; ++s) if (ldsS[s] >= 0) sS[ldsS[s]] = pS[s];
             __syncthreads();
             // loads, in the order they are consumed (the load counter drains in
             // issue order, so waiting for one waits for all issued before it):
@@ -345,6 +404,13 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
             if (STAGE != 1) cown = at<T>(plane(r.c, v), colb);
             T anext, wnext;
             load_av(v + 4, anext, wnext);
+            T s_n = (T)0, us_n = (T)0;
+            if constexpr (FS) {
+                bool flip;
+                const int vn = vidx(v + 1, flip);
+                s_n = at<T>(plane(sin, vn), colb);
+                us_n = at<T>(plane(uv, vn), colb);
+            }
             prefetch(v + 1);
 
             // lateral faces: each thread the x face on the left of its cell and
@@ -362,6 +428,17 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
                                                      ac[5 * AX], uc[0], uc[TX], uc[2 * TX], uc[3 * TX],
                                                      uc[4 * TX], uc[5 * TX], kap, eps);
             }
+            if constexpr (FS) {
+                // S faces on the left of the cell and (3D) below it
+                const T *sr = sS + ((D == 3) ? ty + 1 : 0) * SXL + tx;     // x - 1, x
+                const T *ur = sUx + ty * AX + tx + 2;
+                sGx[ty * (TX + 1) + tx] = sface(sr[0], sr[1], ur[0], ur[1]);
+                if constexpr (D == 3) {
+                    const T *sc = sS + ty * SXL + tx + 1;                  // y - 1, y
+                    const T *uc = sUy + (ty + 2) * TX + tx;
+                    sGy[ty * TX + tx] = sface(sc[0], sc[SXL], uc[0], uc[TX]);
+                }
+            }
             for (int e = tid; e < NEX; e += NT) {
                 const bool xf = e < TY;                   // x face of column TX, row e
                 const int fy = xf ? e : TY, fx = xf ? TX : e - TY;
@@ -376,6 +453,17 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
                                              kap, eps);
                 if (xf) sFx[fy * (TX + 1) + fx] = f;
                 else if constexpr (D == 3) sFy[fy * TX + fx] = f;
+                if constexpr (FS) {
+                    if (xf) {
+                        const T *sr = sS + ((D == 3) ? fy + 1 : 0) * SXL + TX;
+                        const T *ur2 = sUx + fy * AX + TX + 2;
+                        sGx[fy * (TX + 1) + TX] = sface(sr[0], sr[1], ur2[0], ur2[1]);
+                    } else if constexpr (D == 3) {
+                        const T *sc = sS + TY * SXL + fx + 1;
+                        const T *uc = sUy + (TY + 2) * TX + fx;
+                        sGy[TY * TX + fx] = sface(sc[0], sc[SXL], uc[0], uc[TX]);
+                    }
+                }
             }
             // vertical face above this cell
             T fabove;
@@ -384,6 +472,8 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
             else
                 fabove = face6<T, SCHEME>(A(0), A(1), A(2), A(3), A(4), A(5), W(0), W(1), W(2), W(3),
                                           W(4), W(5), kap, eps);
+            T gabove = (T)0;
+            if constexpr (FS) gabove = (walls && v == g.nv - 1) ? (T)0 : sface(s_c, s_n, us_c, us_n);
             __syncthreads();
             T L = -(fabove - fbelow);
             L -= sFx[ty * (TX + 1) + tx + 1] - sFx[ty * (TX + 1) + tx];
@@ -398,6 +488,15 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
                     *(T *)((char *)wplane(r.c, v) + colb) = rk3_stage3<T>(cown, a, L);
                 }
             }
+            if constexpr (FS) {
+                T Ls = -(sGx[ty * (TX + 1) + tx + 1] - sGx[ty * (TX + 1) + tx]);
+                if constexpr (D == 3) Ls -= sGy[(ty + 1) * TX + tx] - sGy[ty * TX + tx];
+                Ls -= gabove - gbelow;
+                if (active && s_entry) *(T *)((char *)wplane(r.s2, v) + colb) = s_c + Ls;
+                gbelow = gabove;
+                s_c = s_n;
+                us_c = us_n;
+            }
             fbelow = fabove;
             A(0) = anext;                     // position 0 leaves, node v + 4 enters
             W(0) = wnext;
@@ -406,11 +505,11 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
     }
 }
 
-template <typename T, int D, int SCHEME, int STAGE, int TX, int TY, bool FULL, bool VSS>
+template <typename T, int D, int SCHEME, int STAGE, int TX, int TY, bool FULL, bool VSS, bool FS = false>
 __global__ void __launch_bounds__(TX *TY) k_stage_tiled(RunDev r, TileGeom g) {
     int bx, by, bz;
     block_tile(g, bx, by, bz);
-    stage_tile<T, D, SCHEME, STAGE, TX, TY, FULL, VSS>(r, g, bx, by, bz);
+    stage_tile<T, D, SCHEME, STAGE, TX, TY, FULL, VSS, FS>(r, g, bx, by, bz, true);
 }
 
 template <int D>
@@ -434,7 +533,7 @@ __host__ __device__ inline TileGeom make_geom(const RunDev &r, int chunk, int TX
 // takes a contiguous range of the global tile list (runs in order, tiles of
 // a run x-fastest), so neighbouring tiles share an L2.  tile_start[b] is the
 // first global tile of run b (prefix sum, nbatch + 1 entries).
-template <typename T, int D, int SCHEME, int STAGE, int TX, int TY, bool VSS>
+template <typename T, int D, int SCHEME, int STAGE, int TX, int TY, bool VSS, bool FS = false>
 __global__ void __launch_bounds__(TX *TY) k_stage_batched(const RunDev *__restrict__ runs,
                                                           const int *__restrict__ tile_start,
                                                           int nbatch, int chunk, int sflip,
@@ -461,22 +560,30 @@ __global__ void __launch_bounds__(TX *TY) k_stage_batched(const RunDev *__restri
         const TileGeom g = make_geom<D>(r, chunk, TX, TY);
         const int t = w - tile_start[b];
         const int bx = t % g.gx, rest = t / g.gx;
-        stage_tile<T, D, SCHEME, STAGE, TX, TY, false, VSS>(r, g, bx, rest % g.gy, rest / g.gy);
+        stage_tile<T, D, SCHEME, STAGE, TX, TY, false, VSS, FS>(r, g, bx, rest % g.gy, rest / g.gy,
+                                                               r.has_s != 0);
     }
 }
 
 // The whole-tile form when the grid divides into tiles, else the masked one
 // (runs with a variable settling speed always take the masked form, which
 // halves the kernels built for them).
-template <typename T, int D, int SCHEME, int STAGE, int TX, int TY, bool VSS>
+template <typename T, int D, int SCHEME, int STAGE, int TX, int TY, bool VSS, bool FS = false>
 void launch_stage(const RunDev &r, const TileGeom &g, unsigned nb, hipStream_t st) {
     if constexpr (!VSS) {
         if (g.nx % TX == 0 && (D == 2 || g.ny % TY == 0)) {
-            k_stage_tiled<T, D, SCHEME, STAGE, TX, TY, true, false><<<nb, TX * TY, 0, st>>>(r, g);
+            k_stage_tiled<T, D, SCHEME, STAGE, TX, TY, true, false, FS><<<nb, TX * TY, 0, st>>>(r, g);
             return;
         }
     }
-    k_stage_tiled<T, D, SCHEME, STAGE, TX, TY, false, VSS><<<nb, TX * TY, 0, st>>>(r, g);
+    k_stage_tiled<T, D, SCHEME, STAGE, TX, TY, false, VSS, FS><<<nb, TX * TY, 0, st>>>(r, g);
+}
+
+// Stage 1, carrying the S update when the run has S.
+template <typename T, int D, int SCHEME, int TX, int TY, bool VSS>
+void launch_stage1(const RunDev &r, const TileGeom &g, unsigned nb, hipStream_t st) {
+    if (r.has_s) launch_stage<T, D, SCHEME, 1, TX, TY, VSS, true>(r, g, nb, st);
+    else launch_stage<T, D, SCHEME, 1, TX, TY, VSS, false>(r, g, nb, st);
 }
 
 template <typename T, int D, int SCHEME, int TX, int TY, bool VSS>
@@ -484,14 +591,8 @@ hipError_t stages(const RunDev &r, int chunk, hipStream_t st) {
     const TileGeom g = make_geom<D>(r, chunk, TX, TY);
     const int64_t nb = (int64_t)g.gx * g.gy * g.gz;
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
-    launch_stage<T, D, SCHEME, 1, TX, TY, VSS>(r, g, (unsigned)nb, st);
+    launch_stage1<T, D, SCHEME, TX, TY, VSS>(r, g, (unsigned)nb, st);
     launch_stage<T, D, SCHEME, 2, TX, TY, VSS>(r, g, (unsigned)nb, st);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (r.has_s) {
-        e = launch_s_update(D, sizeof(T) == 4 ? LBW_FP32_SHIFTED : LBW_FP64, r, st);
-        if (e != hipSuccess) return e;
-    }
     launch_stage<T, D, SCHEME, 3, TX, TY, VSS>(r, g, (unsigned)nb, st);
     return hipGetLastError();
 }
@@ -504,7 +605,7 @@ hipError_t stage_slab_t(const RunDev &r, int chunk, int stage, int v_lo, int v_h
     g.bz0 = c0;
     g.gz = c1 - c0;
     const int64_t nb = (int64_t)g.gx * g.gy * g.gz;
-    if (stage == 1) launch_stage<T, D, SCHEME, 1, TX, TY, false>(r, g, (unsigned)nb, st);
+    if (stage == 1) launch_stage1<T, D, SCHEME, TX, TY, false>(r, g, (unsigned)nb, st);
     else if (stage == 2) launch_stage<T, D, SCHEME, 2, TX, TY, false>(r, g, (unsigned)nb, st);
     else launch_stage<T, D, SCHEME, 3, TX, TY, false>(r, g, (unsigned)nb, st);
     return hipGetLastError();
@@ -553,8 +654,13 @@ hipError_t stage_slab_d(const RunDev &r, const lbw_launch &l, int stage, int v_l
 
 template <typename T, int D, int SCHEME, int TX, int TY, bool VSS>
 hipError_t stages_batched(const BatchArgs &a, hipStream_t st) {
+    bool any_s = false;
+    for (int i = 0; i < a.nbatch; ++i) any_s = any_s || a.host_runs[i].has_s;
     auto stage = [&](int k) {
-        if (k == 1)
+        if (k == 1 && any_s)
+            k_stage_batched<T, D, SCHEME, 1, TX, TY, VSS, true><<<a.grid, TX * TY, 0, st>>>(
+                a.runs, a.tile_start, a.nbatch, a.chunk, a.sflip, a.form);
+        else if (k == 1)
             k_stage_batched<T, D, SCHEME, 1, TX, TY, VSS><<<a.grid, TX * TY, 0, st>>>(
                 a.runs, a.tile_start, a.nbatch, a.chunk, a.sflip, a.form);
         else if (k == 2)
@@ -568,7 +674,6 @@ hipError_t stages_batched(const BatchArgs &a, hipStream_t st) {
     if (a.stage != 0) return stage(a.stage);
     hipError_t e = stage(1);
     if (e == hipSuccess) e = stage(2);
-    if (e == hipSuccess) e = batched_s_updates(D, sizeof(T) == 4 ? LBW_FP32_SHIFTED : LBW_FP64, a, st);
     if (e == hipSuccess) e = stage(3);
     return e;
 }

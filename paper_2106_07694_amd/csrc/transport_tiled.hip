@@ -40,17 +40,6 @@ hipError_t launch_stage_slab(int dim, int precision, const RunDev &r, const lbw_
                     : stage_slab_d<double, 3>(r, l, stage, v_lo, v_hi, st);
 }
 
-hipError_t batched_s_updates(int dim, int precision, const BatchArgs &b, hipStream_t st) {
-    for (int i = 0; i < b.nbatch; ++i) {
-        RunDev r = b.host_runs[i];
-        if (!r.has_s) continue;               // size classes after the first of a run
-        if (b.sflip) { void *t = r.s; r.s = r.s2; r.s2 = t; }
-        const hipError_t e = launch_s_update(dim, precision, r, st);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
-}
-
 hipError_t launch_transport_batched(int dim, int precision, const BatchArgs &b, const lbw_launch &l,
                                     hipStream_t st) {
     const RunDev &r = b.host_runs[0];
@@ -63,7 +52,6 @@ hipError_t launch_transport_batched(int dim, int precision, const BatchArgs &b, 
     BatchArgs x = b;
     for (int k = 1; k <= 3; ++k) {
         hipError_t e = hipSuccess;
-        if (k == 3) e = batched_s_updates(dim, precision, b, st);
         x.stage = k;
         x.form = 0;
         if (e == hipSuccess) e = tiled_any<false>(dim, precision, r, l, st, &x);

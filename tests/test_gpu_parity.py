@@ -231,3 +231,26 @@ def test_tall_grid_more_planes_than_one_launch_row(kw):
     c0, s0 = rng.uniform(0, 1, cfg.shape), rng.uniform(0, 1, cfg.shape)
     u = 0.05 * rng.standard_normal((cfg.dim,) + cfg.shape)
     _check(cfg, 3, c0, s0, u, launch=dict(tile_x=64, tile_y=2))
+
+
+@pytest.mark.parametrize("kw", [dict(nx=70, ny=33), dict(nx=70, ny=33, vert_periodic=True),
+                                dict(lattice=19, nx=21, ny=13, nz=17),
+                                dict(lattice=19, nx=21, ny=13, nz=17, vert_periodic=True)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_shifted"])
+def test_s_update_fused_in_stage1_equals_separate_kernel(kw, precision):
+    """The tiled transport carries the S update in its first stage; the plain
+    transport runs it as a kernel of its own.  Same arithmetic and sum order:
+    S agrees to a few units in the last place (frozen flow, so only the S
+    update differs between the two paths)."""
+    cfg = lbw.RunConfig(fluid_mode=lbw.FLUID_FROZEN, has_s=True, kappa_s=1e-3, vs=2e-3,
+                        kappa_c=1e-3, precision=precision, **kw)
+    rng = np.random.default_rng(73)
+    c0 = as_input(rng.uniform(0, 1, cfg.shape), cfg)
+    s0 = as_input(rng.uniform(0, 1, cfg.shape), cfg)
+    u = as_input(0.05 * rng.standard_normal((cfg.dim,) + cfg.shape), cfg)
+    fused = run_gpu(cfg, c0, s0, u, None, 9, launch=dict(tile_x=64, tile_y=5))
+    plain = run_gpu(cfg, c0, s0, u, None, 9, launch=dict(variant=1))
+    eps = np.finfo(np.float64 if precision == "fp64" else np.float32).eps
+    d = float(np.max(np.abs(fused["s"] - plain["s"]))) / float(np.max(np.abs(plain["s"])))
+    print(f"\n{precision} {kw}: S fused vs separate {d:.2e} ({int(np.count_nonzero(fused['s'] != plain['s']))} cells differ)")
+    assert d <= 8 * eps, d
