@@ -244,6 +244,21 @@ int lbw_import(lbw_handle *h, int32_t run, int32_t field, const void *src);
  * stream).  Returns LBW_ERR_INVAL for any other field. */
 int lbw_rebind(lbw_handle *h, int32_t run, int32_t field, void *ptr);
 
+/* Replay n steps of run `run` from its current state, keeping what the
+ * reverse steps of the adjoint read (S21-S23 and eq. 19-20 at each step):
+ * before step i, C is copied into c_out[i] (every size class, as lbw_export
+ * gives it); during step i the velocity, the density and the first two RK
+ * stages are written into u_out[i], rho_out[i], a1_out[i] and a2_out[i].
+ * The six arrays hold n device pointers each (host arrays of pointers, read
+ * during the call); u_out and rho_out are NULL for LBW_FLUID_FROZEN.  It is n
+ * rounds of lbw_export(C), lbw_rebind(U, RHO, STAGE1, STAGE2) and
+ * lbw_step(1) without a host call per step; afterwards the four fields are
+ * bound back to the buffers given at creation.  Asynchronous on the handle's
+ * stream; the buffers must stay valid until that work has run.  Returns
+ * LBW_ERR_INVAL for n < 0 or a NULL array or element where one is needed. */
+int lbw_replay(lbw_handle *h, int32_t run, int32_t n, void *const *c_out, void *const *u_out,
+               void *const *rho_out, void *const *a1_out, void *const *a2_out);
+
 /* FP64 sums per run into out_host[nbatch]: LBW_MASS_C (sum C over every
  * size class), LBW_MASS_S (sum S), LBW_MASS_FLUID (sum rho), LBW_DEPOSIT
  * (sum of the deposit counters of every class), the particle mass and

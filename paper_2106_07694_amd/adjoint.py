@@ -119,17 +119,13 @@ def backward_from_checkpoints(sol: lbw.Solver, ckpt: dict, nsteps: int, seg: int
         if not frozen:
             sol.import_from("f", f_s)
         sol.import_from("c", c_s)
-        # replay the segment: the step writes its intermediates straight
-        # into that step's buffers
-        for i in range(n):
-            u_n, rho_n, a1, a2 = inter[i]
-            if not frozen:
-                sol.rebind("u", u_n)
-                sol.rebind("rho", rho_n)
-            sol.export_into("c", states[i][1])
-            sol.rebind("stage1", a1)
-            sol.rebind("stage2", a2)
-            sol.step(1)
+        # replay the segment in one library call: each step writes its
+        # intermediates straight into that step's buffers (C is copied
+        # before it)
+        sol.replay([states[i][1] for i in range(n)], [inter[i][2] for i in range(n)],
+                   [inter[i][3] for i in range(n)],
+                   None if frozen else [inter[i][0] for i in range(n)],
+                   None if frozen else [inter[i][1] for i in range(n)])
         for i in reversed(range(n)):
             c_n = states[i][1]
             u_n, rho_n, a1, a2 = inter[i]
@@ -142,9 +138,6 @@ def backward_from_checkpoints(sol: lbw.Solver, ckpt: dict, nsteps: int, seg: int
                                  u_n=u_n, rho_n=rho_n, a1_n=a1, a2_n=a2)
             fbar_next, fbar = fbar, fbar_next
             cbar_next, cbar = cbar, cbar_next
-    for name in ("u", "rho", "stage1", "stage2"):
-        if name in ("stage1", "stage2") or not frozen:
-            sol.rebind(name, None)
     sol.stream.synchronize()
     return cbar_next.clone(), float(vs_bar.item())
 

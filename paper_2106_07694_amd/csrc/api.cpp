@@ -788,6 +788,33 @@ int lbw_rebind(lbw_handle *h, int32_t run, int32_t field, void *ptr) {
     return upload_tables(h);
 }
 
+int lbw_replay(lbw_handle *h, int32_t run, int32_t n, void *const *c_out, void *const *u_out,
+               void *const *rho_out, void *const *a1_out, void *const *a2_out) {
+    int rc = check_run(h, run);
+    if (rc) return rc;
+    if (n < 0) return fail(LBW_ERR_INVAL, "n must be >= 0");
+    const bool lbm = h->fluid_mode == LBW_FLUID_LBM;
+    if (!c_out || !a1_out || !a2_out || (lbm && (!u_out || !rho_out)))
+        return fail(LBW_ERR_INVAL, "NULL pointer array");
+    for (int i = 0; i < n; ++i)
+        if (!c_out[i] || !a1_out[i] || !a2_out[i] || (lbm && (!u_out[i] || !rho_out[i])))
+            return fail(LBW_ERR_INVAL, "NULL buffer for replayed step %d", i);
+    for (int i = 0; i < n && !rc; ++i) {
+        rc = lbw_export(h, run, LBW_FIELD_C, c_out[i]);
+        if (!rc && lbm) rc = lbw_rebind(h, run, LBW_FIELD_U, u_out[i]);
+        if (!rc && lbm) rc = lbw_rebind(h, run, LBW_FIELD_RHO, rho_out[i]);
+        if (!rc) rc = lbw_rebind(h, run, LBW_FIELD_STAGE1, a1_out[i]);
+        if (!rc) rc = lbw_rebind(h, run, LBW_FIELD_STAGE2, a2_out[i]);
+        if (!rc) rc = lbw_step(h, 1);
+    }
+    // bind the per-step outputs back to the handle's own buffers
+    int rb = lbw_rebind(h, run, LBW_FIELD_STAGE1, nullptr);
+    if (!rb) rb = lbw_rebind(h, run, LBW_FIELD_STAGE2, nullptr);
+    if (!rb && lbm) rb = lbw_rebind(h, run, LBW_FIELD_U, nullptr);
+    if (!rb && lbm) rb = lbw_rebind(h, run, LBW_FIELD_RHO, nullptr);
+    return rc ? rc : rb;
+}
+
 int lbw_import(lbw_handle *h, int32_t run, int32_t field, const void *src) {
     int rc = check_run(h, run);
     if (rc) return rc;

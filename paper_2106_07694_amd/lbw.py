@@ -31,7 +31,7 @@ EXPORTED = ("lbw_version", "lbw_last_error", "lbw_scratch_bytes", "lbw_create", 
             "lbw_set_launch", "lbw_get_launch", "lbw_init_equilibrium", "lbw_step",
             "lbw_steps_done", "lbw_export", "lbw_import", "lbw_rebind", "lbw_reduce", "lbw_timing_begin",
             "lbw_timing_end", "lbw_adjoint_work_bytes", "lbw_adjoint_step", "lbw_mass_below",
-            "lbw_front_height", "lbw_front_psd", "lbw_reduce_class")
+            "lbw_front_height", "lbw_front_psd", "lbw_reduce_class", "lbw_replay")
 
 
 class LbwError(RuntimeError):
@@ -103,6 +103,7 @@ def load() -> ctypes.CDLL:
     lib.lbw_export.argtypes = [P, I32, I32, P]
     lib.lbw_import.argtypes = [P, I32, I32, P]
     lib.lbw_rebind.argtypes = [P, I32, I32, P]
+    lib.lbw_replay.argtypes = [P, I32, I32, P, P, P, P, P]
     lib.lbw_reduce.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double)]
     lib.lbw_mass_below.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double)]
     lib.lbw_reduce_class.argtypes = [P, I32, I32, ctypes.POINTER(ctypes.c_double)]
@@ -354,6 +355,15 @@ class Solver:
 
     def step(self, n=1):
         check(self._lib.lbw_step(self._h, int(n)))
+
+    def replay(self, c_out, a1_out, a2_out, u_out=None, rho_out=None, run=0):
+        """len(c_out) steps, keeping per step C before it and the step's
+        velocity, density and first two RK stages (see lbw_replay); the lists
+        hold device tensors, kept alive by the caller until the work has run."""
+        n = len(c_out)
+        arr = lambda ts: (ctypes.c_void_p * n)(*[t.data_ptr() for t in ts]) if ts is not None else None
+        check(self._lib.lbw_replay(self._h, run, n, arr(c_out), arr(u_out), arr(rho_out), arr(a1_out),
+                                   arr(a2_out)))
 
     def steps_done(self) -> int:
         v = ctypes.c_int64(0)

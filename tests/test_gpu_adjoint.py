@@ -294,3 +294,65 @@ def test_fused_2d_transpose_equals_two_kernel_form(shape, vper, precision, froze
     assert torch.equal(cb0, cb1) and torch.equal(vs0, vs1)
     if not frozen:
         assert torch.equal(fb0, fb1)
+
+
+@pytest.mark.parametrize("frozen", [False, True])
+def test_native_replay_records_what_the_per_call_replay_records(frozen):
+    """lbw_replay (one call per segment) against rounds of export, rebind and
+    one step from the host: the recorded C, velocity, density and stages,
+    and the state it leaves, agree bit for bit; afterwards the per-step
+    outputs are bound back to the solver's own buffers."""
+    import torch
+
+    cfg = lbw.RunConfig(nx=48, ny=40, tau=0.6, vs=2e-3, kappa_c=1e-3, gp_c=3e-4,
+                        precision="fp32_shifted",
+                        fluid_mode=lbw.FLUID_FROZEN if frozen else lbw.FLUID_LBM)
+    rng = np.random.default_rng(17)
+    c0 = rng.uniform(0, 1, cfg.shape)
+    u0 = 0.03 * rng.standard_normal((2,) + cfg.shape)
+    n = 7
+
+    def start():
+        sol = lbw.Solver(cfg)
+        sol.set_field("c", c0)
+        if frozen:
+            sol.set_field("u", u0)
+        else:
+            sol.init_equilibrium()
+        return sol
+
+    def bufs():
+        e = lambda *s: torch.empty(s, dtype=torch.float32, device="cuda")
+        return ([e(*cfg.shape) for _ in range(n)], [e(2, *cfg.shape) for _ in range(n)],
+                [e(*cfg.shape) for _ in range(n)], [e(*cfg.shape) for _ in range(n)],
+                [e(*cfg.shape) for _ in range(n)])
+
+    a = start()
+    ca, ua, ra, a1a, a2a = bufs()
+    a.replay(ca, a1a, a2a, None if frozen else ua, None if frozen else ra)
+    a.step(1)                       # the own buffers are bound again
+    b = start()
+    cb, ub, rb, a1b, a2b = bufs()
+    for i in range(n):
+        b.export_into("c", cb[i])
+        if not frozen:
+            b.rebind("u", ub[i])
+            b.rebind("rho", rb[i])
+        b.rebind("stage1", a1b[i])
+        b.rebind("stage2", a2b[i])
+        b.step(1)
+    for name in ("stage1", "stage2") + (() if frozen else ("u", "rho")):
+        b.rebind(name, None)
+    b.step(1)
+    torch.cuda.synchronize()
+    kinds = [(ca, cb), (a1a, a1b), (a2a, a2b)] + ([] if frozen else [(ua, ub), (ra, rb)])
+    for x, y in kinds:
+        for i in range(n):
+            assert torch.equal(x[i], y[i]), i
+    for k in ("c", "deposit", "stage1", "stage2") + (() if frozen else ("f", "u")):
+        assert torch.equal(a.field(k), b.field(k)), k
+    if not frozen:                  # a coupled run needs the density buffers
+        with pytest.raises(lbw.LbwError):
+            a.replay([ca[0]], [a1a[0]], [a2a[0]], [ua[0]], None)
+    a.close()
+    b.close()
