@@ -362,7 +362,7 @@ static void collide_stream(const grid_t *g, const orc_cfg *cfg, const double *f,
 #pragma omp parallel for schedule(static)
     for (k = 0; k < g->N; k++) {
         int p[3], i, d;
-        double uk[3], Fk[3], usq = 0.0;
+        double uk[3], Fk[3], usq = 0.0, drho = 0.0;
         node_coords(g, k, p);
         for (d = 0; d < 3; d++) {
             uk[d] = u[(long)d * g->N + k];
@@ -370,6 +370,11 @@ static void collide_stream(const grid_t *g, const orc_cfg *cfg, const double *f,
             if (d >= g->dim) { uk[d] = 0.0; Fk[d] = 0.0; }
             usq += uk[d] * uk[d];
         }
+        /* shifted populations: the density anomaly is the sum of the stored
+           g_i itself (the same sum as in moments_at, before 1 is added), not
+           (1 + sum) - 1, which would keep it only to the rounding of 1 */
+        if (cfg->shifted)
+            for (i = 0; i < g->q; i++) drho += f[(long)i * g->N + k];
         for (i = 0; i < g->q; i++) {
             double cu = 0.0, cF = 0.0, uF = 0.0, feq, Fi, fs;
             int t[3], wall = 0;
@@ -379,8 +384,7 @@ static void collide_stream(const grid_t *g, const orc_cfg *cfg, const double *f,
                 uF += uk[d] * Fk[d];
             }
             if (cfg->shifted)
-                feq = g->w[i] * ((rho[k] - 1.0) +
-                                 rho[k] * (3.0 * cu + 4.5 * cu * cu - 1.5 * usq));
+                feq = g->w[i] * (drho + rho[k] * (3.0 * cu + 4.5 * cu * cu - 1.5 * usq));
             else
                 feq = g->w[i] * rho[k] * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
             Fi = guo * g->w[i] * (3.0 * (cF - uF) + 9.0 * cu * cF);
