@@ -4,6 +4,13 @@ sizes, walls or periodic vertical axis, lid, body force, S, size classes,
 settling set by S, buoyancy of S on the fluid fraction, scheme, transport
 variant and tile shape, batches of uneven runs, graph replay.  The draws are
 fixed by the seed, so every run tests the same cases.
+
+The bar is 1e-12 of the field's maximum.  White-noise inputs can be
+conditioned worse than that (the WENO weights, with eps = 1e-6, respond
+steeply to near-equal neighbours): where a field misses 1e-12, the oracle is
+run again with every input perturbed by a random +-1 unit in the last
+place, and the field passes if it lies within four times the change that
+perturbation makes to the oracle's own output.
 """
 import numpy as np
 import pytest
@@ -14,7 +21,7 @@ from parity import as_input, compare, run_gpu, run_oracle
 
 pytestmark = pytest.mark.gpu
 TOL64 = 1e-12
-NCASES = 40
+NCASES = 100
 
 
 def _draw(rng, lattice=None, precision=None, shared=None):
@@ -74,7 +81,19 @@ def _inputs(cfg, rng):
     return c, s, u
 
 
-@pytest.mark.parametrize("case", range(NCASES))
+def _oracle_sensitivity(cfg, c0, s0, u, nsteps, o):
+    """Relative change of each oracle output field when every input value is
+    moved by a random +-1 unit in the last place (FP64)."""
+    rng = np.random.default_rng(7)
+    nudge = lambda x: None if x is None else x * (1 + np.finfo(np.float64).eps *
+                                                  rng.choice([-1.0, 1.0], size=x.shape))
+    o2 = run_oracle(cfg, nudge(c0), nudge(s0), nudge(u), None, nsteps)
+    return compare(o2, o)
+
+
+# the draw of seed 20071 is conditioned at ~1e-12 (white-noise C, WENO3): it
+# takes the sensitivity path
+@pytest.mark.parametrize("case", list(range(NCASES)) + [19071])
 def test_random_config_matches_oracle(case):
     rng = np.random.default_rng(1000 + case)
     cfg = _draw(rng)
@@ -86,6 +105,10 @@ def test_random_config_matches_oracle(case):
     errs = compare(g, o)
     print(f"\ncase {case}: {cfg} {launch} steps={nsteps}: {errs}")
     bad = {k: v for k, v in errs.items() if k != "u" and not v <= TOL64}
+    if bad:
+        sens = _oracle_sensitivity(cfg, c0, s0, u, nsteps, o)
+        print(f"oracle sensitivity to one ulp of its input: {sens}")
+        bad = {k: v for k, v in bad.items() if not v <= 4 * sens[k]}
     assert not bad, (errs, cfg, launch)
     if "f" in o:
         du = float(np.max(np.abs(g["u"] - o["u"])))
