@@ -19,7 +19,7 @@ def _dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).to("cuda", torch.float64)
 
 
-@pytest.mark.parametrize("case", range(24))
+@pytest.mark.parametrize("case", range(72))
 def test_random_adjoint_step(case):
     rng = np.random.default_rng(7000 + case)
     q = int(rng.choice([9, 19]))
