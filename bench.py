@@ -306,6 +306,13 @@ def run_adjoint(nsteps: int) -> dict:
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     sol.close()
+    # warm-up of the gradient path (untimed, like the forward's warm-up
+    # steps): a short forward and backward, so the reverse kernels' first
+    # launches are not inside the timed backward
+    c0w = torch.from_numpy(c0).to("cuda", torch.float32).requires_grad_(True)
+    vsw = torch.tensor(cfg.vs, dtype=torch.float64, requires_grad=True)
+    adjoint.DepositedMass.apply(c0w, vsw, cfg, 4, None, launch).backward()
+    torch.cuda.synchronize()
     c0t = torch.from_numpy(c0).to("cuda", torch.float32).requires_grad_(True)
     vst = torch.tensor(cfg.vs, dtype=torch.float64, requires_grad=True)
     torch.cuda.synchronize()
