@@ -255,7 +255,8 @@ int lbw_rebind(lbw_handle *h, int32_t run, int32_t field, void *ptr);
  * lbw_step(1) without a host call per step; afterwards the four fields are
  * bound back to the buffers given at creation.  Asynchronous on the handle's
  * stream; the buffers must stay valid until that work has run.  Returns
- * LBW_ERR_INVAL for n < 0 or a NULL array or element where one is needed. */
+ * LBW_ERR_INVAL for n < 0 or a NULL array or element where one is needed,
+ * LBW_ERR_UNSUPPORTED for a batch (a step advances every run of it). */
 int lbw_replay(lbw_handle *h, int32_t run, int32_t n, void *const *c_out, void *const *u_out,
                void *const *rho_out, void *const *a1_out, void *const *a2_out);
 

@@ -793,6 +793,7 @@ int lbw_replay(lbw_handle *h, int32_t run, int32_t n, void *const *c_out, void *
     int rc = check_run(h, run);
     if (rc) return rc;
     if (n < 0) return fail(LBW_ERR_INVAL, "n must be >= 0");
+    if (h->nbatch > 1) return fail(LBW_ERR_UNSUPPORTED, "lbw_replay drives a single run (a step advances every run of a batch)");
     const bool lbm = h->fluid_mode == LBW_FLUID_LBM;
     if (!c_out || !a1_out || !a2_out || (lbm && (!u_out || !rho_out)))
         return fail(LBW_ERR_INVAL, "NULL pointer array");

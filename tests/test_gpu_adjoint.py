@@ -356,3 +356,14 @@ def test_native_replay_records_what_the_per_call_replay_records(frozen):
             a.replay([ca[0]], [a1a[0]], [a2a[0]], [ua[0]], None)
     a.close()
     b.close()
+
+
+def test_replay_refuses_a_batch():
+    import torch
+
+    cfgs = [lbw.RunConfig(nx=16, ny=12), lbw.RunConfig(nx=20, ny=10)]
+    sol = lbw.Solver(cfgs, stream=torch.cuda.Stream())
+    t = torch.zeros((16 * 12,), dtype=torch.float64, device="cuda")
+    with pytest.raises(lbw.LbwError):
+        sol.replay([t], [t], [t], [t], [t])
+    sol.close()
