@@ -238,10 +238,10 @@ def run_sweep(steps: int, warmup: int) -> dict:
             "speedup": ms_seq / ms_batched, "launch": launch}
 
 
-def run_precision(nsteps: int, marks=(1000, 5000, 10000, 20000)) -> dict:
-    """Form (1) against the plain FP64 step on the same GPU: the 2D two-scalar
-    workload run in FP32 with shifted populations and in FP64 from the same
-    seeded state; relative L2 differences of u, C and the per-column deposit
+def run_precision(nsteps: int, marks=(1000, 5000, 10000, 20000), wl=None) -> dict:
+    """Form (1) against the plain FP64 step on the same GPU: a workload (the
+    2D two-scalar one unless wl is given) run in FP32 with shifted
+    populations and in FP64 from the same seeded state; relative L2 differences of u, C and the per-column deposit
     (and of the total deposited mass) at several step counts.  The FP64 GPU
     path is the reference here because it equals the FP64 oracle to 1e-12 on
     every size the oracle can step; at this size the oracle would need tens
@@ -250,7 +250,7 @@ def run_precision(nsteps: int, marks=(1000, 5000, 10000, 20000)) -> dict:
     import torch
     from paper_2106_07694_amd import autotune, lbw, workloads as W
 
-    wl = W.C2
+    wl = wl or W.C2
     marks = [m for m in marks if m <= nsteps] or [nsteps]
     runs = {}
     for prec in ("fp64", "fp32_shifted"):
@@ -396,6 +396,9 @@ def main() -> int:
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the FP32-vs-FP64 error report of the 2D workload")
     ap.add_argument("--precision-steps", type=int, default=20000)
+    ap.add_argument("--precision-3d", type=int, default=0, metavar="STEPS",
+                    help="also compare FP32 against FP64 on the 3D workload over STEPS steps "
+                         "(reported under fp32_vs_fp64_3d; off by default)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run the known-size copy kernel (profiler counter calibration); it runs "
                          "by default unless --no-copy")
@@ -465,6 +468,12 @@ def main() -> int:
         last = prec["l2_rel"][str(prec["steps"][-1])]
         print(f"[bench] fp32 vs fp64 after {prec['steps'][-1]} steps: u {last['u']:.2e}, "
               f"C {last['c']:.2e}, deposit {last['deposit']:.2e}", file=sys.stderr, flush=True)
+    prec3 = None
+    if args.precision_3d > 0:
+        prec3 = run_precision(args.precision_3d, marks=(500, 1000, 2000), wl=W.C3)
+        last = prec3["l2_rel"][str(prec3["steps"][-1])]
+        print(f"[bench] 3d fp32 vs fp64 after {prec3['steps'][-1]} steps: u {last['u']:.2e}, "
+              f"C {last['c']:.2e}, deposit {last['deposit']:.2e}", file=sys.stderr, flush=True)
     copy = calibrate_copy() if (args.calibrate_copy or not args.no_copy) else None
     if copy:
         # the achievable-bandwidth reference: a plain copy of known size on
@@ -508,6 +517,7 @@ def main() -> int:
         "sweep": sweep,
         "adjoint": adj,
         "fp32_vs_fp64": prec,
+        "fp32_vs_fp64_3d": prec3,
         "size_classes": poly,
         "full_force": full,
         "copy_calibration": copy,
