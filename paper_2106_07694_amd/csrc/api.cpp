@@ -533,10 +533,11 @@ int ensure_pipeline(lbw_handle *h, int P) {
 // One step of the pipelined variant.  Stream A (the handle's) runs the
 // collide-stream kernel slab by slab; stream B runs the three RK stages in a
 // wavefront over the slabs.  Slab p of stage 1 waits for the collide-stream of
-// slabs up to p+1 (its velocity halo); stages 2 and 3 follow stage 1 on B; the
-// collide-stream of the next step on slab p waits for stage 3 (and S) on
-// slabs up to p+1, which also retires every reader of this step's velocity
-// and concentration in slab p.  `primed` says whether B's events of the
+// slabs up to p+1 (its velocity halo) and carries the slab's S update;
+// stages 2 and 3 follow stage 1 on B; the collide-stream of the next step on
+// slab p waits for stage 3 on slabs up to p+1, which also retires every
+// reader of this step's velocity and concentration in slab p (and, stage 1
+// being earlier on B, the S update of those slabs).  `primed` says whether B's events of the
 // previous step are pending in this call.
 int enqueue_step_pipelined(lbw_handle *h, bool primed) {
     std::vector<int> lo, hi;
