@@ -12,6 +12,7 @@ from .oracle import (  # noqa: F401
     equilibrium,
     moments,
     rhs_c,
+    faces_c,
     run,
     sums,
     library_path,

@@ -24,7 +24,10 @@
  *
  * Parity pins: every routine is exercised by the CPU tests against closed
  * forms or invariants.  The wall ghost rules of the WENO stencils are pinned
- * only through conservation (parity unpinned beyond that).
+ * by a mirror image: every face of a walled run equals the same face of a
+ * periodic run of twice the height that holds the run and its reflection
+ * (the Neumann and no-penetration conditions of eq. 14-15 written out as
+ * data), the wall faces aside.
  */
 #include "lbw_oracle.h"
 
@@ -295,17 +298,13 @@ static double interior_face_flux(const grid_t *g, const orc_cfg *cfg,
     return hhat - kappa * (av[3] - av[2]);
 }
 
-/* L(a) = -sum over axes of (Phi_{j+1/2} - Phi_{j-1/2}).
- * absorbing = 1: the bottom wall face carries the settling flux -vs*a_0
- * (outflow per column returned); otherwise walls carry no flux. */
-static void spatial_operator(const grid_t *g, const orc_cfg *cfg, int scheme,
-                             double kappa, double vs, int absorbing,
-                             const double *a, const double *u, const double *s,
-                             double *L, double *outflow)
+/* phi[ax][k]: flux through the +ax face of node k; the face of the top
+ * wall carries no flux. */
+static void face_fluxes(const grid_t *g, const orc_cfg *cfg, int scheme,
+                        double kappa, double vs, const double *a, const double *u,
+                        const double *s, double *phi)
 {
-    double *phi = (double *)malloc(sizeof(double) * (size_t)g->dim * g->N);
     long k;
-    /* phi[ax][k]: flux through the +ax face of node k */
 #pragma omp parallel for schedule(static)
     for (k = 0; k < g->N; k++) {
         int p[3], d;
@@ -318,6 +317,19 @@ static void spatial_operator(const grid_t *g, const orc_cfg *cfg, int scheme,
                     interior_face_flux(g, cfg, scheme, kappa, vs, a, u, s, p, d);
         }
     }
+}
+
+/* L(a) = -sum over axes of (Phi_{j+1/2} - Phi_{j-1/2}).
+ * absorbing = 1: the bottom wall face carries the settling flux -vs*a_0
+ * (outflow per column returned); otherwise walls carry no flux. */
+static void spatial_operator(const grid_t *g, const orc_cfg *cfg, int scheme,
+                             double kappa, double vs, int absorbing,
+                             const double *a, const double *u, const double *s,
+                             double *L, double *outflow)
+{
+    double *phi = (double *)malloc(sizeof(double) * (size_t)g->dim * g->N);
+    long k;
+    face_fluxes(g, cfg, scheme, kappa, vs, a, u, s, phi);
 #pragma omp parallel for schedule(static)
     for (k = 0; k < g->N; k++) {
         int p[3], d, gh;
@@ -485,6 +497,30 @@ int orc_rhs_c(const orc_cfg *cfg, const double *a, const double *u,
     if (setup(cfg, &g)) return -1;
     spatial_operator(&g, cfg, cfg->scheme_c, cfg->kappa_c, cfg->vs, 1, a, u, NULL,
                      out, outflow);
+    return 0;
+}
+
+int orc_faces_c(const orc_cfg *cfg, const double *a, const double *u, const double *s,
+                double *phi, double *bottom)
+{
+    grid_t g;
+    long k;
+    if (setup(cfg, &g)) return -1;
+    if (g.ncls != 1) return -1;
+    if (cfg->vs_s != 0.0 && !s) return -1;
+    face_fluxes(&g, cfg, cfg->scheme_c, cfg->kappa_c, cfg->vs, a, u,
+                cfg->vs_s != 0.0 ? s : NULL, phi);
+    for (k = 0; k < g.ncol; k++) bottom[k] = 0.0;
+    if (!cfg->vert_periodic) {
+        for (k = 0; k < g.N; k++) {
+            int p[3];
+            node_coords(&g, k, p);
+            /* the same value the operator differences at the bottom wall */
+            if (p[g.vert] == 0)
+                bottom[column_of(&g, p)] =
+                    -settling_at(cfg, cfg->vs_s != 0.0 ? s : NULL, cfg->vs, k) * a[k];
+        }
+    }
     return 0;
 }
 

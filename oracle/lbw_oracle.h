@@ -15,10 +15,11 @@
  *
  * Every routine returns 0 on success and a negative value on bad arguments.
  *
- * Pins (tests/test_oracle_*.py): closed forms and invariants for every part,
- * except the ghost values the WENO stencils see beyond a wall (mirrored
- * scalar, sign-flipped vertical fluid velocity): parity unpinned beyond the
- * particle budget and the uniform-layer deposit, which they must satisfy.
+ * Pins (tests/test_oracle_*.py): closed forms and invariants for every part.
+ * The ghost values the WENO stencils see beyond a wall (mirrored scalar,
+ * sign-flipped vertical fluid velocity, settling kept downward) are pinned by
+ * a mirror image: a walled run's faces equal those of a periodic run of twice
+ * the height holding the run and its reflection (eq. 14-15 as data).
  */
 #ifndef LBW_ORACLE_H
 #define LBW_ORACLE_H
@@ -81,6 +82,17 @@ int orc_moments(const orc_cfg *cfg, const double *f, const double *c,
  * flux through the bottom wall. */
 int orc_rhs_c(const orc_cfg *cfg, const double *a, const double *u,
               double *out, double *outflow);
+
+/* Face fluxes of the C equation (one size class): phi[ax][N] is the flux
+ * through the +ax face of each node (advective WENO or upwind part minus the
+ * central diffusion; the face of the top wall carries none) and bottom[ncol]
+ * the flux through the bottom wall face that the operator differences, the
+ * absorbed settling flux -Vs a_0 (0 with a periodic vertical axis, where the
+ * bottom face of a column is the +face of its top node).  s is read only
+ * when vs_s != 0 (settling speed Vs (1 - vs_s S)).  L(a) of orc_rhs_c is
+ * minus the divergence of these faces. */
+int orc_faces_c(const orc_cfg *cfg, const double *a, const double *u, const double *s,
+                double *phi, double *bottom);
 
 /* Advance nsteps coupled steps in place.  dep has one entry per size class
  * and bottom column (nx in 2D, nx*ny in 3D).  u_in is read in frozen mode; u_out

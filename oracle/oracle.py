@@ -140,6 +140,7 @@ def _load():
         lib.orc_equilibrium.argtypes = [cfgp, P, P, P]
         lib.orc_moments.argtypes = [cfgp, P, P, P, P, P]
         lib.orc_rhs_c.argtypes = [cfgp, P, P, P, P]
+        lib.orc_faces_c.argtypes = [cfgp, P, P, P, P, P]
         lib.orc_run.argtypes = [cfgp, P, P, P, P, P, P, ctypes.c_int32]
         lib.orc_sums.argtypes = [cfgp, P, P, P, P, P]
         lib.orc_adjoint_step.argtypes = [cfgp, P, P, P, P, P, ctypes.c_double, P, P, P]
@@ -198,6 +199,21 @@ def rhs_c(cfg: OracleConfig, a, u):
     cc = cfg._c()
     _check(lib.orc_rhs_c(ctypes.byref(cc), _ptr(a), _ptr(u), _ptr(out), _ptr(outflow)), "rhs_c")
     return out, outflow
+
+
+def faces_c(cfg: OracleConfig, a, u, s=None):
+    """Face fluxes of the C equation: (phi[dim, nz, ny, nx] through the +axis
+    face of every node, bottom[ncol] through the bottom wall)."""
+    lib = _load()
+    a = np.ascontiguousarray(a, np.float64)
+    u = np.ascontiguousarray(u, np.float64)
+    s = None if s is None else np.ascontiguousarray(s, np.float64)
+    phi = np.zeros((cfg.dim,) + cfg.shape, np.float64)
+    bottom = np.zeros(cfg.ncol, np.float64)
+    cc = cfg._c()
+    _check(lib.orc_faces_c(ctypes.byref(cc), _ptr(a), _ptr(u), _ptr(s), _ptr(phi), _ptr(bottom)),
+           "faces_c")
+    return phi, bottom
 
 
 def run(cfg: OracleConfig, f, c, s=None, dep=None, u_in=None, nsteps=1, want_u=False):

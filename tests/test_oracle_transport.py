@@ -260,3 +260,128 @@ def test_settling_front_overshoot(vs, kappa, steps):
     _, c, _, dep, _ = oracle.run(cfg, None, a0, u_in=np.zeros((2,) + cfg.shape), nsteps=steps)
     assert c.min() > -1e-3 and c.max() < 1 + 1e-3, (c.min(), c.max())
     assert abs(c.sum() + dep.sum() - a0.sum()) < 1e-12 * a0.sum()
+
+
+# ---------------------------------------------------------------------------
+# Wall ghosts by a mirror image (section 2.2.1, eq. 14-15).  Zero normal
+# gradient of the scalar and no flow through the wall are what an even
+# reflection of C and an odd reflection of the vertical fluid velocity about
+# the wall produce; settling does not reverse at a wall (it is the particles'
+# own motion, not the fluid's).  A walled run of height n therefore sees, in
+# every stencil that reaches beyond a wall, exactly what a periodic run of
+# height 2n sees when it holds the reflected run below the physical one:
+# image cell n-1-m = physical cell m with C, the lateral velocities and S
+# unchanged and the vertical transport velocity -u_v(m) - Vs(m), physical
+# cells with u_v - Vs.  The periodic run settles at 0 (its velocity carries
+# the settling), so none of the wall rules is in it: each face of the walled
+# run must equal the same face of the periodic run bit for bit, except the
+# two wall faces the method overrides (R10: -Vs a_0 at the bottom, 0 at the
+# top).  An image built by another rule (settling reversed, C odd, fluid
+# velocity even) must not agree, which shows the comparison can fail.
+# ---------------------------------------------------------------------------
+
+def _mirror_case(q, nx, nvert, scheme, vs, kappa, vs_s, seed):
+    rng = np.random.default_rng(seed)
+    if q == 9:
+        shape, vax = (1, nvert, nx), 1
+        kw = dict(q=9, nx=nx, ny=nvert, nz=1)
+    else:
+        shape, vax = (nvert, 3, nx), 0
+        kw = dict(q=19, nx=nx, ny=3, nz=nvert)
+    dim = 2 if q == 9 else 3
+    a = 0.5 + rng.random(shape)
+    a += 0.3 * np.sin(np.arange(nvert) / 3.0).reshape([-1 if i == vax else 1 for i in range(3)])
+    u = 0.05 * (rng.random((dim,) + shape) - 0.5)
+    s = rng.random(shape) if vs_s else None
+    walled = OracleConfig(frozen=True, scheme_c=scheme, vs=vs, kappa_c=kappa, weno_eps=1e-6,
+                          has_s=vs_s != 0.0, vs_s=vs_s, **kw)
+    kw_p = dict(kw)
+    if q == 9:
+        kw_p["ny"] = 2 * nvert
+    else:
+        kw_p["nz"] = 2 * nvert
+    periodic = OracleConfig(frozen=True, scheme_c=scheme, vs=0.0, kappa_c=kappa, weno_eps=1e-6,
+                            vert_periodic=True, **kw_p)
+    settle = vs if not vs_s else vs * (1.0 - vs_s * s)
+    return walled, periodic, a, u, s, settle, vax, dim
+
+
+def _image(a, u, settle, vax, dim, rule="paper"):
+    """The periodic run's fields: the reflected run (image) below the run."""
+    flip = lambda x: np.flip(x, axis=vax)
+    uv = u[dim - 1]
+    phys_w = uv - settle
+    if rule == "paper":
+        img_a, img_w = flip(a), flip(-uv - settle)
+    elif rule == "settling_reversed":
+        img_a, img_w = flip(a), flip(-(uv - settle))
+    elif rule == "c_odd":
+        img_a, img_w = flip(-a), flip(-uv - settle)
+    elif rule == "fluid_even":
+        img_a, img_w = flip(a), flip(uv - settle)
+    else:
+        raise ValueError(rule)
+    ap = np.ascontiguousarray(np.concatenate([img_a, a], axis=vax))
+    up = np.empty((dim,) + ap.shape)
+    for d in range(dim - 1):
+        up[d] = np.concatenate([flip(u[d]), u[d]], axis=vax)
+    up[dim - 1] = np.concatenate([img_w, phys_w], axis=vax)
+    return ap, up
+
+
+def _upper(x, vax, n):
+    """the physical half of a periodic field (the last n planes)"""
+    return np.take(x, np.arange(n, 2 * n), axis=vax)
+
+
+@pytest.mark.parametrize("q,nx", [(9, 7), (19, 5)])
+@pytest.mark.parametrize("scheme", ["weno5", "weno3", "upwind1"])
+@pytest.mark.parametrize("vs_s", [0.0, 0.4])
+def test_wall_ghosts_mirror_image(q, nx, scheme, vs_s):
+    n = 12
+    walled, periodic, a, u, s, settle, vax, dim = _mirror_case(q, nx, n, scheme, 0.02, 3e-3,
+                                                               vs_s, seed=17 + q)
+    phi_w, bot_w = oracle.faces_c(walled, a, u, s)
+    ap, up = _image(a, u, settle, vax, dim)
+    phi_p, _ = oracle.faces_c(periodic, ap, up)
+    for d in range(dim):
+        pw, pp = phi_w[d], _upper(phi_p[d], vax, n)
+        if d == dim - 1:
+            # the top node's +face is the top wall: no flux in the walled run
+            top = [slice(None)] * 3
+            top[vax] = slice(n - 1, n)
+            assert np.all(pw[tuple(top)] == 0.0)
+            keep = [slice(None)] * 3
+            keep[vax] = slice(0, n - 1)
+            pw, pp = pw[tuple(keep)], pp[tuple(keep)]
+        np.testing.assert_array_equal(pw, pp)
+    # the bottom wall face carries the absorbed settling flux -Vs a_0
+    bottom = [slice(None)] * 3
+    bottom[vax] = 0
+    a0 = a[tuple(bottom)]
+    vs0 = settle if np.isscalar(settle) else settle[tuple(bottom)]
+    np.testing.assert_array_equal(bot_w, (-vs0 * a0).ravel())
+    if vs_s == 0.0:
+        # the operator itself: every cell off the walls agrees bit for bit
+        L_w, _ = oracle.rhs_c(walled, a, u)
+        L_p, _ = oracle.rhs_c(periodic, ap, up)
+        inner = [slice(None)] * 3
+        inner[vax] = slice(1, n - 1)
+        np.testing.assert_array_equal(L_w[tuple(inner)], _upper(L_p, vax, n)[tuple(inner)])
+
+
+@pytest.mark.parametrize("q,nx", [(9, 7), (19, 5)])
+@pytest.mark.parametrize("scheme", ["weno5", "weno3"])
+@pytest.mark.parametrize("rule", ["settling_reversed", "c_odd", "fluid_even"])
+def test_wall_ghosts_mirror_image_rejects_other_rules(q, nx, scheme, rule):
+    n = 12
+    walled, periodic, a, u, s, settle, vax, dim = _mirror_case(q, nx, n, scheme, 0.02, 3e-3,
+                                                               0.0, seed=29 + q)
+    phi_w, _ = oracle.faces_c(walled, a, u)
+    ap, up = _image(a, u, settle, vax, dim, rule)
+    phi_p, _ = oracle.faces_c(periodic, ap, up)
+    v = dim - 1
+    keep = [slice(None)] * 3
+    keep[vax] = slice(0, n - 1)
+    diff = np.abs(phi_w[v][tuple(keep)] - _upper(phi_p[v], vax, n)[tuple(keep)])
+    assert diff.max() > 1e-6 * np.abs(phi_w[v]).max()
