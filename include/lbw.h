@@ -46,8 +46,10 @@
  * lbw_import, which present the canonical pre-collision layout f_i(x, t).
  *
  * Ownership.  Every device buffer belongs to the caller and must outlive the
- * handle.  The library allocates no device memory and never synchronises the
- * stream except in lbw_reduce.  Calls on one handle must not overlap.
+ * handle.  The library allocates no device memory (its one device array, the
+ * fixed scratch of lbw_reduce_static, is part of its code object) and never
+ * synchronises the stream except in the reductions.  Calls on one handle
+ * must not overlap.
  *
  * Errors.  Every int-returning function returns LBW_OK (0) or a negative
  * LBW_ERR_* code; lbw_last_error() then describes the failure (thread-local
@@ -268,6 +270,21 @@ int lbw_replay(lbw_handle *h, int32_t run, int32_t n, void *const *c_out, void *
  * the result is bitwise reproducible.  Synchronises the stream.  Returns
  * LBW_ERR_NONFINITE if any sum is NaN or Inf (the values are still written). */
 int lbw_reduce(lbw_handle *h, int32_t what, double *out_host);
+
+/* lbw_reduce for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid allocation): the
+ * same sums, bit for bit, with the partial sums kept in a device array the
+ * library holds itself instead of the scratch passed at creation, which may
+ * then be NULL.  That array is static: 128 * 256 + 128 doubles (263,168
+ * bytes) on every device the library runs on, held until the process ends,
+ * enough for batches of up to 128 runs (LBW_ERR_INVAL beyond).  The call
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine).
+ * All calls on one device share that device's array and leave their partial
+ * sums in it; each call writes every value it reads, so no clearing is
+ * needed, but calls that overlap on one device (other threads, other
+ * handles) race and must be serialised by the caller.  Synchronises the
+ * stream; LBW_ERR_NONFINITE as lbw_reduce. */
+int lbw_reduce_static(lbw_handle *h, int32_t what, double *out_host);
 
 /* The sums of lbw_reduce for one particle size class, per run, into
  * out_host[nbatch]: LBW_MASS_C (sum of C_cls) or LBW_DEPOSIT (the class's

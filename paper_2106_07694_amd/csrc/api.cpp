@@ -9,6 +9,7 @@
 #include <cstring>
 #include <string>
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "lbw_internal.h"
@@ -848,23 +849,57 @@ int lbw_import(lbw_handle *h, int32_t run, int32_t field, const void *src) {
     return e == hipSuccess ? LBW_OK : hip_fail(e, "import");
 }
 
+// Device scratch of the no-allocation reduction (lbw_reduce_static): the
+// per-block partial sums and the per-run results of up to kStaticRuns runs,
+// laid out as in the caller's scratch (partials run after run, then the
+// sums).  Each device holds its own copy; host code reaches it only through
+// the address hipGetSymbolAddress returns for the device (the array's name
+// is a host-side stand-in, not a device address).
+constexpr int kStaticRuns = 128;
+constexpr size_t kStaticDoubles = (size_t)kStaticRuns * lbw::kReduceBlocks + kStaticRuns;
+static __device__ __align__(256) double scratch[kStaticDoubles];
+
 namespace {
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[kMaxDevices] = {};
+
+// Address of `scratch` on the device the handle's stream runs on, looked up
+// once per device with that device current.
+int static_scratch(const lbw_handle *h, double **out) {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    int dev = cur;
+    if (h->stream) {
+        e = hipStreamGetDevice(h->stream, &dev);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamGetDevice");
+    }
+    if (dev < 0 || dev >= kMaxDevices) return fail(LBW_ERR_UNSUPPORTED, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        if (dev != cur && (e = hipSetDevice(dev)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (dev != cur) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_dev[dev] = (double *)p;
+    }
+    *out = g_scratch_dev[dev];
+    return LBW_OK;
+}
+
 // The sums of lbw_reduce, over the cells below a horizontal plane of each run
-// (plane >= 0) or over all cells (-1).
-int reduce_impl(lbw_handle *h, int32_t what, double *out_host, int plane, int cls = -1) {
-    size_t need = 0;
-    lbw_scratch_bytes(h->cfg.data(), h->nbatch, &need);
-    const lbw_buffers &b0 = h->buf[0];
-    if (!b0.scratch || b0.scratch_bytes < need)
-        return fail(LBW_ERR_INVAL, "scratch of run 0 must hold %zu bytes", need);
-    double *scratch = (double *)b0.scratch;
+// (plane >= 0) or over all cells (-1), with the partials in `part`
+// (nbatch * kReduceBlocks values, then the nbatch sums).
+int reduce_on(lbw_handle *h, int32_t what, double *out_host, int plane, int cls, double *part) {
     std::vector<lbw::RunDev> cur(h->nbatch);
     for (int b = 0; b < h->nbatch; ++b) cur[b] = current(h, b);
     hipError_t e = lbw::launch_reduce(h->q, h->precision, cur.data(), h->nbatch, what, h->odd,
-                                      scratch, h->stream, plane, cls);
+                                      part, h->stream, plane, cls);
     if (e != hipSuccess) return hip_fail(e, "reduce launch");
-    e = hipMemcpyAsync(out_host, (char *)b0.scratch + scratch_layout(h->nbatch, 0).out,
+    e = hipMemcpyAsync(out_host, part + (size_t)h->nbatch * lbw::kReduceBlocks,
                        sizeof(double) * h->nbatch, hipMemcpyDeviceToHost, h->stream);
     if (e != hipSuccess) return hip_fail(e, "reduce copy");
     e = hipStreamSynchronize(h->stream);
@@ -874,15 +909,43 @@ int reduce_impl(lbw_handle *h, int32_t what, double *out_host, int plane, int cl
     return LBW_OK;
 }
 
-}  // namespace
+// The same over the caller's scratch (run 0's buffers).
+int reduce_impl(lbw_handle *h, int32_t what, double *out_host, int plane, int cls = -1) {
+    size_t need = 0;
+    lbw_scratch_bytes(h->cfg.data(), h->nbatch, &need);
+    const lbw_buffers &b0 = h->buf[0];
+    if (!b0.scratch || b0.scratch_bytes < need)
+        return fail(LBW_ERR_INVAL, "scratch of run 0 must hold %zu bytes", need);
+    return reduce_on(h, what, out_host, plane, cls, (double *)b0.scratch);
+}
 
-int lbw_reduce(lbw_handle *h, int32_t what, double *out_host) {
+int check_reduce(const lbw_handle *h, int32_t what, const double *out_host) {
     if (!h || !out_host) return fail(LBW_ERR_INVAL, "NULL argument");
     if (what < LBW_MASS_C || what > LBW_DEPOSIT) return fail(LBW_ERR_INVAL, "unknown reduction %d", what);
     if (what == LBW_MASS_S && !h->has_s) return fail(LBW_ERR_INVAL, "run has no S");
     if (what == LBW_MASS_FLUID && h->fluid_mode != LBW_FLUID_LBM)
         return fail(LBW_ERR_INVAL, "frozen fluid has no populations");
-    return reduce_impl(h, what, out_host, -1);
+    return LBW_OK;
+}
+
+}  // namespace
+
+int lbw_reduce(lbw_handle *h, int32_t what, double *out_host) {
+    const int rc = check_reduce(h, what, out_host);
+    return rc ? rc : reduce_impl(h, what, out_host, -1);
+}
+
+int lbw_reduce_static(lbw_handle *h, int32_t what, double *out_host) {
+    int rc = check_reduce(h, what, out_host);
+    if (rc) return rc;
+    if (h->nbatch > kStaticRuns)
+        return fail(LBW_ERR_INVAL, "lbw_reduce_static handles at most %d runs (got %d)", kStaticRuns,
+                    h->nbatch);
+    double *p = nullptr;
+    if ((rc = static_scratch(h, &p))) return rc;
+    // every partial and every sum is written before it is read, so nothing
+    // left from an earlier call needs clearing
+    return reduce_on(h, what, out_host, -1, -1, p);
 }
 
 int lbw_reduce_class(lbw_handle *h, int32_t what, int32_t cls, double *out_host) {

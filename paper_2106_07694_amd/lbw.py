@@ -31,7 +31,8 @@ EXPORTED = ("lbw_version", "lbw_last_error", "lbw_scratch_bytes", "lbw_create", 
             "lbw_set_launch", "lbw_get_launch", "lbw_init_equilibrium", "lbw_step",
             "lbw_steps_done", "lbw_export", "lbw_import", "lbw_rebind", "lbw_reduce", "lbw_timing_begin",
             "lbw_timing_end", "lbw_adjoint_work_bytes", "lbw_adjoint_step", "lbw_mass_below",
-            "lbw_front_height", "lbw_front_psd", "lbw_reduce_class", "lbw_replay")
+            "lbw_front_height", "lbw_front_psd", "lbw_reduce_class", "lbw_replay",
+            "lbw_reduce_static")
 
 
 class LbwError(RuntimeError):
@@ -105,6 +106,7 @@ def load() -> ctypes.CDLL:
     lib.lbw_rebind.argtypes = [P, I32, I32, P]
     lib.lbw_replay.argtypes = [P, I32, I32, P, P, P, P, P]
     lib.lbw_reduce.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double)]
+    lib.lbw_reduce_static.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double)]
     lib.lbw_mass_below.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double)]
     lib.lbw_reduce_class.argtypes = [P, I32, I32, ctypes.POINTER(ctypes.c_double)]
     lib.lbw_front_height.argtypes = [P, I32, ctypes.c_double, P]
@@ -222,7 +224,7 @@ class RunConfig:
 class Solver:
     """A batch of runs bound to torch-owned device buffers and a HIP stream."""
 
-    def __init__(self, cfgs, device="cuda", stream=None):
+    def __init__(self, cfgs, device="cuda", stream=None, scratch=True):
         import torch
 
         if not torch.cuda.is_available():
@@ -240,6 +242,10 @@ class Solver:
         self._ccfg = (CConfig * self.nbatch)(*[c.to_c() for c in self.cfgs])
         nbytes = ctypes.c_size_t(0)
         check(lib.lbw_scratch_bytes(self._ccfg, self.nbatch, ctypes.byref(nbytes)))
+        if not scratch:
+            if self.nbatch > 1:
+                raise ValueError("a batch needs its scratch (work lists)")
+            nbytes = ctypes.c_size_t(0)
         self.tensors = []
         cbufs = []
         torch.cuda.current_stream(self.device).synchronize()
@@ -264,7 +270,8 @@ class Solver:
                 "s_tmp": z(*c.shape) if c.has_s else None,
                 "u": z(c.dim, *c.shape),
                 "deposit": z(*c.deposit_shape, dt=torch.float64),
-                "scratch": z((scratch_bytes + 7) // 8, dt=torch.float64) if i == 0 else None,
+                "scratch": (z((scratch_bytes + 7) // 8, dt=torch.float64)
+                            if i == 0 and scratch_bytes else None),
             }
             self.tensors.append(t)
             b = CBuffers()
@@ -384,6 +391,13 @@ class Solver:
     def reduce(self, what) -> np.ndarray:
         out = (ctypes.c_double * self.nbatch)()
         check(self._lib.lbw_reduce(self._h, int(what), out))
+        return np.array(out[:], dtype=np.float64)
+
+    def reduce_static(self, what) -> np.ndarray:
+        """The sums of reduce(), computed through the library's own static
+        device scratch (lbw_reduce_static: no caller scratch needed)."""
+        out = (ctypes.c_double * self.nbatch)()
+        check(self._lib.lbw_reduce_static(self._h, int(what), out))
         return np.array(out[:], dtype=np.float64)
 
     def reduce_class(self, what, cls: int) -> np.ndarray:
