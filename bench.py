@@ -37,19 +37,29 @@ def _alg_bytes(wl) -> dict:
     (each particle size class is a transported scalar).
     collide_stream kernel: read + write every population, read the scalars
     that set the buoyancy force.
-    """
+    transport (the three RK stages, per step): stage 1 reads C and the
+    velocity and writes a1; stages 2 and 3 also read C; each reads its input
+    stage and writes one value (the S update adds S read and written)."""
     s = 4 if wl.precision == "fp32_shifted" else 8
     nsc = max(1, wl.n_classes) + (1 if wl.has_s else 0)
+    ncls = max(1, wl.n_classes)
+    u = wl.dim * s
+    stages = ncls * ((2 * s + u) + 2 * (3 * s + u)) + (2 * s if wl.has_s else 0)
     return {"step": 2 * wl.q * s + 2 * nsc * s,
-            "collide_stream": 2 * wl.q * s + nsc * s}
+            "collide_stream": 2 * wl.q * s + nsc * s,
+            "transport": stages}
 
 
-def _kernel_hash() -> str:
-    """Hash of what the collide-stream kernel is built from: its two source
-    files and the run descriptor it reads (the RunDev struct)."""
+_SOURCES = {"collide_stream": ("lbm.hip", "lbm_device.h"),
+            "transport": ("transport_tiled.h", "transport_tiled.hip", "transport_device.h")}
+
+
+def _kernel_hash(kind: str = "collide_stream") -> str:
+    """Hash of what a phase's kernels are built from: their source files and
+    the run descriptor they read (the RunDev struct)."""
     csrc = os.path.join(ROOT, "paper_2106_07694_amd", "csrc")
     h = hashlib.sha256()
-    for name in ("lbm.hip", "lbm_device.h"):
+    for name in _SOURCES[kind]:
         with open(os.path.join(csrc, name), "rb") as fh:
             h.update(fh.read())
     with open(os.path.join(csrc, "lbw_internal.h")) as fh:
@@ -60,17 +70,75 @@ def _kernel_hash() -> str:
 
 
 def _traffic(wl_name: str, kernel: str):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they
-    were taken on the current kernel source; else None."""
+    """HBM bytes per launch (collide_stream: the mean of the two kernels of
+    the in-place pair) or per step (transport: its three stages) from
+    committed rocprofv3 counter runs, if they were taken on the current
+    kernel source; else None."""
     try:
         with open(PROFILE_COUNTERS) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
     e = d.get(wl_name, {}).get(kernel)
-    if not e or e.get("source_hash") != _kernel_hash():
+    if not e or e.get("source_hash") != _kernel_hash(kernel):
         return None
     return e.get("bytes_per_launch")
+
+
+def ingest_counters(fetch_csv: str, write_csv: str, workload: str, cells: int,
+                    copy_bytes: int = 256 << 20) -> dict:
+    """Turn two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; CSV output
+    of the same bench command) into per-kernel HBM bytes, each counter scaled
+    by what it reads for the known-size copy kernel of that run, and store
+    them in profiles/hbm_traffic.json under `workload` with the current
+    source hashes."""
+    import csv
+    from collections import defaultdict
+
+    def per_kernel(path, counter):
+        vals = defaultdict(list)
+        with open(path) as fh:
+            for row in csv.DictReader(fh):
+                if row.get("Counter_Name") != counter:
+                    continue
+                vals[row["Kernel_Name"]].append(float(row["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in vals.items()}, {k: len(v) for k, v in vals.items()}
+
+    fetch, n_f = per_kernel(fetch_csv, "FETCH_SIZE")
+    write, _ = per_kernel(write_csv, "WRITE_SIZE")
+    copy = [k for k in fetch if "AUnaryFunctor" in k or "MulFunctor" in k]
+    if not copy:
+        raise ValueError("the copy kernel (torch.mul of a 256 MiB tensor) is not in the counter runs")
+    fs = copy_bytes / 1024.0 / fetch[copy[0]]
+    ws = copy_bytes / 1024.0 / write[copy[0]]
+    kernels = {}
+    for k in fetch:
+        if k in copy or k not in write:
+            continue
+        short = k.replace("void lbw::(anonymous namespace)::", "").split("(")[0]
+        fb, wb = fetch[k] * 1024.0 * fs, write[k] * 1024.0 * ws
+        kernels[short] = {"fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb,
+                          "bytes_per_cell": (fb + wb) / cells, "launches": n_f[k]}
+    entry = {"_calibration": {"kernel": "torch.mul(src, 1.0, out=dst), 256 MiB float32 each way",
+                              "fetch_kib_read": fetch[copy[0]], "write_kib_read": write[copy[0]],
+                              "fetch_scale": fs, "write_scale": ws},
+             "kernels": kernels}
+    cs = [v["bytes_per_launch"] for k, v in kernels.items() if k.startswith("k_collide_stream<")]
+    if cs:
+        entry["collide_stream"] = {"source_hash": _kernel_hash("collide_stream"),
+                                   "bytes_per_launch": sum(cs) / len(cs)}
+    st = [v["bytes_per_launch"] for k, v in kernels.items() if k.startswith("k_stage_tiled<")]
+    if len(st) == 3:
+        entry["transport"] = {"source_hash": _kernel_hash("transport"), "bytes_per_launch": sum(st)}
+    try:
+        with open(PROFILE_COUNTERS) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        d = {}
+    d[workload] = entry
+    with open(PROFILE_COUNTERS, "w") as fh:
+        json.dump(d, fh, indent=1, sort_keys=True)
+    return entry
 
 
 def run_gpu(wl, steps: int, warmup: int, diagnostics: bool = True, tuned_as=None) -> dict:
@@ -115,20 +183,38 @@ def run_gpu(wl, steps: int, warmup: int, diagnostics: bool = True, tuned_as=None
     sol.close()
     cells = wl.cells
     ab = _alg_bytes(wl)
-    avg_cs_s = phases["collide_stream_ms"] / max(phases["steps"], 1) * 1e-3
-    achieved = cells * ab["collide_stream"] / avg_cs_s / 1e9
-    traffic = _traffic(wl.name, "collide_stream")
+    nst = max(phases["steps"], 1)
+    cs_ms = phases["collide_stream_ms"] / nst
+    tr_ms = phases["transport_ms"] / nst
+    step_ms = ms / steps
+    cs_gbs = cells * ab["collide_stream"] / (cs_ms * 1e-3) / 1e9
+    tr_gbs = cells * ab["transport"] / (tr_ms * 1e-3) / 1e9
+    step_gbs = cells * ab["step"] / (step_ms * 1e-3) / 1e9
+    cs_traffic = _traffic(wl.name, "collide_stream")
+    tr_traffic = _traffic(wl.name, "transport")
+    step_traffic = (cs_traffic + tr_traffic) if cs_traffic and tr_traffic else None
     return {
         "mlups": cells * steps / (ms * 1e-3) / 1e6,
-        "ms_per_step": ms / steps,
+        "ms_per_step": step_ms,
         "ms_per_step_with_phase_events": ms_instr / steps,
-        "phase_ms_per_step": {"collide_stream": phases["collide_stream_ms"] / max(phases["steps"], 1),
-                              "transport": phases["transport_ms"] / max(phases["steps"], 1)},
-        "step_alg_gbs": cells * ab["step"] * steps / (ms * 1e-3) / 1e9,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "collide_stream", "alg_bytes_per_cell": ab["collide_stream"],
-                     "cells_per_launch": cells},
+        "phase_ms_per_step": {"collide_stream": cs_ms, "transport": tr_ms},
+        "step_alg_gbs": step_gbs,
+        # the coupled step against the HBM roofline: the method's algorithmic
+        # bytes per cell update over the measured time per step; the phases
+        # below it (HIP events around their launches in the second pass)
+        "roofline": {"bound": "hbm", "scope": "coupled step", "achieved": step_gbs,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": step_gbs / HBM_PEAK_GBS,
+                     "traffic": step_traffic, "alg_bytes_per_cell": ab["step"],
+                     "cells_per_step": cells,
+                     "kernels": {
+                         "collide_stream": {
+                             "bound": "hbm", "achieved": cs_gbs, "frac": cs_gbs / HBM_PEAK_GBS,
+                             "ms": cs_ms, "alg_bytes_per_cell": ab["collide_stream"],
+                             "traffic": cs_traffic, "cells_per_launch": cells},
+                         "transport": {
+                             "bound": "valu (close to vector-issue bound)", "achieved": tr_gbs,
+                             "frac": tr_gbs / HBM_PEAK_GBS, "ms": tr_ms, "launches": 3,
+                             "alg_bytes_per_cell": ab["transport"], "traffic": tr_traffic}}},
         "particle_budget": mass,
         "diagnostics": diag,
     }
@@ -216,26 +302,37 @@ def run_sweep(steps: int, warmup: int) -> dict:
     ms_batched = start.elapsed_time(stop)
     sol.close()
     del sol
-    # one at a time: each run's own solver and launches, same stream
-    singles = []
-    for w, c in zip(runs, cfgs):
-        one = lbw.Solver(c, stream=side)
-        one.setup_workload(w)
-        one.step(2)
-        singles.append(one)
-    torch.cuda.synchronize()
-    start.record(side)
-    for one in singles:
-        one.step(steps)
-    stop.record(side)
-    torch.cuda.synchronize()
-    ms_seq = start.elapsed_time(stop)
-    for one in singles:
-        one.close()
+    # one at a time: each run's own solver with the sweep's tuned launch
+    # shape, same stream; once with a host launch per kernel and once
+    # replaying each run's two-step HIP graph
+    def sequential(graph: int) -> float:
+        singles = []
+        for w, c in zip(runs, cfgs):
+            one = lbw.Solver(c, stream=side)
+            one.set_launch(**dict(launch, graph=graph))
+            one.setup_workload(w)
+            one.step(2)
+            singles.append(one)
+        torch.cuda.synchronize()
+        start.record(side)
+        for one in singles:
+            one.step(steps)
+        stop.record(side)
+        torch.cuda.synchronize()
+        t = start.elapsed_time(stop)
+        for one in singles:
+            one.close()
+        return t
+
+    ms_seq = sequential(0)
+    ms_seq_graph = sequential(1)
     return {"workload": "sweep_64_uneven_2d_fp32", "runs": len(runs), "cells": cells,
             "steps": steps, "batched_mlups": cells * steps / (ms_batched * 1e-3) / 1e6,
             "sequential_mlups": cells * steps / (ms_seq * 1e-3) / 1e6,
-            "speedup": ms_seq / ms_batched, "launch": launch}
+            "sequential_graph_mlups": cells * steps / (ms_seq_graph * 1e-3) / 1e6,
+            "speedup": ms_seq / ms_batched,
+            "speedup_vs_graph_replayed_sequential": ms_seq_graph / ms_batched,
+            "launch": launch}
 
 
 def run_precision(nsteps: int, marks=(1000, 5000, 10000, 20000), wl=None) -> dict:
@@ -282,6 +379,43 @@ def run_precision(nsteps: int, marks=(1000, 5000, 10000, 20000), wl=None) -> dic
             "deposited_mass_fp64": b["deposited"], "deposited_mass_fp32": a["deposited"],
             "deposited_mass_abs_diff": abs(a["deposited"] - b["deposited"])}
     return out
+
+
+def run_precision_oracle(nsteps: int, wl=None) -> dict:
+    """Form (1) and the plain FP64 step against the FP64 oracle itself: the
+    2D two-scalar workload (full grid) advanced nsteps from the same seeded
+    state on the GPU (FP32 shifted and FP64) and by the oracle on the host;
+    relative L2 differences of u, C, S and the per-column deposit."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_2106_07694_amd import autotune, lbw, workloads as W
+
+    wl = wl or W.C2
+    gpu = {}
+    for prec in ("fp64", "fp32_shifted"):
+        cfg = lbw.RunConfig.from_workload(wl.replace(precision=prec))
+        sol = lbw.Solver(cfg)
+        tuned = autotune.lookup(wl.name)
+        if tuned:
+            sol.set_launch(**tuned)
+        sol.setup_workload(wl)
+        sol.step(nsteps)
+        torch.cuda.synchronize()
+        gpu[prec] = {k: sol.field(k).double().cpu().numpy() for k in ("u", "c", "s", "deposit")}
+        sol.close()
+    ocfg = oracle.OracleConfig(q=wl.q, nx=wl.nx, ny=wl.ny, nz=wl.nz, tau=wl.tau, vs=wl.vs,
+                               kappa_c=wl.kappa_c, gp_c=wl.gp_c, has_s=wl.has_s,
+                               kappa_s=wl.kappa_s, gp_s=wl.gp_s)
+    c, s = W.initial_scalars(wl)
+    t0 = time.perf_counter()
+    _, oc, os_, od, ou = oracle.run(ocfg, oracle.equilibrium(ocfg), c, s, nsteps=nsteps, want_u=True)
+    dt = time.perf_counter() - t0
+    ref = {"u": ou, "c": oc, "s": os_, "deposit": od}
+    rel = lambda a, b: float(np.linalg.norm(a.ravel() - b.ravel()) / max(np.linalg.norm(b), 1e-300))
+    return {"workload": wl.name, "reference": "FP64 oracle (host)", "steps": nsteps,
+            "oracle_s": dt,
+            "l2_rel": {prec: {k: rel(gpu[prec][k], ref[k]) for k in ref} for prec in gpu}}
 
 
 def run_adjoint(nsteps: int) -> dict:
@@ -355,12 +489,29 @@ def calibrate_copy(mib: int = 256, reps: int = 10) -> dict:
             "gbs": 2 * n * 4 / (ms * 1e-3) / 1e9}
 
 
-def cpu_baseline(wl, nz_crop: int, ny_crop: int, steps: int) -> dict:
+def cpu_baseline(wl, nz_crop: int, ny_crop: int, steps: int, one_thread=None) -> dict:
     """The FP64 oracle as it stands, timed on the host cores on a crop of
-    the workload (vertical extent cut), reported as MLUPS."""
+    the workload (vertical extent cut), reported as MLUPS.  one_thread =
+    (nz_crop, ny_crop, steps): also time it on one thread, in a child
+    process started with OMP_NUM_THREADS=1 (the thread count of the
+    oracle's OpenMP runtime is fixed when it starts)."""
     import oracle
     from paper_2106_07694_amd import workloads as W
 
+    out1 = None
+    if one_thread:
+        import subprocess
+        code = ("import json, sys; sys.path.insert(0, %r); import bench; "
+                "from paper_2106_07694_amd import workloads as W; "
+                "print(json.dumps(bench.cpu_baseline(W.%s, %d, %d, %d)))"
+                % (ROOT, wl_var(wl), *one_thread))
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                           timeout=600)
+        if r.returncode == 0:
+            out1 = json.loads(r.stdout.strip().splitlines()[-1])
+        else:
+            out1 = {"error": r.stderr[-400:]}
     sample = wl.replace(nz=nz_crop) if wl.dim == 3 else wl.replace(ny=ny_crop)
     ocfg = oracle.OracleConfig(q=sample.q, nx=sample.nx, ny=sample.ny, nz=sample.nz,
                                shifted=True, tau=sample.tau, vs=sample.vs,
@@ -372,10 +523,22 @@ def cpu_baseline(wl, nz_crop: int, ny_crop: int, steps: int) -> dict:
     oracle.run(ocfg, f, c, s, nsteps=steps)
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
-    return {"value": sample.cells * steps / dt / 1e6, "unit": "MLUPS", "cores": cores,
-            "kind": "oracle",
-            "sample": f"{steps} FP64 oracle steps on a {sample.nx}x{sample.ny}x{sample.nz} crop "
-                      f"of the workload ({dt:.1f} s)"}
+    res = {"value": sample.cells * steps / dt / 1e6, "unit": "MLUPS", "cores": cores,
+           "kind": "oracle",
+           "sample": f"{steps} FP64 oracle steps on a {sample.nx}x{sample.ny}x{sample.nz} crop "
+                     f"of the workload ({dt:.1f} s)"}
+    if out1 is not None:
+        res["one_thread"] = out1
+    return res
+
+
+def wl_var(wl) -> str:
+    """Name of the workloads-module variable holding wl."""
+    from paper_2106_07694_amd import workloads as W
+    for k, v in vars(W).items():
+        if v is wl:
+            return k
+    raise KeyError(wl.name)
 
 
 def main() -> int:
@@ -396,15 +559,28 @@ def main() -> int:
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the FP32-vs-FP64 error report of the 2D workload")
     ap.add_argument("--precision-steps", type=int, default=20000)
-    ap.add_argument("--precision-3d", type=int, default=0, metavar="STEPS",
-                    help="also compare FP32 against FP64 on the 3D workload over STEPS steps "
-                         "(reported under fp32_vs_fp64_3d; off by default)")
+    ap.add_argument("--precision-3d", type=int, default=2000, metavar="STEPS",
+                    help="compare FP32 against FP64 on the 3D workload over STEPS steps "
+                         "(reported under fp32_vs_fp64_3d; 0 skips it)")
+    ap.add_argument("--precision-oracle", type=int, default=0, metavar="STEPS",
+                    help="also compare the 2D two-scalar workload's FP32 and FP64 runs with the "
+                         "FP64 oracle after STEPS steps (full grid; the oracle takes about 0.1 s "
+                         "per step on 16 cores; reported under fp32_vs_oracle; off by default)")
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="store per-kernel HBM bytes from two rocprofv3 --pmc runs of this "
+                         "command (FETCH_SIZE, WRITE_SIZE) in profiles/hbm_traffic.json and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run the known-size copy kernel (profiler counter calibration); it runs "
                          "by default unless --no-copy")
     ap.add_argument("--no-copy", action="store_true",
                     help="skip the copy kernel that measures the achievable bandwidth")
     args = ap.parse_args()
+    if args.ingest_counters:
+        from paper_2106_07694_amd import workloads as W
+        wl = W.C3 if args.workload == "3d" else W.C2
+        e = ingest_counters(*args.ingest_counters, workload=wl.name, cells=wl.cells)
+        print(json.dumps({k: v for k, v in e.items() if k != "kernels"}))
+        return 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the library has no multi-GPU path "
               f"(asked for --gpus {args.gpus}).", file=sys.stderr)
@@ -439,8 +615,9 @@ def main() -> int:
     if not args.no_sweep:
         sweep = run_sweep(min(args.steps, 200), 4)
         print(f"[bench] sweep: batched {sweep['batched_mlups']:.0f} MLUPS, one at a time "
-              f"{sweep['sequential_mlups']:.0f} MLUPS ({sweep['speedup']:.1f}x)", file=sys.stderr,
-              flush=True)
+              f"{sweep['sequential_mlups']:.0f} MLUPS ({sweep['speedup']:.1f}x), one at a time "
+              f"with graph replay {sweep['sequential_graph_mlups']:.0f} MLUPS "
+              f"({sweep['speedup_vs_graph_replayed_sequential']:.1f}x)", file=sys.stderr, flush=True)
     adj = None
     if not args.no_adjoint:
         adj = run_adjoint(args.adjoint_steps)
@@ -468,6 +645,11 @@ def main() -> int:
         last = prec["l2_rel"][str(prec["steps"][-1])]
         print(f"[bench] fp32 vs fp64 after {prec['steps'][-1]} steps: u {last['u']:.2e}, "
               f"C {last['c']:.2e}, deposit {last['deposit']:.2e}", file=sys.stderr, flush=True)
+    prec_orc = None
+    if args.precision_oracle > 0:
+        prec_orc = run_precision_oracle(args.precision_oracle)
+        print(f"[bench] fp32/fp64 vs oracle after {args.precision_oracle} steps: "
+              f"{json.dumps(prec_orc['l2_rel'])}", file=sys.stderr, flush=True)
     prec3 = None
     if args.precision_3d > 0:
         prec3 = run_precision(args.precision_3d, marks=(500, 1000, 2000), wl=W.C3)
@@ -480,11 +662,16 @@ def main() -> int:
         # this device (the roofline's peak stays the vendor figure)
         res["roofline"]["copy_gbs"] = copy["gbs"]
         res["roofline"]["frac_of_copy"] = res["roofline"]["achieved"] / copy["gbs"]
+        cs = res["roofline"]["kernels"]["collide_stream"]
+        cs["frac_of_copy"] = cs["achieved"] / copy["gbs"]
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = (cpu_baseline(main_wl, nz_crop=128, ny_crop=0, steps=20) if main_wl.dim == 3
-               else cpu_baseline(main_wl, nz_crop=0, ny_crop=2048, steps=40))
-        print(f"[bench] cpu baseline: {cpu['value']:.2f} MLUPS on {cpu['cores']} cores",
+        cpu = (cpu_baseline(main_wl, nz_crop=128, ny_crop=0, steps=20, one_thread=(32, 0, 4))
+               if main_wl.dim == 3
+               else cpu_baseline(main_wl, nz_crop=0, ny_crop=2048, steps=40,
+                                 one_thread=(0, 256, 8)))
+        print(f"[bench] cpu baseline: {cpu['value']:.2f} MLUPS on {cpu['cores']} cores, "
+              f"{cpu.get('one_thread', {}).get('value', float('nan')):.2f} MLUPS on one",
               file=sys.stderr, flush=True)
     line = {
         "metric": METRIC,
@@ -509,7 +696,6 @@ def main() -> int:
         "ms_per_step_with_phase_events": res["ms_per_step_with_phase_events"],
         "phase_ms_per_step": res["phase_ms_per_step"],
         "step_alg_gbs": res["step_alg_gbs"],
-        "step_alg_frac": res["step_alg_gbs"] / HBM_PEAK_GBS,
         "roofline": res["roofline"],
         "diagnostics": res["diagnostics"],
         "cpu_baseline": cpu,
@@ -518,6 +704,7 @@ def main() -> int:
         "adjoint": adj,
         "fp32_vs_fp64": prec,
         "fp32_vs_fp64_3d": prec3,
+        "fp32_vs_oracle": prec_orc,
         "size_classes": poly,
         "full_force": full,
         "copy_calibration": copy,

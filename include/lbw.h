@@ -150,17 +150,11 @@ typedef struct {
     int32_t tile_y;        /* transport chunk: vertical planes per block */
     int32_t variant;       /* 0 tiled transport (LDS, marching) after the
                               collide-stream kernel; 1 plain transport (one
-                              thread per node, no LDS); 2 pipelined: the
-                              vertical axis is cut into slabs and the
-                              collide-stream of step n+1 on a slab runs on a
-                              second stream, overlapping the transport of step
-                              n on the slabs above it (single run with walls,
-                              one size class and a constant settling speed;
-                              other runs take variant 0) */
+                              thread per node, no LDS) */
     int32_t graph;         /* 1: lbw_step replays a captured HIP graph of two
                               steps (needs a non-null stream; the graph is
                               runtime-owned and rebuilt after lbw_set_launch) */
-    int32_t slabs;         /* pipelined variant: number of vertical slabs */
+    int32_t reserved;      /* must be 0 */
     int32_t tile_rows;     /* transport tile rows (3D): 0 = 256 / tile_x
                               (32x8, 64x4, 128x2 with 256 threads), or 16 with
                               tile_x 32 and 8 with tile_x 64 (512 threads);
@@ -377,9 +371,7 @@ int lbw_adjoint_step(lbw_handle *h, int32_t run, const void *f_n, const void *c_
 /* Per-phase GPU time of the lbw_step calls made between lbw_timing_begin and
  * lbw_timing_end: HIP events are recorded on the stream each launch goes to,
  * around every collide-stream launch and around the transport launches of
- * every step (around each slab's kernels in the pipelined variant, where
- * the phases overlap in time and each span includes the slow-down from the
- * kernels running beside it).  lbw_timing_end waits for the events and writes
+ * every step.  lbw_timing_end waits for the events and writes
  * the summed milliseconds per phase to ms_out[LBW_NPHASES] and the number of
  * steps timed to *steps.  Events are host-side runtime objects, pooled in the
  * handle; graph replay is not used while timing. */

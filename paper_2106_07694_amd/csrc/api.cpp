@@ -35,10 +35,6 @@ struct lbw_handle {
     std::vector<hipEvent_t> pool;
     size_t pool_used = 0;
     int64_t timed_steps = 0;
-    // pipelined variant: second stream and the slab events
-    hipStream_t side = nullptr;
-    std::vector<hipEvent_t> ev_lbm, ev_tr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool sflip = false;              // S currently lives in s_tmp
     int num_cu = 256;
     // batched mode (nbatch > 1): tables in run 0's scratch.  The transport
@@ -354,14 +350,6 @@ int lbw_create(const lbw_config *cfgs, const lbw_buffers *bufs, int32_t nbatch, 
 void lbw_destroy(lbw_handle *h) {
     if (!h) return;
     for (hipEvent_t ev : h->pool) (void)hipEventDestroy(ev);
-    for (hipEvent_t ev : h->ev_lbm) (void)hipEventDestroy(ev);
-    for (hipEvent_t ev : h->ev_tr) (void)hipEventDestroy(ev);
-    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
-    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
-    if (h->side) {
-        (void)hipStreamSynchronize(h->side);
-        (void)hipStreamDestroy(h->side);
-    }
     release_graph(h);
     delete h;
 }
@@ -394,12 +382,9 @@ int lbw_set_launch(lbw_handle *h, const lbw_launch *l) {
         if (l->tile_y < 1 || l->tile_y > 4096) return fail(LBW_ERR_INVAL, "tile_y must lie in [1, 4096]");
         n.tile_y = l->tile_y;
     }
-    if (l->variant < 0 || l->variant > 2) return fail(LBW_ERR_INVAL, "variant must be 0, 1 or 2");
-    if (l->variant == 2 && h->nbatch > 1)
-        return fail(LBW_ERR_UNSUPPORTED, "the pipelined variant drives a single run");
+    if (l->variant < 0 || l->variant > 1) return fail(LBW_ERR_INVAL, "variant must be 0 or 1");
     n.variant = l->variant;
-    if (l->slabs < 0 || l->slabs > 64) return fail(LBW_ERR_INVAL, "slabs must lie in [0, 64]");
-    n.slabs = l->slabs;
+    if (l->reserved != 0) return fail(LBW_ERR_INVAL, "reserved must be 0");
     if (l->graph < 0 || l->graph > 1) return fail(LBW_ERR_INVAL, "graph must be 0 or 1");
     n.graph = l->graph;
     h->launch = n;
@@ -500,98 +485,6 @@ int enqueue_step(lbw_handle *h) {
     return LBW_OK;
 }
 
-// Vertical slabs of the pipelined variant: chunk-aligned plane ranges.
-void slab_planes(const lbw_handle *h, int nslab, std::vector<int> &lo, std::vector<int> &hi) {
-    const lbw::RunDev &r = h->run[0];
-    const int nv = h->dim == 3 ? r.nz : r.ny;
-    int chunk = lbw::resolve_tile_shape(h->dim, h->launch).chunk;
-    if (chunk > nv) chunk = nv;
-    const int nch = (nv + chunk - 1) / chunk;
-    const int P = std::max(1, std::min(nslab, nch));
-    lo.resize(P);
-    hi.resize(P);
-    for (int p = 0; p < P; ++p) {
-        lo[p] = (int)((int64_t)nch * p / P) * chunk;
-        hi[p] = std::min(nv, (int)((int64_t)nch * (p + 1) / P) * chunk);
-    }
-}
-
-int ensure_pipeline(lbw_handle *h, int P) {
-    hipError_t e = hipSuccess;
-    if (!h->side) e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
-    if (e == hipSuccess && !h->ev_fork) e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
-    if (e == hipSuccess && !h->ev_join) e = hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming);
-    while (e == hipSuccess && (int)h->ev_lbm.size() < P) {
-        hipEvent_t a = nullptr, b = nullptr;
-        e = hipEventCreateWithFlags(&a, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&b, hipEventDisableTiming);
-        if (a) h->ev_lbm.push_back(a);
-        if (b) h->ev_tr.push_back(b);
-    }
-    return e == hipSuccess ? LBW_OK : hip_fail(e, "pipeline stream/events");
-}
-
-// One step of the pipelined variant.  Stream A (the handle's) runs the
-// collide-stream kernel slab by slab; stream B runs the three RK stages in a
-// wavefront over the slabs.  Slab p of stage 1 waits for the collide-stream of
-// slabs up to p+1 (its velocity halo) and carries the slab's S update;
-// stages 2 and 3 follow stage 1 on B; the collide-stream of the next step on
-// slab p waits for stage 3 on slabs up to p+1, which also retires every
-// reader of this step's velocity and concentration in slab p (and, stage 1
-// being earlier on B, the S update of those slabs).  `primed` says whether B's events of the
-// previous step are pending in this call.
-int enqueue_step_pipelined(lbw_handle *h, bool primed) {
-    std::vector<int> lo, hi;
-    slab_planes(h, h->launch.slabs > 0 ? h->launch.slabs : 8, lo, hi);
-    const int P = (int)lo.size();
-    int rc = ensure_pipeline(h, P);
-    if (rc) return rc;
-    hipStream_t A = h->stream, B = h->side;
-    const lbw::RunDev r = current(h, 0);
-    const int64_t sv = h->dim == 3 ? (int64_t)r.nx * r.ny : (int64_t)r.nx;
-    hipError_t e;
-    for (int p = 0; p < P; ++p) {
-        if (primed) {
-            e = hipStreamWaitEvent(A, h->ev_tr[std::min(p + 1, P - 1)], 0);
-            if (e != hipSuccess) return hip_fail(e, "stream wait");
-        }
-        if (h->fluid_mode == LBW_FLUID_LBM) {
-            const int sp = span_open(h, LBW_PHASE_COLLIDE_STREAM, A);
-            e = lbw::launch_collide_stream(h->q, h->precision, r, h->odd, h->launch.lbm_block, A,
-                                           lo[p] * sv, hi[p] * sv);
-            if (e != hipSuccess) return hip_fail(e, "collide-stream launch");
-            if ((rc = span_close(h, sp, A))) return rc;
-        }
-        e = hipEventRecord(h->ev_lbm[p], A);
-        if (e != hipSuccess) return hip_fail(e, "event record");
-    }
-    for (int i = 0; i < P + 2; ++i) {
-        const int sp = span_open(h, LBW_PHASE_TRANSPORT, B);
-        if (i < P) {
-            e = hipStreamWaitEvent(B, h->ev_lbm[std::min(i + 1, P - 1)], 0);
-            if (e == hipSuccess) e = lbw::launch_stage_slab(h->dim, h->precision, r, h->launch, 1, lo[i], hi[i], B);
-            if (e != hipSuccess) return hip_fail(e, "stage 1 launch");
-        }
-        if (i >= 1 && i <= P) {
-            e = lbw::launch_stage_slab(h->dim, h->precision, r, h->launch, 2, lo[i - 1], hi[i - 1], B);
-            if (e != hipSuccess) return hip_fail(e, "stage 2 launch");
-        }
-        if (i >= 2) {
-            const int q = i - 2;
-            e = lbw::launch_stage_slab(h->dim, h->precision, r, h->launch, 3, lo[q], hi[q], B);
-            if (e != hipSuccess) return hip_fail(e, "stage 3 launch");
-            e = hipEventRecord(h->ev_tr[q], B);
-            if (e != hipSuccess) return hip_fail(e, "event record");
-        }
-        if ((rc = span_close(h, sp, B))) return rc;
-    }
-    if (h->timing) ++h->timed_steps;
-    if (h->has_s) h->sflip = !h->sflip;
-    if (h->fluid_mode == LBW_FLUID_LBM) h->odd = !h->odd;
-    ++h->steps;
-    return LBW_OK;
-}
-
 // Capture two steps from the current state into a graph (the state returns
 // to where it was: two steps restore the parity and the S roles).
 int build_graph(lbw_handle *h) {
@@ -628,22 +521,7 @@ int lbw_step(lbw_handle *h, int32_t nsteps) {
     if (!h) return fail(LBW_ERR_INVAL, "NULL handle");
     if (nsteps < 0) return fail(LBW_ERR_INVAL, "nsteps must be >= 0");
     int rc;
-    // the slab order assumes walls: a periodic vertical axis couples the first
-    // and last slabs, so such runs take the sequential order
-    if (h->launch.variant == 2 && !h->run[0].vper && h->run[0].ncls == 1 && h->run[0].vs_s == 0.0 &&
-        nsteps > 0) {
-        if ((rc = ensure_pipeline(h, 1))) return rc;
-        // B starts after everything already queued on A, A ends after B
-        hipError_t e = hipEventRecord(h->ev_fork, h->stream);
-        if (e == hipSuccess) e = hipStreamWaitEvent(h->side, h->ev_fork, 0);
-        if (e != hipSuccess) return hip_fail(e, "pipeline fork");
-        for (int32_t s = 0; s < nsteps; ++s)
-            if ((rc = enqueue_step_pipelined(h, s > 0))) return rc;
-        e = hipEventRecord(h->ev_join, h->side);
-        if (e == hipSuccess) e = hipStreamWaitEvent(h->stream, h->ev_join, 0);
-        return e == hipSuccess ? LBW_OK : hip_fail(e, "pipeline join");
-    }
-    if (h->launch.graph && h->launch.variant != 2 && !h->timing && nsteps >= 2) {  // never pipelined
+    if (h->launch.graph && !h->timing && nsteps >= 2) {
         if (!h->stream) return fail(LBW_ERR_UNSUPPORTED, "graph replay needs a non-null stream");
         if (!h->gexec || h->graph_odd != h->odd || h->graph_sflip != h->sflip)
             if ((rc = build_graph(h))) return rc;

@@ -33,34 +33,16 @@ __device__ __forceinline__ void collide_stream_node(const RunDev &r, int64_t k) 
 #pragma unroll
     for (int i = 0; i < Q; ++i) fi[i] = load_canonical<Q, T, NT>(r, f, i, k, x, y, z, ODD);
 
-    // moments (eq. 19-20) with the Guo shift and the buoyancy force (eq. 10)
-    T F[3], uu[3], rho, drho;
+    // moments (eq. 19-20) with the Guo shift and the buoyancy force (eq. 10),
+    // then the BGK + Guo collision (eq. 18, 22)
+    T F[3], uu[3], rho;
     lbm_force<D, T>(r, (const T *)r.c, (const T *)r.s, k, F);
-    lbm_rho_u<Q, T, SH>(fi, F, rho, drho, uu);
-    const T Fx = F[0], Fy = F[1], Fz = F[2];
-    const T ux = uu[0], uy = uu[1], uz = uu[2];
+    lbm_collide<Q, T, SH>(r, fi, F, rho, uu);
     T *__restrict__ uo = (T *)r.u;
-    uo[k] = ux;
-    uo[r.N + k] = uy;
-    if (D == 3) uo[2 * r.N + k] = uz;
+    uo[k] = uu[0];
+    uo[r.N + k] = uu[1];
+    if (D == 3) uo[2 * r.N + k] = uu[2];
     if (r.rho) ((T *)r.rho)[k] = rho;
-
-    // BGK + Guo collision (eq. 18, 22)
-    const T omega = (T)r.omega, guo = (T)r.guo;
-    const T usq = ux * ux + uy * uy + uz * uz;
-    const T uF = ux * Fx + uy * Fy + uz * Fz;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const T w = (T)L::w[i];
-        const T cu = (T)L::cx[i] * ux + (T)L::cy[i] * uy + (T)L::cz[i] * uz;
-        const T cF = (T)L::cx[i] * Fx + (T)L::cy[i] * Fy + (T)L::cz[i] * Fz;
-        const T poly = (T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * usq;
-        // shifted: g_eq = w (drho + rho poly); plain: f_eq = w rho (1 + poly)
-        const T feq = SH ? w * (drho + rho * poly) : w * rho * ((T)1 + poly);
-        const T Fi = guo * w * ((T)3 * (cF - uF) + (T)9 * cu * cF);
-        fi[i] = fi[i] - omega * (fi[i] - feq) + Fi;
-    }
-    (void)drho;
 
     // store (streaming)
 #pragma unroll
@@ -169,8 +151,8 @@ inline bool streaming_populations(size_t bytes) { return bytes > kStreamingBytes
 template <int Q, typename T, bool SH>
 hipError_t collide_stream_t(const RunDev &r, bool odd, int block, int64_t k0, int64_t k1,
                             hipStream_t st) {
-    const dim3 grid(blocks_for(k1 - k0, block));
     const bool nt = streaming_populations((size_t)Q * sizeof(T) * (size_t)r.N);
+    const dim3 grid(blocks_for(k1 - k0, block));
     if (odd) {
         if (nt) k_collide_stream<Q, T, SH, true, true><<<grid, block, 0, st>>>(r, k0, k1);
         else k_collide_stream<Q, T, SH, true, false><<<grid, block, 0, st>>>(r, k0, k1);

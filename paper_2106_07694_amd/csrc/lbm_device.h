@@ -57,10 +57,17 @@ __device__ __forceinline__ void pop_store(T *p, T v) {
 
 // 6 w_i (c_i . u_top): momentum a moving top wall hands to a reflected
 // population (half-way bounce-back with a wall velocity).
+// The components with c_i = 0 are left out of the sum (each kept product is
+// exact, c_i being +-1), so for an unrolled i only the wall's tangential
+// and normal parts that the direction carries are computed.
 template <int Q>
 __device__ __forceinline__ double lid_term(const RunDev &r, int i) {
     using L = Lattice<Q>;
-    return 6.0 * L::w[i] * (L::cx[i] * r.utop[0] + L::cy[i] * r.utop[1] + L::cz[i] * r.utop[2]);
+    double cu = 0.0;
+    if (L::cx[i]) cu = L::cx[i] * r.utop[0];
+    if (L::cy[i]) cu = cu + L::cy[i] * r.utop[1];
+    if (L::cz[i]) cu = cu + L::cz[i] * r.utop[2];
+    return 6.0 * L::w[i] * cu;
 }
 
 // Canonical pre-collision population f_i at node k when the buffer holds the
@@ -137,16 +144,64 @@ __device__ __forceinline__ void lbm_rho_u(const T (&fi)[Q], const T F[3], T &rho
 // the density anomaly of the fluid acts on its fraction 1 - phi, phi =
 // phi_c C (phi_c = 0: the linear form).  With several particle size classes
 // C is their total, summed in class order (eq. 11-12).
+// The same from the total concentration ctot and S (sv, read only with S).
+template <int D, typename T>
+__device__ __forceinline__ void lbm_force_of(const RunDev &r, T ctot, T sv, T F[3]) {
+    T fv = -(T)r.gp_c * ctot;
+    if (r.has_s) fv -= (T)r.gp_s * (sv * ((T)1 - (T)r.phi_c * ctot));
+    F[0] = (T)r.body[0];
+    F[1] = (T)r.body[1] + (D == 2 ? fv : (T)0);
+    F[2] = (T)r.body[2] + (D == 3 ? fv : (T)0);
+}
+
 template <int D, typename T>
 __device__ __forceinline__ void lbm_force(const RunDev &r, const T *__restrict__ c,
                                           const T *__restrict__ s, int64_t k, T F[3]) {
     T ctot = c[k];
     for (int i = 1; i < r.ncls; ++i) ctot += c[k + (int64_t)i * r.N];
-    T fv = -(T)r.gp_c * ctot;
-    if (r.has_s) fv -= (T)r.gp_s * (s[k] * ((T)1 - (T)r.phi_c * ctot));
-    F[0] = (T)r.body[0];
-    F[1] = (T)r.body[1] + (D == 2 ? fv : (T)0);
-    F[2] = (T)r.body[2] + (D == 3 ? fv : (T)0);
+    lbm_force_of<D, T>(r, ctot, r.has_s ? s[k] : (T)0, F);
+}
+
+// c_i . a for the unrolled direction i: the components with c = 0 are left
+// out (0 * a is not folded away in IEEE arithmetic, so writing them costs a
+// multiply or fused multiply-add each); with c = +-1 every kept product is
+// exact, and the sum equals the full one up to the sign of a zero.
+template <int Q, typename T>
+__device__ __forceinline__ T cdot(int i, T ax, T ay, T az) {
+    using L = Lattice<Q>;
+    T s = (T)0;
+    bool any = false;
+    if (L::cx[i]) { s = L::cx[i] > 0 ? ax : -ax; any = true; }
+    if (L::cy[i]) { const T t = L::cy[i] > 0 ? ay : -ay; s = any ? s + t : t; any = true; }
+    if (L::D == 3 && L::cz[i]) { const T t = L::cz[i] > 0 ? az : -az; s = any ? s + t : t; }
+    return s;
+}
+
+// BGK collision with Guo forcing (eq. 18, 22) of one node's populations fi
+// (in place) for force F, after the moments of eq. 19-20: rho and the
+// force-shifted velocity u come back for the caller to store.
+template <int Q, typename T, bool SH>
+__device__ __forceinline__ void lbm_collide(const RunDev &r, T (&fi)[Q], const T F[3], T &rho,
+                                            T uu[3]) {
+    using L = Lattice<Q>;
+    T drho;
+    lbm_rho_u<Q, T, SH>(fi, F, rho, drho, uu);
+    const T Fx = F[0], Fy = F[1], Fz = F[2];
+    const T ux = uu[0], uy = uu[1], uz = uu[2];
+    const T omega = (T)r.omega, guo = (T)r.guo;
+    const T usq = ux * ux + uy * uy + uz * uz;
+    const T uF = ux * Fx + uy * Fy + uz * Fz;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const T w = (T)L::w[i];
+        const T cu = cdot<Q>(i, ux, uy, uz);
+        const T cF = cdot<Q>(i, Fx, Fy, Fz);
+        const T poly = (T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * usq;
+        // shifted: g_eq = w (drho + rho poly); plain: f_eq = w rho (1 + poly)
+        const T feq = SH ? w * (drho + rho * poly) : w * rho * ((T)1 + poly);
+        const T Fi = guo * w * ((T)3 * (cF - uF) + (T)9 * cu * cF);
+        fi[i] = fi[i] - omega * (fi[i] - feq) + Fi;
+    }
 }
 
 // Canonical density at node k (shifted storage adds back rho0 = 1).

@@ -73,7 +73,7 @@ class CBuffers(ctypes.Structure):
 class CLaunch(ctypes.Structure):
     _fields_ = [("lbm_block", ctypes.c_int32), ("tile_x", ctypes.c_int32),
                 ("tile_y", ctypes.c_int32), ("variant", ctypes.c_int32),
-                ("graph", ctypes.c_int32), ("slabs", ctypes.c_int32),
+                ("graph", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("tile_rows", ctypes.c_int32)]
 
 
@@ -377,15 +377,15 @@ class Solver:
         check(self._lib.lbw_steps_done(self._h, ctypes.byref(v)))
         return v.value
 
-    def set_launch(self, lbm_block=0, tile_x=0, tile_y=0, variant=0, graph=0, slabs=0, tile_rows=0):
-        lc = CLaunch(lbm_block, tile_x, tile_y, variant, graph, slabs, tile_rows)
+    def set_launch(self, lbm_block=0, tile_x=0, tile_y=0, variant=0, graph=0, tile_rows=0):
+        lc = CLaunch(lbm_block, tile_x, tile_y, variant, graph, 0, tile_rows)
         check(self._lib.lbw_set_launch(self._h, ctypes.byref(lc)))
 
     def get_launch(self) -> dict:
         lc = CLaunch()
         check(self._lib.lbw_get_launch(self._h, ctypes.byref(lc)))
         return {"lbm_block": lc.lbm_block, "tile_x": lc.tile_x, "tile_y": lc.tile_y,
-                "variant": lc.variant, "graph": lc.graph, "slabs": lc.slabs,
+                "variant": lc.variant, "graph": lc.graph,
                 "tile_rows": lc.tile_rows}
 
     def reduce(self, what) -> np.ndarray:

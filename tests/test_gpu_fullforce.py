@@ -70,11 +70,9 @@ def test_full_force_matches_oracle_fp64(kw):
     _check(_cfg(lattice, **kw), 20)
 
 
-@pytest.mark.parametrize("launch", [dict(variant=1), dict(tile_x=64, tile_y=5),
-                                    dict(variant=2, slabs=3)])
+@pytest.mark.parametrize("launch", [dict(variant=1), dict(tile_x=64, tile_y=5)])
 def test_every_transport_form(launch):
-    """Plain and tiled kernels agree with the oracle; the pipelined variant
-    runs such a run in the sequential order."""
+    """Plain and tiled kernels agree with the oracle."""
     _check(_cfg(9, nx=150, ny=37), 9, launch=launch)
 
 

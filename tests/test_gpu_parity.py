@@ -125,8 +125,6 @@ def test_launch_shapes_give_identical_bits(lbm_block):
     dict(tile_x=128, tile_y=5),
     dict(tile_x=256, tile_y=1000),
     dict(tile_x=512, tile_y=6),
-    dict(variant=2, tile_y=4, slabs=3),
-    dict(variant=2, tile_y=8, slabs=64),
 ])
 def test_2d_transport_launches(launch):
     """Every transport tiling, ragged chunks included, matches the oracle."""
@@ -143,8 +141,6 @@ def test_2d_transport_launches(launch):
     dict(tile_x=128, tile_y=64),
     dict(tile_x=32, tile_rows=16, tile_y=5),
     dict(tile_x=64, tile_rows=8, tile_y=3),
-    dict(variant=2, tile_y=2, slabs=4),
-    dict(variant=2, tile_y=3, slabs=2),
 ])
 @pytest.mark.parametrize("vper", [False, True])
 def test_3d_transport_launches(launch, vper):
@@ -152,29 +148,6 @@ def test_3d_transport_launches(launch, vper):
                         gp_c=5e-4, vert_periodic=vper)
     c0, _ = _rng_fields(cfg, 9)
     _check(cfg, 8, c0, launch=launch)
-
-
-@pytest.mark.parametrize("q", [9, 19, "19s"])
-def test_pipelined_equals_sequential_bitwise(q):
-    """The slab-pipelined variant runs the same kernels on the same data in a
-    different order (the S update slab by slab): its results must be
-    identical bit for bit."""
-    if q == 9:
-        wl = W.C2.replace(nx=192, ny=160)
-        kw = dict(tile_x=64, tile_y=8)
-    elif q == 19:
-        wl = W.C3.replace(nx=32, ny=24, nz=40)
-        kw = dict(tile_x=32, tile_y=4)
-    else:
-        wl = W.C3.replace(nx=32, ny=24, nz=40, has_s=True, kappa_s=1e-4, gp_s=2e-5)
-        kw = dict(tile_x=32, tile_y=4)
-    cfg = lbw.RunConfig.from_workload(wl)
-    c0, s0 = W.initial_scalars(wl)
-    ref = run_gpu(cfg, c0, s0, nsteps=13, launch=dict(kw))
-    for slabs in (2, 5, 64):
-        got = run_gpu(cfg, c0, s0, nsteps=13, launch=dict(kw, variant=2, slabs=slabs))
-        for k in ref:
-            assert np.array_equal(ref[k], got[k]), (slabs, k)
 
 
 @pytest.mark.parametrize("frozen", [False, True])

@@ -95,11 +95,10 @@ def test_classes_fp32_shifted(lattice):
     assert all(errs[k] <= bounds[k] for k in errs), errs
 
 
-@pytest.mark.parametrize("launch", [dict(variant=1), dict(tile_x=64, tile_y=5),
-                                    dict(variant=2, slabs=3)])
+@pytest.mark.parametrize("launch", [dict(variant=1), dict(tile_x=64, tile_y=5)])
 def test_classes_every_transport_form(launch):
     """The plain and tiled transports agree with the oracle for several
-    classes; the pipelined variant runs such runs in the sequential order."""
+    classes."""
     cfg = _cfg(2, 9, nx=150, ny=37)
     c0, _ = _fields(cfg, 15)
     _check(cfg, 9, c0, launch=launch)
