@@ -1,16 +1,18 @@
 """FP32 shifted-population form against the FP64 oracle (same inputs).
 
 Tolerances per field after 100 steps, relative to the field's maximum:
-u 1e-4, C 3e-5, S 1e-5, populations 1e-4 (compared as g = f - w, what is
+u 1e-4, C 1e-5, S 1e-5, populations 1e-4 (compared as g = f - w, what is
 stored, relative to max |g|) -- FP32 storage and arithmetic.  The deposit is
-accumulated in FP64 from FP32 concentrations, so its error follows the
-concentration's: it is measured relative to n Vs max|C| (what n steps of a
-full bottom layer would deposit) and bounded by 1e-6.  Measured on MI355X
-(128x256 with S, C0 in {0.5, 1, 2}): C 4.5e-6 .. 6.5e-6, u <= 3.4e-6,
-S <= 4.4e-6, deposit <= 8e-10; 3D 32x32x64: C 2.6e-6.  C is the most
+accumulated in FP64 from FP32 concentrations of the bottom cells, so its
+error is that of the bottom plane's concentration relative to itself: it is
+measured against the oracle's own deposit (max |dD| / max |D|) and bounded
+like C, by 1e-5 (measured 4e-7 to 6e-7).  Measured on MI355X (128x256 with S, C0 in {0.5, 1, 2}): C 4.5e-6
+.. 6.5e-6, u <= 3.4e-6, S <= 4.4e-6; 3D 32x32x64: C 2.6e-6.  C is the most
 sensitive: with eps = 1e-6 the WENO weights respond to smoothness
 indicators of the 1e-3 seeded noise, which single precision differences of
-O(1) values resolve only to about ten percent.
+O(1) values resolve only to about ten percent.  (White-noise fields, where
+every face sees O(1) indicator differences, reach 2e-5: the size-class and
+full-force tests keep 3e-5 for C.)
 """
 import numpy as np
 import pytest
@@ -20,7 +22,7 @@ from paper_2106_07694_amd import lbw, workloads as W
 from parity import as_input, compare, run_gpu, run_oracle
 
 pytestmark = pytest.mark.gpu
-TOL = {"u": 1e-4, "c": 3e-5, "s": 1e-5, "deposit": 1e-6, "f": 1e-4}
+TOL = {"u": 1e-4, "c": 1e-5, "s": 1e-5, "deposit": 1e-5, "f": 1e-4}
 
 
 def _fp32_case(wl, nsteps):
@@ -30,9 +32,9 @@ def _fp32_case(wl, nsteps):
     c0, s0 = as_input(c0, cfg), as_input(s0, cfg)
     g = run_gpu(cfg, c0, s0, nsteps=nsteps)
     o = run_oracle(cfg, c0, s0, nsteps=nsteps)
+    dep = o.pop("deposit")
     errs = compare(g, o)
-    scale = nsteps * wl.vs * float(np.max(np.abs(o["c"])))
-    errs["deposit"] = float(np.max(np.abs(g["deposit"] - o["deposit"]))) / scale
+    errs["deposit"] = float(np.max(np.abs(g["deposit"] - dep))) / float(np.max(np.abs(dep)))
     print(f"\n{wl.name} steps={nsteps}: {errs}")
     return errs
 

@@ -89,6 +89,9 @@ def test_full_force_fp32_shifted(lattice):
     o = run_oracle(cfg, c0, s0, None, None, 50)
     errs = compare(g, o)
     print(f"\nfp32 {lattice}: {errs}")
+    # white-noise fields: every face sees O(1) smoothness-indicator
+    # differences, which FP32 resolves less well than the workloads' smooth
+    # layers, hence 3e-5 for C here (1e-5 on the workload-shaped inputs)
     bounds = {"c": 3e-5, "u": 1e-4, "s": 1e-5, "f": 1e-4, "deposit": 1e-5}
     assert all(errs[k] <= bounds[k] for k in errs), errs
 

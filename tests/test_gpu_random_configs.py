@@ -91,8 +91,14 @@ def _oracle_sensitivity(cfg, c0, s0, u, nsteps, o):
     return compare(o2, o)
 
 
-# the draw of seed 20071 is conditioned at ~1e-12 (white-noise C, WENO3): it
-# takes the sensitivity path
+# Draws whose conditioning sits at the 1e-12 bar: a random +-1-ulp change of
+# every input moves the oracle's own output by about as much.  Only these may
+# use the sensitivity allowance, and only up to 1e-11.  Case 19071 (seed
+# 20071: white-noise C, WENO3, frozen flow) is the one found.
+SENSITIVE = {19071}
+SENSITIVE_CAP = 1e-11
+
+
 @pytest.mark.parametrize("case", list(range(NCASES)) + [19071])
 def test_random_config_matches_oracle(case):
     rng = np.random.default_rng(1000 + case)
@@ -105,10 +111,10 @@ def test_random_config_matches_oracle(case):
     errs = compare(g, o)
     print(f"\ncase {case}: {cfg} {launch} steps={nsteps}: {errs}")
     bad = {k: v for k, v in errs.items() if k != "u" and not v <= TOL64}
-    if bad:
+    if bad and case in SENSITIVE:
         sens = _oracle_sensitivity(cfg, c0, s0, u, nsteps, o)
         print(f"oracle sensitivity to one ulp of its input: {sens}")
-        bad = {k: v for k, v in bad.items() if not v <= 4 * sens[k]}
+        bad = {k: v for k, v in bad.items() if not (v <= 4 * sens[k] and v <= SENSITIVE_CAP)}
     assert not bad, (errs, cfg, launch)
     if "f" in o:
         du = float(np.max(np.abs(g["u"] - o["u"])))
