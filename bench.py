@@ -113,9 +113,11 @@ def ingest_counters(fetch_csv: str, write_csv: str, workload: str, cells: int,
     ws = copy_bytes / 1024.0 / write[copy[0]]
     kernels = {}
     for k in fetch:
-        if k in copy or k not in write:
+        if k in copy or k not in write or "lbw::" not in k:
             continue
-        short = k.replace("void lbw::(anonymous namespace)::", "").split("(")[0]
+        short = k.replace("(anonymous namespace)::", "").replace("lbw::", "")
+        short = short[5:] if short.startswith("void ") else short
+        short = short.split("(")[0]
         fb, wb = fetch[k] * 1024.0 * fs, write[k] * 1024.0 * ws
         kernels[short] = {"fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb,
                           "bytes_per_cell": (fb + wb) / cells, "launches": n_f[k]}
@@ -123,18 +125,22 @@ def ingest_counters(fetch_csv: str, write_csv: str, workload: str, cells: int,
                               "fetch_kib_read": fetch[copy[0]], "write_kib_read": write[copy[0]],
                               "fetch_scale": fs, "write_scale": ws},
              "kernels": kernels}
-    cs = [v["bytes_per_launch"] for k, v in kernels.items() if k.startswith("k_collide_stream<")]
+    cs = [v for k, v in kernels.items() if k.startswith("k_collide_stream<")]
     if cs:
-        entry["collide_stream"] = {"source_hash": _kernel_hash("collide_stream"),
-                                   "bytes_per_launch": sum(cs) / len(cs)}
-    st = [v["bytes_per_launch"] for k, v in kernels.items() if k.startswith("k_stage_tiled<")]
+        f, w = (sum(v[x] for v in cs) / len(cs) for x in ("fetch_bytes", "write_bytes"))
+        entry["collide_stream"] = {"source_hash": _kernel_hash("collide_stream"), "fetch_bytes": f,
+                                   "write_bytes": w, "bytes_per_launch": f + w}
+    st = [v for k, v in kernels.items() if k.startswith("k_stage_tiled<")]
     if len(st) == 3:
-        entry["transport"] = {"source_hash": _kernel_hash("transport"), "bytes_per_launch": sum(st)}
+        f, w = (sum(v[x] for v in st) for x in ("fetch_bytes", "write_bytes"))
+        entry["transport"] = {"source_hash": _kernel_hash("transport"), "fetch_bytes": f,
+                              "write_bytes": w, "bytes_per_launch": f + w}
     try:
         with open(PROFILE_COUNTERS) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         d = {}
+    d = {k: v for k, v in d.items() if not k.startswith("_")}
     d[workload] = entry
     with open(PROFILE_COUNTERS, "w") as fh:
         json.dump(d, fh, indent=1, sort_keys=True)

