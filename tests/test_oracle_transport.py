@@ -385,3 +385,32 @@ def test_wall_ghosts_mirror_image_rejects_other_rules(q, nx, scheme, rule):
     keep[vax] = slice(0, n - 1)
     diff = np.abs(phi_w[v][tuple(keep)] - _upper(phi_p[v], vax, n)[tuple(keep)])
     assert diff.max() > 1e-6 * np.abs(phi_w[v]).max()
+
+
+@pytest.mark.parametrize("q,nx", [(9, 7), (19, 5)])
+@pytest.mark.parametrize("vper", [False, True])
+def test_operator_is_minus_the_divergence_of_the_exposed_faces(q, nx, vper):
+    """orc_faces_c exposes the fluxes orc_rhs_c differences: summing the
+    per-axis differences (bottom wall face included, periodic axes wrapped)
+    gives L, so the mirror-image comparison above is about the operator's own
+    faces."""
+    n = 12
+    walled, _, a, u, _, _, vax, dim = _mirror_case(q, nx, n, "weno5", 0.02, 3e-3, 0.0, seed=41 + q)
+    cfg = walled if not vper else OracleConfig(**{**walled.__dict__, "vert_periodic": True})
+    phi, bottom = oracle.faces_c(cfg, a, u)
+    L, _ = oracle.rhs_c(cfg, a, u)
+    arr_ax = {0: 2, 1: 1, 2: 0}          # field axis of each lattice axis (z, y, x order)
+    acc = np.zeros_like(a)
+    for d in range(dim):
+        ax = arr_ax[d] if dim == 3 else (2 if d == 0 else 1)
+        left = np.roll(phi[d], 1, axis=ax)
+        if d == dim - 1 and not vper:
+            sl = [slice(None)] * 3
+            sl[ax] = 0
+            left[tuple(sl)] = bottom.reshape(left[tuple(sl)].shape)
+        acc = acc + (phi[d] - left)
+    np.testing.assert_allclose(L, -acc, rtol=0, atol=1e-15 * np.abs(phi).max())
+    if not vper:
+        top = [slice(None)] * 3
+        top[vax] = n - 1
+        assert np.all(phi[dim - 1][tuple(top)] == 0.0)
