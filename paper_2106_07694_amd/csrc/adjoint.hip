@@ -392,7 +392,8 @@ __global__ void __launch_bounds__(256) k_adj_gather(AdjDev A) {
         const int n = d == 0 ? r.nx : (d == 1 ? r.ny : r.nz);
         const int64_t stride = d == 0 ? 1 : (d == 1 ? (int64_t)r.nx : (int64_t)r.nx * r.ny);
         // images of node m as seen by stencils: itself, and beyond each wall
-        const int nimg = walls ? 3 : 1;
+        // (only rows m <= 1 and m >= n - 2 have images that a face reads)
+        const int nimg = (walls && (m <= 1 || m >= n - 2)) ? 3 : 1;
         for (int im = 0; im < nimg; ++im) {
             const int p = im == 0 ? m : (im == 1 ? -1 - m : 2 * n - 1 - m);
             const bool ghost = im != 0;
@@ -603,7 +604,11 @@ __global__ void __launch_bounds__(256) k_adj_stage2d(AdjDev A, const T *__restri
         // when m <= 1, so y0 = 0) and the top images (faces >= ny - 3 >= m - 2,
         // read only when m >= ny - 3).
         if (x0 + lx >= nx || m >= ny) continue;
-        const int nimg = walls ? 3 : 1;
+        // wall images reach only rows m <= 1 (the image -1 - m feeds faces 0
+        // and 1) and m >= ny - 2 (the image 2 ny - 1 - m feeds faces ny - 3
+        // and ny - 2); tiles clear of both take the node itself only (the
+        // same sum: the skipped images add nothing)
+        const int nimg = (walls && (y0 < 2 || y0 + TY > ny - 2)) ? 3 : 1;
         for (int im = 0; im < nimg; ++im) {
             const int p = im == 0 ? m : (im == 1 ? -1 - m : 2 * ny - 1 - m);
             const bool ghost = im != 0;
