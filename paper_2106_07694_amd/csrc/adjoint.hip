@@ -680,11 +680,10 @@ hipError_t adjoint_t(const AdjDev &A, const lbw_launch &l, hipStream_t st) {
         fr.c2 = A.a2;
         fr.u = A.frozen ? A.r.u : A.u;
         const int prec = sizeof(T) == 4 ? LBW_FP32_SHIFTED : LBW_FP64;
-        const int nv = D == 3 ? A.r.nz : A.r.ny;
         lbw_launch lt = l;
         lt.variant = 0;
-        e = launch_stage_slab(D, prec, fr, lt, 1, 0, nv, st);
-        if (e == hipSuccess) e = launch_stage_slab(D, prec, fr, lt, 2, 0, nv, st);
+        e = launch_one_stage(D, prec, fr, lt, 1, st);
+        if (e == hipSuccess) e = launch_one_stage(D, prec, fr, lt, 2, st);
         if (e != hipSuccess) return e;
     }
     if (D == 2 && l.variant != 1) {

@@ -62,11 +62,11 @@ __device__ __forceinline__ void collide_stream_node(const RunDev &r, int64_t k) 
     }
 }
 
-// Nodes [k0, k1) of one run (the whole run, or one vertical slab of it).
+// Every node of one run, one per thread.
 template <int Q, typename T, bool SH, bool ODD, bool NT>
-__global__ void __launch_bounds__(1024) k_collide_stream(RunDev r, int64_t k0, int64_t k1) {
-    const int64_t k = k0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= k1) return;
+__global__ void __launch_bounds__(1024) k_collide_stream(RunDev r) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= r.N) return;
     collide_stream_node<Q, T, SH, ODD, NT>(r, k);
 }
 
@@ -149,16 +149,15 @@ constexpr size_t kStreamingBytes = (size_t)192 << 20;
 inline bool streaming_populations(size_t bytes) { return bytes > kStreamingBytes; }
 
 template <int Q, typename T, bool SH>
-hipError_t collide_stream_t(const RunDev &r, bool odd, int block, int64_t k0, int64_t k1,
-                            hipStream_t st) {
+hipError_t collide_stream_t(const RunDev &r, bool odd, int block, hipStream_t st) {
     const bool nt = streaming_populations((size_t)Q * sizeof(T) * (size_t)r.N);
-    const dim3 grid(blocks_for(k1 - k0, block));
+    const dim3 grid(blocks_for(r.N, block));
     if (odd) {
-        if (nt) k_collide_stream<Q, T, SH, true, true><<<grid, block, 0, st>>>(r, k0, k1);
-        else k_collide_stream<Q, T, SH, true, false><<<grid, block, 0, st>>>(r, k0, k1);
+        if (nt) k_collide_stream<Q, T, SH, true, true><<<grid, block, 0, st>>>(r);
+        else k_collide_stream<Q, T, SH, true, false><<<grid, block, 0, st>>>(r);
     } else {
-        if (nt) k_collide_stream<Q, T, SH, false, true><<<grid, block, 0, st>>>(r, k0, k1);
-        else k_collide_stream<Q, T, SH, false, false><<<grid, block, 0, st>>>(r, k0, k1);
+        if (nt) k_collide_stream<Q, T, SH, false, true><<<grid, block, 0, st>>>(r);
+        else k_collide_stream<Q, T, SH, false, false><<<grid, block, 0, st>>>(r);
     }
     return hipGetLastError();
 }
@@ -178,12 +177,11 @@ hipError_t collide_stream_batched_t(const RunDev *runs, const int *blk_start, in
 }
 
 template <int Q>
-hipError_t collide_stream_q(int precision, const RunDev &r, bool odd, int block, int64_t k0,
-                            int64_t k1, hipStream_t st) {
+hipError_t collide_stream_q(int precision, const RunDev &r, bool odd, int block, hipStream_t st) {
     switch (precision) {
-        case LBW_FP64: return collide_stream_t<Q, double, false>(r, odd, block, k0, k1, st);
-        case LBW_FP64_SHIFTED: return collide_stream_t<Q, double, true>(r, odd, block, k0, k1, st);
-        case LBW_FP32_SHIFTED: return collide_stream_t<Q, float, true>(r, odd, block, k0, k1, st);
+        case LBW_FP64: return collide_stream_t<Q, double, false>(r, odd, block, st);
+        case LBW_FP64_SHIFTED: return collide_stream_t<Q, double, true>(r, odd, block, st);
+        case LBW_FP32_SHIFTED: return collide_stream_t<Q, float, true>(r, odd, block, st);
     }
     return hipErrorInvalidValue;
 }
@@ -233,12 +231,11 @@ hipError_t export_q(int precision, const RunDev &r, void *dst, hipStream_t st) {
 }  // namespace
 
 hipError_t launch_collide_stream(int q, int precision, const RunDev &r, bool odd, int block,
-                                 hipStream_t st, int64_t k0, int64_t k1) {
+                                 hipStream_t st) {
     if (block <= 0 || block > 1024 || block % 64) return hipErrorInvalidValue;
-    if (k1 < 0) k1 = r.N;
-    if (k0 < 0 || k1 > r.N || k0 >= k1) return k0 == k1 ? hipSuccess : hipErrorInvalidValue;
-    return q == 9 ? collide_stream_q<9>(precision, r, odd, block, k0, k1, st)
-                  : collide_stream_q<19>(precision, r, odd, block, k0, k1, st);
+    if (r.N <= 0) return hipSuccess;
+    return q == 9 ? collide_stream_q<9>(precision, r, odd, block, st)
+                  : collide_stream_q<19>(precision, r, odd, block, st);
 }
 
 hipError_t launch_collide_stream_batched(int q, int precision, const RunDev *runs, const int *blk_start,

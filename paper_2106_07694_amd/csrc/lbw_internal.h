@@ -88,7 +88,7 @@ struct BatchArgs {
 // Launchers (return the launch error, if any).  `odd` selects the second
 // kernel of the in-place streaming pair.
 hipError_t launch_collide_stream(int q, int precision, const RunDev &r, bool odd,
-                                 int block, hipStream_t st, int64_t k0 = 0, int64_t k1 = -1);
+                                 int block, hipStream_t st);
 hipError_t launch_equilibrium(int q, int precision, const RunDev &r, bool odd, const void *rho,
                               const void *u, hipStream_t st);
 hipError_t launch_import_f(int q, int precision, const RunDev &r, bool odd, const void *src,
@@ -99,12 +99,11 @@ hipError_t launch_transport(int dim, int precision, const RunDev &r, const lbw_l
                             hipStream_t st);
 hipError_t launch_transport_tiled(int dim, int precision, const RunDev &r, const lbw_launch &l,
                                   hipStream_t st);
-hipError_t launch_s_update(int dim, int precision, const RunDev &r, hipStream_t st,
-                           int64_t k0 = 0, int64_t k1 = -1);
-// One RK stage (1, 2 or 3) of the tiled transport over the vertical planes
-// [v_lo, v_hi), which must start and end on a chunk boundary (or the top).
-hipError_t launch_stage_slab(int dim, int precision, const RunDev &r, const lbw_launch &l,
-                             int stage, int v_lo, int v_hi, hipStream_t st);
+hipError_t launch_s_update(int dim, int precision, const RunDev &r, hipStream_t st);
+// One RK stage (1, 2 or 3) of the tiled transport over the whole grid (runs
+// with a constant settling speed).
+hipError_t launch_one_stage(int dim, int precision, const RunDev &r, const lbw_launch &l,
+                            int stage, hipStream_t st);
 TileShape resolve_tile_shape(int dim, const lbw_launch &l);
 int64_t transport_tiles(int dim, const RunDev &r, const lbw_launch &l);
 hipError_t launch_transport_batched(int dim, int precision, const BatchArgs &b, const lbw_launch &l,
@@ -118,7 +117,6 @@ hipError_t launch_transport_tiled_vs(int dim, int precision, const RunDev &r, co
 hipError_t launch_collide_stream_batched(int q, int precision, const RunDev *runs, const int *blk_start,
                                          int nbatch, int sflip, bool odd, int block, int grid,
                                          int64_t nodes, hipStream_t st);
-hipError_t launch_rk_stages12(int dim, int precision, const RunDev &r, hipStream_t st);
 size_t adjoint_work_bytes(int dim, int precision, int64_t N);
 hipError_t launch_adjoint(int q, int precision, const RunDev &r, bool frozen, const void *f_n,
                           const void *c_n, const void *u_n, const void *rho_n, const void *a1_n,

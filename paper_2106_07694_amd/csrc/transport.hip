@@ -188,13 +188,9 @@ hipError_t transport_d(const RunDev &r, hipStream_t st) {
 
 }  // namespace
 
-hipError_t launch_s_update(int dim, int precision, const RunDev &r, hipStream_t st, int64_t k0,
-                           int64_t k1) {
-    if (k1 < 0) k1 = r.N;
-    if (k0 >= k1) return hipSuccess;
+hipError_t launch_s_update(int dim, int precision, const RunDev &r, hipStream_t st) {
     const int64_t P = (int64_t)r.nx * (dim == 3 ? r.ny : 1);
-    if (k0 % P || k1 % P) return hipErrorInvalidValue;      // whole planes only
-    const int v_lo = (int)(k0 / P), v_hi = (int)(k1 / P);
+    const int v_lo = 0, v_hi = dim == 3 ? r.nz : r.ny;
     const dim3 grid((unsigned)((P + 255) / 256), (unsigned)std::min(v_hi - v_lo, 65535));
     if (precision == LBW_FP32_SHIFTED) {
         if (dim == 2) k_s_update<float, 2><<<grid, 256, 0, st>>>(r, v_lo, v_hi);
@@ -202,29 +198,6 @@ hipError_t launch_s_update(int dim, int precision, const RunDev &r, hipStream_t 
     } else {
         if (dim == 2) k_s_update<double, 2><<<grid, 256, 0, st>>>(r, v_lo, v_hi);
         else k_s_update<double, 3><<<grid, 256, 0, st>>>(r, v_lo, v_hi);
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_rk_stages12(int dim, int precision, const RunDev &r, hipStream_t st) {
-    const int block = 256;
-    const dim3 grid((unsigned)((r.N + block - 1) / block));
-    if (precision == LBW_FP32_SHIFTED) {
-        if (dim == 2) {
-            k_rk_stage<float, 2, LBW_WENO5, 1><<<grid, block, 0, st>>>(r);
-            k_rk_stage<float, 2, LBW_WENO5, 2><<<grid, block, 0, st>>>(r);
-        } else {
-            k_rk_stage<float, 3, LBW_WENO5, 1><<<grid, block, 0, st>>>(r);
-            k_rk_stage<float, 3, LBW_WENO5, 2><<<grid, block, 0, st>>>(r);
-        }
-    } else {
-        if (dim == 2) {
-            k_rk_stage<double, 2, LBW_WENO5, 1><<<grid, block, 0, st>>>(r);
-            k_rk_stage<double, 2, LBW_WENO5, 2><<<grid, block, 0, st>>>(r);
-        } else {
-            k_rk_stage<double, 3, LBW_WENO5, 1><<<grid, block, 0, st>>>(r);
-            k_rk_stage<double, 3, LBW_WENO5, 2><<<grid, block, 0, st>>>(r);
-        }
     }
     return hipGetLastError();
 }

@@ -598,13 +598,10 @@ hipError_t stages(const RunDev &r, int chunk, hipStream_t st) {
 }
 
 template <typename T, int D, int SCHEME, int TX, int TY>
-hipError_t stage_slab_t(const RunDev &r, int chunk, int stage, int v_lo, int v_hi, hipStream_t st) {
-    TileGeom g = make_geom<D>(r, chunk, TX, TY);
-    const int c0 = v_lo / g.chunk, c1 = (v_hi + g.chunk - 1) / g.chunk;
-    if (v_lo % g.chunk || c1 > g.gz || c0 >= c1) return hipErrorInvalidValue;
-    g.bz0 = c0;
-    g.gz = c1 - c0;
+hipError_t one_stage_t(const RunDev &r, int chunk, int stage, hipStream_t st) {
+    const TileGeom g = make_geom<D>(r, chunk, TX, TY);
     const int64_t nb = (int64_t)g.gx * g.gy * g.gz;
+    if (nb > 0x7fffffff) return hipErrorInvalidValue;
     if (stage == 1) launch_stage1<T, D, SCHEME, TX, TY, false>(r, g, (unsigned)nb, st);
     else if (stage == 2) launch_stage<T, D, SCHEME, 2, TX, TY, false>(r, g, (unsigned)nb, st);
     else launch_stage<T, D, SCHEME, 3, TX, TY, false>(r, g, (unsigned)nb, st);
@@ -632,22 +629,19 @@ hipError_t with_tile(const TileShape &sh, F &&fn) {
 }
 
 template <typename T, int D, int SCHEME>
-hipError_t stage_slab_shape(const RunDev &r, const lbw_launch &l, int stage, int v_lo, int v_hi,
-                            hipStream_t st) {
+hipError_t one_stage_shape(const RunDev &r, const lbw_launch &l, int stage, hipStream_t st) {
     const TileShape sh = resolve_tile_shape(D, l);
     return with_tile<D>(sh, [&](auto tx, auto ty) {
-        return stage_slab_t<T, D, SCHEME, decltype(tx)::value, decltype(ty)::value>(r, sh.chunk, stage, v_lo,
-                                                                                  v_hi, st);
+        return one_stage_t<T, D, SCHEME, decltype(tx)::value, decltype(ty)::value>(r, sh.chunk, stage, st);
     });
 }
 
 template <typename T, int D>
-hipError_t stage_slab_d(const RunDev &r, const lbw_launch &l, int stage, int v_lo, int v_hi,
-                        hipStream_t st) {
+hipError_t one_stage_d(const RunDev &r, const lbw_launch &l, int stage, hipStream_t st) {
     switch (r.scheme) {
-        case LBW_WENO5: return stage_slab_shape<T, D, LBW_WENO5>(r, l, stage, v_lo, v_hi, st);
-        case LBW_WENO3: return stage_slab_shape<T, D, LBW_WENO3>(r, l, stage, v_lo, v_hi, st);
-        case LBW_UPWIND1: return stage_slab_shape<T, D, LBW_UPWIND1>(r, l, stage, v_lo, v_hi, st);
+        case LBW_WENO5: return one_stage_shape<T, D, LBW_WENO5>(r, l, stage, st);
+        case LBW_WENO3: return one_stage_shape<T, D, LBW_WENO3>(r, l, stage, st);
+        case LBW_UPWIND1: return one_stage_shape<T, D, LBW_UPWIND1>(r, l, stage, st);
     }
     return hipErrorInvalidValue;
 }

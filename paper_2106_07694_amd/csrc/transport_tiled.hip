@@ -30,14 +30,12 @@ hipError_t launch_transport_tiled(int dim, int precision, const RunDev &r, const
     return tiled_any<false>(dim, precision, r, l, st, nullptr);
 }
 
-hipError_t launch_stage_slab(int dim, int precision, const RunDev &r, const lbw_launch &l,
-                             int stage, int v_lo, int v_hi, hipStream_t st) {
-    if (r.vs_s != 0.0) return hipErrorInvalidValue;   // such runs take the sequential order
+hipError_t launch_one_stage(int dim, int precision, const RunDev &r, const lbw_launch &l,
+                            int stage, hipStream_t st) {
+    if (r.vs_s != 0.0) return hipErrorInvalidValue;   // built for a constant settling speed
     if (precision == LBW_FP32_SHIFTED)
-        return dim == 2 ? stage_slab_d<float, 2>(r, l, stage, v_lo, v_hi, st)
-                        : stage_slab_d<float, 3>(r, l, stage, v_lo, v_hi, st);
-    return dim == 2 ? stage_slab_d<double, 2>(r, l, stage, v_lo, v_hi, st)
-                    : stage_slab_d<double, 3>(r, l, stage, v_lo, v_hi, st);
+        return dim == 2 ? one_stage_d<float, 2>(r, l, stage, st) : one_stage_d<float, 3>(r, l, stage, st);
+    return dim == 2 ? one_stage_d<double, 2>(r, l, stage, st) : one_stage_d<double, 3>(r, l, stage, st);
 }
 
 hipError_t launch_transport_batched(int dim, int precision, const BatchArgs &b, const lbw_launch &l,
