@@ -218,7 +218,7 @@ def run_gpu(wl, steps: int, warmup: int, diagnostics: bool = True, tuned_as=None
                              "ms": cs_ms, "alg_bytes_per_cell": ab["collide_stream"],
                              "traffic": cs_traffic, "cells_per_launch": cells},
                          "transport": {
-                             "bound": "valu (close to vector-issue bound)", "achieved": tr_gbs,
+                             "bound": "valu (vector-issue bound at the power-limited clock)", "achieved": tr_gbs,
                              "frac": tr_gbs / HBM_PEAK_GBS, "ms": tr_ms, "launches": 3,
                              "alg_bytes_per_cell": ab["transport"], "traffic": tr_traffic}}},
         "particle_budget": mass,
