@@ -9,7 +9,9 @@
 //     into LDS and differenced by the two cells that share it;
 //   * each thread keeps its own column's six-node vertical stencil of a and
 //     of the vertical transport velocity in registers, computes the face
-//     above its cell and carries it down as the face below the next cell;
+//     above its cell and carries it down as the face below the next cell
+//     (3D, single precision, WENO5: the stencil's node data instead, each
+//     node's flux and indicators computed once, as the node enters);
 //   * the next plane's global loads are issued before the current plane is
 //     computed (software pipelining).
 // Arithmetic and wall rules are those of the plain kernels (transport.hip):
@@ -95,6 +97,50 @@ __device__ __forceinline__ T face6(T a0, T a1, T a2, T a3, T a4, T a5, T w0, T w
     return hh - kappa * (a3 - a2);
 }
 
+// WENO5 with the work of each node done once (the arithmetic of weno5_rcp
+// regrouped by node).  Node m is the centre of three sub-stencils that faces
+// read: with t = a_{m+1} - 2 a_m + a_{m-1} and c = a_{m+1} - a_{m-1}, their
+// scaled indicators are
+//   e_c = t^2 + (3/13) c^2 + eps12        (the face's centre sub-stencil),
+//   e_l = e_c + (12/13) t (t + c)          (one-sided difference 2t + c, at m+1),
+//   e_r = e_c + (12/13) t (t - c)          (one-sided difference 2t - c, at m-1),
+// the last two being t^2 + (3/13)(2t +- c)^2 + eps12 expanded (each stays
+// within a few units in the last place of its value: e_l, e_r >= t^2 + eps12
+// and the cancelling part is at most 2 t^2).  A face takes three of them and
+// five node fluxes h = w a, chosen by its upwind side.  Contraction is pinned
+// per expression, so every kernel that inlines these gives the same bits.
+template <typename T>
+__device__ __forceinline__ void weno5_node(T dl, T dr, T eps12, T &el, T &ec, T &er) {
+#pragma clang fp contract(on)
+    const T t = dr - dl, c = dr + dl;            // dl = a_m - a_{m-1}, dr = a_{m+1} - a_m
+    ec = t * t + ((T)(3.0 / 13.0) * c * c + eps12);
+    const T kt = (T)(12.0 / 13.0) * t;
+    el = kt * (t + c) + ec;
+    er = kt * (t - c) + ec;
+}
+
+// Total flux through face j+1/2 from node data: fluxes h at j-2 .. j+3, e_l
+// at j-1 and j, e_c at j and j+1, e_r at j+1 and j+2, the upwind side (pos:
+// the face velocity w_j + w_{j+1} >= 0) and d = a_{j+1} - a_j for diffusion.
+// Upwind from j the sub-stencils are centred at j-1 (as the upwind-most), j,
+// j+1 (as the downwind-most); upwind from j+1 at j+2, j+1, j, mirrored.
+template <typename T>
+__device__ __forceinline__ T weno5_flux_nodes(bool pos, T h0, T h1, T h2, T h3, T h4, T h5,
+                                              T el_jm1, T el_j, T ec_j, T ec_jp1, T er_jp1,
+                                              T er_jp2, T d, T kappa) {
+#pragma clang fp contract(on)
+    const T H0 = pos ? h0 : h5, H1 = pos ? h1 : h4, H2 = pos ? h2 : h3, H3 = pos ? h3 : h2,
+            H4 = pos ? h4 : h1;
+    const T e0 = pos ? el_jm1 : er_jp2, e1 = pos ? ec_j : ec_jp1, e2 = pos ? er_jp1 : el_j;
+    const T S0 = e0 * e0, S1 = e1 * e1, S2 = e2 * e2;
+    const T P = S1 * S2, Q = S0 * S2, R = S0 * S1;
+    const T q0 = (T)(1.0 / 3.0) * H0 - (T)(7.0 / 6.0) * H1 + (T)(11.0 / 6.0) * H2;
+    const T q1 = (T)5 * H2 - H1 + (T)2 * H3;
+    const T q2 = H2 + (T)2.5 * H3 - (T)0.5 * H4;
+    const T hh = (P * q0 + Q * q1 + R * q2) * fast_rcp<T>(P + (T)6 * Q + (T)3 * R);
+    return hh - kappa * d;
+}
+
 struct TileGeom {
     int nx, ny, nv;     // lateral sizes (ny = 1 in 2D) and vertical extent
     int64_t sv;         // stride of the vertical axis
@@ -154,16 +200,34 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
     constexpr int NT = TX * TY;
     constexpr int AX = TX + 6;                  // a plane row length (x halo 3 + 3)
     constexpr int AY = (D == 3) ? TY + 6 : 1;   // a plane rows
-    __shared__ T sA[AY * AX];
-    __shared__ T sUx[TY * AX];
-    __shared__ T sUy[(D == 3) ? (TY + 6) * TX : 1];
-    __shared__ T sFx[TY * (TX + 1)];
-    __shared__ T sFy[(D == 3) ? (TY + 1) * TX : 1];
+    // NV (3D, single precision, WENO5): the vertical faces share each node's
+    // work (its flux w a and the three indicators it centres, weno5_node),
+    // done once as the node enters the column's window; the fluxes and
+    // differences stay in registers, the indicators in a per-thread LDS ring
+    // (in registers they would cost a block of occupancy).  The lateral faces
+    // keep face6: shared node data there needs an extra LDS round trip and
+    // barrier per plane, which cost more than the arithmetic saves, and 2D
+    // tiles wait on their barriers and loads rather than on instruction issue.
+    constexpr bool NV = (SCHEME == LBW_WENO5 && D == 3 && sizeof(T) == 4);
     constexpr int SXL = TX + 2;                         // S row with a one-cell x halo
     constexpr int SYL = (D == 3) ? TY + 2 : 1;          // S rows (one-cell y halo in 3D)
-    __shared__ T sS[FS ? SXL * SYL : 1];
-    __shared__ T sGx[FS ? TY * (TX + 1) : 1];           // S face fluxes
-    __shared__ T sGy[(FS && D == 3) ? (TY + 1) * TX : 1];
+    // The LDS arrays are pieces of one allocation at fixed offsets, so that
+    // accesses which share a lane-dependent index can share one address
+    // register and differ only in the instruction's constant offset.
+    constexpr int O_A = 0, O_UX = AY * AX, O_UY = O_UX + TY * AX,
+                  O_FX = O_UY + ((D == 3) ? (TY + 6) * TX : 1), O_FY = O_FX + TY * (TX + 1),
+                  O_S = O_FY + ((D == 3) ? (TY + 1) * TX : 1), O_GX = O_S + (FS ? SXL * SYL : 1),
+                  O_GY = O_GX + (FS ? TY * (TX + 1) : 1),
+                  O_END = O_GY + ((FS && D == 3) ? (TY + 1) * TX : 1);
+    __shared__ T smem[O_END];
+    T *const sA = smem + O_A;                   // stage input a, plane with halos
+    T *const sUx = smem + O_UX;                 // x velocity, rows with x halo
+    T *const sUy = smem + O_UY;                 // y velocity, columns with y halo
+    T *const sFx = smem + O_FX;                 // x face fluxes
+    T *const sFy = smem + O_FY;                 // y face fluxes
+    T *const sS = smem + O_S;                   // S plane with a one-cell halo
+    T *const sGx = smem + O_GX;                 // S face fluxes
+    T *const sGy = smem + O_GY;
 
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
@@ -290,25 +354,72 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
         return hh - kaps * (a3 - a2);
     };
 
-    // faces on the far edges of the tile (x faces of column TX, y faces of
-    // row TY), taken by the first lanes in one extra pass with strided LDS
-    // reads, so that the main passes are exactly one face per thread
-    constexpr int NEX = (D == 3) ? TY + TX : 1;
+    constexpr int NEX = (D == 3) ? TX + TY : 1;   // faces on the tile's far edges
 
-    // vertical windows: a and w at v-2 .. v+3 for the face above v
+    // vertical windows for the face above v: a and w at v-2 .. v+3 (face6),
+    // or (NV) the node data of the same nodes: fluxes vH at v-2 .. v+3, the
+    // indicators e_l, e_c, e_r of nodes v-1 .. v+2 (EL, EC, ER), and for the
+    // faces j+1/2, j = v .. v+2, the upwind side vP (w_j + w_{j+1} >= 0) and
+    // the difference vD = a_{j+1} - a_j (a face's slot is its lower node's);
+    // a_last, w_last hold node v+3
+    const T eps12 = (T)(12.0 / 13.0) * eps;
     T aw[6], ww[6];
+    T vH[6], vD[6];
+    // the indicators of the window's nodes, per thread in LDS (six-slot rings
+    // that rotate like the window; each thread reads only what it wrote)
+    __shared__ T sE[NV ? 18 * NT : 1];
+    auto EL = [&](int slot) -> T & { return sE[(0 * 6 + slot) * NT + tid]; };
+    auto EC = [&](int slot) -> T & { return sE[(1 * 6 + slot) * NT + tid]; };
+    auto ER = [&](int slot) -> T & { return sE[(2 * 6 + slot) * NT + tid]; };
+    bool vP[6];
+    T a_last = (T)0, w_last = (T)0, a_first;
+    T fbelow;                                       // face below the first plane
+    if constexpr (NV) {
+        T an[7], wn[7], hn[7], dn[6], sn[6], ln[7], cn[7], rn[7];   // nodes v0-3 .. v0+3
 #pragma unroll
-    for (int m = 0; m < 6; ++m) load_av(v0 - 2 + m, aw[m], ww[m]);
-    // face below the first plane
-    T fbelow;
-    if (walls && v0 == 0) {
-        fbelow = -vs_at(0) * aw[2];                 // absorbing bottom
+        for (int k = 0; k < 7; ++k) {
+            load_av(v0 - 3 + k, an[k], wn[k]);
+            hn[k] = wn[k] * an[k];
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            dn[k] = an[k + 1] - an[k];
+            sn[k] = wn[k] + wn[k + 1];
+        }
+#pragma unroll
+        for (int k = 1; k < 6; ++k) weno5_node<T>(dn[k - 1], dn[k], eps12, ln[k], cn[k], rn[k]);
+        // window position m is node v0-2+m, index k = m+1 here
+#pragma unroll
+        for (int m = 0; m < 6; ++m) vH[m] = hn[m + 1];
+#pragma unroll
+        for (int m = 1; m < 5; ++m) {
+            EL(m) = ln[m + 1];
+            EC(m) = cn[m + 1];
+            ER(m) = rn[m + 1];
+        }
+#pragma unroll
+        for (int m = 2; m < 5; ++m) {
+            vP[m] = sn[m + 1] >= (T)0;
+            vD[m] = dn[m + 1];
+        }
+        a_last = an[6];
+        w_last = wn[6];
+        a_first = an[3];
+        if (!(walls && v0 == 0))
+            fbelow = weno5_flux_nodes<T>(sn[2] >= (T)0, hn[0], hn[1], hn[2], hn[3], hn[4], hn[5], ln[1],
+                                         ln[2], cn[2], cn[3], rn[3], rn[4], dn[2], kap);
     } else {
-        T ab, wb;
-        load_av(v0 - 3, ab, wb);
-        fbelow = face6<T, SCHEME>(ab, aw[0], aw[1], aw[2], aw[3], aw[4], wb, ww[0], ww[1], ww[2],
-                                  ww[3], ww[4], kap, eps);
+#pragma unroll
+        for (int m = 0; m < 6; ++m) load_av(v0 - 2 + m, aw[m], ww[m]);
+        a_first = aw[2];
+        if (!(walls && v0 == 0)) {
+            T ab, wb;
+            load_av(v0 - 3, ab, wb);
+            fbelow = face6<T, SCHEME>(ab, aw[0], aw[1], aw[2], aw[3], aw[4], wb, ww[0], ww[1], ww[2],
+                                      ww[3], ww[4], kap, eps);
+        }
     }
+    if (walls && v0 == 0) fbelow = -vs_at(0) * a_first;   // absorbing bottom
 
     // S and the raw vertical velocity at this plane of the column, and the S
     // face below the first plane (closed walls; periodic: wrapped)
@@ -332,7 +443,7 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
                 VSS ? r.vs * (1.0 - r.vs_s * (double)at<T>(plane(r.s, 0), colb)) : r.vs;
             const double o0 = vsd * (double)at<T>(plane(r.c, 0), colb);
             const double o1 = vsd * (double)at<T>(plane(r.c1, 0), colb);
-            const double o2 = vsd * (double)aw[2];
+            const double o2 = vsd * (double)a_first;
             r.dep[col] += o0 / 6.0 + o1 / 6.0 + 2.0 / 3.0 * o2;
         }
     }
@@ -413,13 +524,16 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
             }
             prefetch(v + 1);
 
-            // lateral faces: each thread the x face on the left of its cell and
-            // (3D) the y face below it
+            // each thread the x face on the left of its cell and (3D) the y
+            // face below it; the stage input at the cell is the x stencil's
+            // fourth node
+            T a_own;
             {
                 const T *ar = sA + ((D == 3) ? (ty + 3) : 0) * AX + tx;   // nodes tx-3 .. tx+2
                 const T *ur = sUx + ty * AX + tx;
                 sFx[ty * (TX + 1) + tx] = face6<T, SCHEME>(ar[0], ar[1], ar[2], ar[3], ar[4], ar[5], ur[0],
                                                             ur[1], ur[2], ur[3], ur[4], ur[5], kap, eps);
+                a_own = ar[3];
             }
             if constexpr (D == 3) {
                 const T *ac = sA + ty * AX + tx + 3;      // rows ty-3+3 .. ty+2+3 of column tx
@@ -439,46 +553,59 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
                     sGy[ty * TX + tx] = sface(sc[0], sc[SXL], uc[0], uc[TX]);
                 }
             }
-            for (int e = tid; e < NEX; e += NT) {
-                const bool xf = e < TY;                   // x face of column TX, row e
-                const int fy = xf ? e : TY, fx = xf ? TX : e - TY;
-                const T *ar = xf ? sA + ((D == 3) ? (fy + 3) : 0) * AX + fx : sA + fx + 3;
-                const T *ur = xf ? sUx + fy * AX + fx : sUy + fx;
-                const int sa = xf ? 1 : AX, su = xf ? 1 : TX;
+            // faces on the far edges of the tile, taken by the first lanes in
+            // one extra pass, so that the main passes are exactly one face
+            // per thread: (3D) the y faces of row TY first, so that they
+            // fill whole waves (a lane with tid < TX has ty = 0 and tx = tid,
+            // so their addresses are the main pass's plus a constant), then
+            // the x faces of column TX
+            static_assert(NEX <= NT, "one pass of edge faces");
+            if (D == 3 && tid < TX) {
                 if constexpr (D == 3) {
-                    if (!xf) { ar += fy * AX; ur += fy * TX; }
-                }
-                const T f = face6<T, SCHEME>(ar[0], ar[sa], ar[2 * sa], ar[3 * sa], ar[4 * sa], ar[5 * sa],
-                                             ur[0], ur[su], ur[2 * su], ur[3 * su], ur[4 * su], ur[5 * su],
-                                             kap, eps);
-                if (xf) sFx[fy * (TX + 1) + fx] = f;
-                else if constexpr (D == 3) sFy[fy * TX + fx] = f;
-                if constexpr (FS) {
-                    if (xf) {
-                        const T *sr = sS + ((D == 3) ? fy + 1 : 0) * SXL + TX;
-                        const T *ur2 = sUx + fy * AX + TX + 2;
-                        sGx[fy * (TX + 1) + TX] = sface(sr[0], sr[1], ur2[0], ur2[1]);
-                    } else if constexpr (D == 3) {
-                        const T *sc = sS + TY * SXL + fx + 1;
-                        const T *uc = sUy + (TY + 2) * TX + fx;
-                        sGy[TY * TX + fx] = sface(sc[0], sc[SXL], uc[0], uc[TX]);
+                    const T *ac = sA + (ty + TY) * AX + tx + 3;
+                    const T *uc = sUy + (ty + TY) * TX + tx;
+                    sFy[(ty + TY) * TX + tx] = face6<T, SCHEME>(ac[0], ac[AX], ac[2 * AX], ac[3 * AX],
+                                                                ac[4 * AX], ac[5 * AX], uc[0], uc[TX],
+                                                                uc[2 * TX], uc[3 * TX], uc[4 * TX],
+                                                                uc[5 * TX], kap, eps);
+                    if constexpr (FS) {
+                        const T *sc = sS + (ty + TY) * SXL + tx + 1;
+                        const T *uc2 = sUy + (ty + TY + 2) * TX + tx;
+                        sGy[(ty + TY) * TX + tx] = sface(sc[0], sc[SXL], uc2[0], uc2[TX]);
                     }
+                }
+            } else if (tid < NEX) {
+                const int fy = tid - ((D == 3) ? TX : 0);
+                const T *ar = sA + ((D == 3) ? (fy + 3) : 0) * AX + TX;
+                const T *ur = sUx + fy * AX + TX;
+                sFx[fy * (TX + 1) + TX] = face6<T, SCHEME>(ar[0], ar[1], ar[2], ar[3], ar[4], ar[5], ur[0],
+                                                           ur[1], ur[2], ur[3], ur[4], ur[5], kap, eps);
+                if constexpr (FS) {
+                    const T *sr = sS + ((D == 3) ? fy + 1 : 0) * SXL + TX;
+                    const T *ur2 = sUx + fy * AX + TX + 2;
+                    sGx[fy * (TX + 1) + TX] = sface(sr[0], sr[1], ur2[0], ur2[1]);
                 }
             }
             // vertical face above this cell
             T fabove;
-            if (walls && v == g.nv - 1)
+            if (walls && v == g.nv - 1) {
                 fabove = (T)0;
-            else
+            } else if constexpr (NV) {
+                auto S6 = [&](int m) { return (ph + m) % 6; };
+                fabove = weno5_flux_nodes<T>(vP[S6(2)], vH[S6(0)], vH[S6(1)], vH[S6(2)],
+                                             vH[S6(3)], vH[S6(4)], vH[S6(5)], EL(S6(1)), EL(S6(2)),
+                                             EC(S6(2)), EC(S6(3)), ER(S6(3)), ER(S6(4)), vD[S6(2)], kap);
+            } else {
                 fabove = face6<T, SCHEME>(A(0), A(1), A(2), A(3), A(4), A(5), W(0), W(1), W(2), W(3),
                                           W(4), W(5), kap, eps);
+            }
             T gabove = (T)0;
             if constexpr (FS) gabove = (walls && v == g.nv - 1) ? (T)0 : sface(s_c, s_n, us_c, us_n);
             __syncthreads();
             T L = -(fabove - fbelow);
             L -= sFx[ty * (TX + 1) + tx + 1] - sFx[ty * (TX + 1) + tx];
             if constexpr (D == 3) L -= sFy[(ty + 1) * TX + tx] - sFy[ty * TX + tx];
-            const T a = A(2);
+            const T a = a_own;
             if (active) {
                 if constexpr (STAGE == 1) {
                     *(T *)((char *)wplane(r.c1, v) + colb) = a + L;
@@ -498,9 +625,26 @@ __device__ __forceinline__ void stage_tile(const RunDev &r, const TileGeom &g, i
                 us_c = us_n;
             }
             fbelow = fabove;
-            A(0) = anext;                     // position 0 leaves, node v + 4 enters
-            W(0) = wnext;
-            __syncthreads();
+            // node v + 4 enters, position 0 leaves
+            if constexpr (NV) {
+                const T dnew = anext - a_last;
+                T el, ec, er;
+                weno5_node<T>(vD[(ph + 4) % 6], dnew, eps12, el, ec, er);
+                EL((ph + 5) % 6) = el;
+                EC((ph + 5) % 6) = ec;
+                ER((ph + 5) % 6) = er;
+                vD[(ph + 5) % 6] = dnew;
+                vP[(ph + 5) % 6] = (w_last + wnext) >= (T)0;
+                vH[ph % 6] = wnext * anext;
+                a_last = anext;
+                w_last = wnext;
+            } else {
+                A(0) = anext;
+                W(0) = wnext;
+            }
+            // no barrier here: the next plane's publication writes arrays
+            // last read before the barrier above, and the face arrays read
+            // since are next written after that plane's own first barrier
         }
     }
 }
