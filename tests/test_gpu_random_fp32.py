@@ -73,10 +73,10 @@ def _layer(cfg, rng, scale):
 
 def _smooth_velocity(cfg, rng, amp=0.02):
     """Frozen velocity of one random Fourier mode per component (|u| <= amp).
-    White-noise velocities compress C at every node; the oracle's own FP64
-    output then moves by 1e-10 for a one-ulp input change within ten steps,
-    and FP32 rounding is amplified alike, so they test the input's
-    conditioning rather than the kernels."""
+    White-noise velocities compress C at every node and amplify rounding
+    tenfold every two steps (the FP64 GPU path and the oracle, differing only
+    in rounding order, end 7e-11 apart after eleven steps; FP32 up to 3e-3),
+    so they would test the input's conditioning rather than the kernels."""
     nz, ny, nx = cfg.shape
     z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     comps = []
