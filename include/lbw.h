@@ -182,6 +182,9 @@ typedef struct lbw_handle lbw_handle;
  * kappa above the explicit-diffusion limit 1/(2 dim), |u_top| or vs above the
  * CFL bound (S7), weno_eps <= 0, NULL required buffers, and, when nbatch > 1,
  * runs of different lattice, precision, fluid mode, scheme or S option.
+ * A run may hold up to 2^32 - 1024 cells (the per-cell kernels launch one
+ * work-item per cell), with fewer than 2^29 cells in a horizontal plane
+ * (lanes address a plane with 32-bit byte offsets).
  * Host memory only (freed by lbw_destroy).  *out is NULL on failure. */
 int lbw_create(const lbw_config *cfgs, const lbw_buffers *bufs, int32_t nbatch,
                void *stream, lbw_handle **out);

@@ -191,7 +191,11 @@ int validate(const lbw_config &c, const lbw_buffers &b, int idx) {
     const int64_t lateral = dim == 2 ? (int64_t)c.nx : (int64_t)c.nx * c.ny;
     if (lateral * 8 >= ((int64_t)1 << 32))
         return fail(LBW_ERR_INVAL, "run %d: a horizontal plane must hold fewer than 2^29 cells", idx);
-    if (N * (int64_t)c.lattice > (int64_t)1 << 40) return fail(LBW_ERR_INVAL, "run %d: grid too large", idx);
+    // the per-node kernels launch one work-item per cell, and a dispatch
+    // holds fewer than 2^32 work-items
+    if (N > ((int64_t)1 << 32) - 1024)
+        return fail(LBW_ERR_INVAL, "run %d: grid too large (%lld cells; at most 2^32 - 1024)", idx,
+                    (long long)N);
     if (c.fluid_mode != LBW_FLUID_LBM && c.fluid_mode != LBW_FLUID_FROZEN)
         return fail(LBW_ERR_INVAL, "run %d: unknown fluid mode", idx);
     if (c.scheme_c != LBW_WENO5 && c.scheme_c != LBW_WENO3 && c.scheme_c != LBW_UPWIND1)

@@ -96,6 +96,8 @@ def test_valid_config_creates():
     (dict(u_top=(2.0, 0, 0)), "lid"),
     (dict(nx=0), "grid"),
     (dict(lattice=19, nx=32768, ny=16384, nz=6), "horizontal plane"),
+    (dict(lattice=19, nx=4096, ny=1024, nz=1025), "grid too large"),
+    (dict(nx=65536, ny=65536), "grid too large"),
     (dict(n_classes=2, vs=1e-3, vs_class=(1e-3, 2e-3), kappa_class=(0.0, 0.0)), "vs_class"),
     (dict(n_classes=2, vs_class=(1e-3, 2.0), kappa_class=(0.0, 0.0)), "vs_class[1]"),
     (dict(n_classes=3, vs_class=(0.0,) * 3, kappa_class=(0.0, 0.0, 0.3)), "kappa_class[2]"),
