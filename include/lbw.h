@@ -268,9 +268,9 @@ int lbw_replay(lbw_handle *h, int32_t run, int32_t n, void *const *c_out, void *
  * LBW_ERR_NONFINITE if any sum is NaN or Inf (the values are still written). */
 int lbw_reduce(lbw_handle *h, int32_t what, double *out_host);
 
-/* lbw_reduce for callers that cannot allocate device memory (code under
- * HIP graph capture, serving loops, harnesses that forbid allocation): the
- * same sums, bit for bit, with the partial sums kept in a device array the
+/* lbw_reduce for callers that cannot allocate device memory (serving loops,
+ * harnesses that forbid allocation, code that runs between graph replays):
+ * the same sums, bit for bit, with the partial sums kept in a device array the
  * library holds itself instead of the scratch passed at creation, which may
  * then be NULL.  That array is static: 128 * 256 + 128 doubles (263,168
  * bytes) on every device the library runs on, held until the process ends,
@@ -280,7 +280,8 @@ int lbw_reduce(lbw_handle *h, int32_t what, double *out_host);
  * sums in it; each call writes every value it reads, so no clearing is
  * needed, but calls that overlap on one device (other threads, other
  * handles) race and must be serialised by the caller.  Synchronises the
- * stream; LBW_ERR_NONFINITE as lbw_reduce. */
+ * stream (so it cannot itself be recorded into a graph); LBW_ERR_NONFINITE
+ * as lbw_reduce. */
 int lbw_reduce_static(lbw_handle *h, int32_t what, double *out_host);
 
 /* The sums of lbw_reduce for one particle size class, per run, into
