@@ -122,8 +122,9 @@ def test_batched_fp64_matches_oracle():
 
 @pytest.mark.parametrize("nbatch", [1, 4])
 def test_graph_replay_matches_eager(nbatch):
-    """Capture two steps, replay repeatedly (odd counts too), interleaved with
-    eager work and syncs; every replay must equal the eager reference."""
+    """Capture two steps, replay repeatedly (odd counts, a single step and no
+    step too), interleaved with eager work and syncs; every replay must equal
+    the eager reference."""
     import torch
     cfgs = _runs("fp32_shifted", has_s=True, n=nbatch)
     side = torch.cuda.Stream()
@@ -132,7 +133,7 @@ def test_graph_replay_matches_eager(nbatch):
     _setup(ref, cfgs)
     _setup(gra, cfgs)
     gra.set_launch(graph=1)
-    for rep, n in enumerate((4, 2, 5, 6, 3)):
+    for rep, n in enumerate((4, 2, 0, 5, 1, 6, 3)):
         ref.step(n)
         gra.step(n)
         torch.cuda.synchronize()
