@@ -17,6 +17,8 @@ tests/test_gpu_fp32.py.
 The workloads' physics and launch (the tuned launch bench.py times) on
   3D: 1024 x 1024 x 2049 = 2^31 + 2^20 cells, 215 GB of device memory;
   2D with S: 65536 x 32769 = 2^31 + 2^16 cells, 138 GB;
+  2D with S: 536870400 x 6 (a plane of 2^29 - 512 cells, just under the
+  limit, over the minimal height), 3.2e9 cells, 206 GB;
 each from the seeded tanh-layer state (C noise of amplitude 1e-3) plus a
 smooth initial velocity of amplitude 0.02 that varies along every axis.
 """
@@ -40,6 +42,9 @@ STEPS = 2
 CASES = {
     "3d_1024x1024x2049": (W.C3, (1024, 1024), (64, 64), 2049),
     "2d_s_65536x32769": (W.C2, (65536, 1), (512, 1), 32769),
+    # the widest plane a run may have (lanes address a plane with 32-bit byte
+    # offsets, here up to 2^31 - 2048) over the minimal height
+    "2d_s_536870400x6": (W.C2, (536870400, 1), (512, 1), 6),
 }
 
 
