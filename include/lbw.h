@@ -199,12 +199,16 @@ int lbw_get_launch(const lbw_handle *h, lbw_launch *launch);
 
 /* Populations of run `run` <- equilibrium at density rho[N] and velocity
  * u[dim][N] (device arrays of the run's element type; NULL means rho = 1,
- * u = 0), the initial state of section 2.2 (fluid at rest).  Resets the
- * in-place streaming parity.  Asynchronous on the handle's stream. */
+ * u = 0), the initial state of section 2.2 (fluid at rest).  Written in the
+ * layout the current in-place streaming parity expects (as lbw_import does),
+ * so it may be called after any number of steps.  Asynchronous on the
+ * handle's stream. */
 int lbw_init_equilibrium(lbw_handle *h, int32_t run, const void *rho, const void *u);
 
-/* Advance every run by nsteps coupled steps (nsteps >= 0).  Asynchronous on
- * the handle's stream; no host synchronisation, no allocation. */
+/* Advance every run by nsteps coupled steps (nsteps >= 0; 0 does nothing).
+ * Asynchronous on the handle's stream; no host synchronisation, no
+ * allocation.  If a launch fails (LBW_ERR_HIP) the runs' state is undefined:
+ * import or re-initialise it before stepping again. */
 int lbw_step(lbw_handle *h, int32_t nsteps);
 
 /* Number of steps taken since creation or the last import of populations. */
