@@ -211,7 +211,7 @@ int lbw_init_equilibrium(lbw_handle *h, int32_t run, const void *rho, const void
  * import or re-initialise it before stepping again. */
 int lbw_step(lbw_handle *h, int32_t nsteps);
 
-/* Number of steps taken since creation or the last import of populations. */
+/* Number of steps taken since creation (imports do not change it). */
 int lbw_steps_done(const lbw_handle *h, int64_t *out);
 
 /* Copy field `field` of run `run` in canonical layout into the device buffer
