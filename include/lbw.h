@@ -223,8 +223,9 @@ int lbw_steps_done(const lbw_handle *h, int64_t *out);
 int lbw_export(lbw_handle *h, int32_t run, int32_t field, void *dst);
 
 /* Overwrite field `field` of run `run` from the canonical device buffer src
- * (same layouts as lbw_export).  Importing populations resets the streaming
- * parity and the step counter.  A state exported after an even number of
+ * (same layouts as lbw_export).  Populations are written in the layout the
+ * current in-place streaming parity expects; the parity and the step counter
+ * are unchanged.  A state exported after an even number of
  * steps and imported into a fresh handle continues bit for bit as the
  * uninterrupted run; after an odd number the two continue with different
  * kernels of the in-place pair and agree to rounding.  Asynchronous on the
