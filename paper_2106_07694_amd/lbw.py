@@ -304,8 +304,32 @@ class Solver:
         self.stream.synchronize()
         return y
 
+    def _shape(self, name, run):
+        c = self.cfgs[run]
+        return {"f": (c.lattice, *c.shape), "c": c.c_shape, "s": c.shape, "u": (c.dim, *c.shape),
+                "deposit": c.deposit_shape, "stage1": c.c_shape, "stage2": c.c_shape,
+                "rho": c.shape}[name]
+
+    def _checked(self, name, t, run):
+        """t as a device buffer of field `name`: the library reads or writes
+        exactly that field's bytes through the pointer, so a tensor of another
+        size or element type, not contiguous or not on the device is refused."""
+        import torch
+        want = torch.float64 if name == "deposit" else self.dtype
+        n = int(np.prod(self._shape(name, run)))
+        if t.dtype != want:
+            raise ValueError(f"{name}: element type {t.dtype}, the run stores {want}")
+        if t.numel() != n:
+            raise ValueError(f"{name}: {t.numel()} values, the field holds {n}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name}: the tensor is not contiguous")
+        if t.device.type != "cuda":
+            raise ValueError(f"{name}: the tensor is on {t.device}, not on the device")
+        return t
+
     def init_equilibrium(self, run=0, rho=None, u=None):
-        keep = [self._dev(rho) if rho is not None else None, self._dev(u) if u is not None else None]
+        keep = [self._checked("rho", self._dev(rho), run) if rho is not None else None,
+                self._checked("u", self._dev(u), run) if u is not None else None]
         check(self._lib.lbw_init_equilibrium(
             self._h, run, keep[0].data_ptr() if keep[0] is not None else None,
             keep[1].data_ptr() if keep[1] is not None else None))
@@ -315,7 +339,7 @@ class Solver:
         fid = self._FIELDS[name]
         import torch
         dt = torch.float64 if name == "deposit" else None
-        src = self._dev(value, dt)
+        src = self._checked(name, self._dev(value, dt), run)
         check(self._lib.lbw_import(self._h, run, fid, src.data_ptr()))
         self.stream.synchronize()
 
@@ -339,12 +363,14 @@ class Solver:
     def export_into(self, name, out, run=0):
         """Canonical copy of a field into an existing device tensor, ordered on
         the solver's stream (no host synchronisation)."""
-        check(self._lib.lbw_export(self._h, run, self._FIELDS[name], out.data_ptr()))
+        check(self._lib.lbw_export(self._h, run, self._FIELDS[name],
+                                   self._checked(name, out, run).data_ptr()))
 
     def import_from(self, name, src, run=0):
         """Overwrite a field from a device tensor written on the solver's
         stream (no host synchronisation)."""
-        check(self._lib.lbw_import(self._h, run, self._FIELDS[name], src.data_ptr()))
+        check(self._lib.lbw_import(self._h, run, self._FIELDS[name],
+                                   self._checked(name, src, run).data_ptr()))
 
     def rebind(self, name, out=None, run=0):
         """Make the next steps write the per-step field `name` ("u", "rho",
@@ -354,7 +380,7 @@ class Solver:
         if not hasattr(self, "_bound"):
             self._bound = {}
         check(self._lib.lbw_rebind(self._h, run, self._FIELDS[name],
-                                   out.data_ptr() if out is not None else None))
+                                   self._checked(name, out, run).data_ptr() if out is not None else None))
         if out is None:
             self._bound.pop((run, name), None)
         else:

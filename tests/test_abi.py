@@ -248,3 +248,25 @@ def test_adjoint_wrapper_refuses_what_the_kernels_do_not_cover():
                 dict(n_classes=2, vs_class=(1e-3, 2e-3), kappa_class=(0.0, 0.0))):
         with pytest.raises(ValueError):
             adjoint.check_supported(lbw.RunConfig(**bad))
+
+
+def test_binding_refuses_buffers_of_the_wrong_size_type_or_place():
+    """The binding hands the library raw pointers to buffers it reads or
+    writes in full, so it refuses any tensor that is not exactly the field:
+    wrong element count, element type, layout or device (host logic only)."""
+    import torch
+
+    cfg = lbw.RunConfig(lattice=19, nx=8, ny=4, nz=6, precision="fp32_shifted")
+    sol = lbw.Solver.__new__(lbw.Solver)      # no device needed for the checks
+    sol.cfgs, sol.dtype = [cfg], torch.float32
+    n = cfg.cells
+    cases = [("c", torch.zeros(n + 1), "values"), ("f", torch.zeros(19 * n - 1), "values"),
+             ("c", torch.zeros(n, dtype=torch.float64), "element type"),
+             ("deposit", torch.zeros(cfg.ncol, dtype=torch.float32), "element type"),
+             ("rho", torch.zeros(n, dtype=torch.float64), "element type"),
+             ("u", torch.zeros(2, 3 * n)[0, :].view(3, n)[:, :].t().contiguous().t(), "contiguous"),
+             ("c", torch.zeros(n), "not on the device"),
+             ("deposit", torch.zeros(cfg.ncol, dtype=torch.float64), "not on the device")]
+    for name, t, reason in cases:
+        with pytest.raises(ValueError, match=reason):
+            sol._checked(name, t, 0)
