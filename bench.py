@@ -553,6 +553,10 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", choices=["3d", "2d"], default="3d")
+    ap.add_argument("--grid", type=int, nargs=3, metavar=("NX", "NY", "NZ"),
+                    help="time the main workload's physics on this grid instead (2D: NZ = 1), "
+                         "with that workload's tuned launch; the run must fit the device "
+                         "(3D FP32: 100 B per cell)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-also", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
@@ -603,9 +607,18 @@ def main() -> int:
         build.build()
 
     main_wl, other = (W.C3, W.C2) if args.workload == "3d" else (W.C2, W.C3)
+    base_wl = main_wl
+    if args.grid:
+        nx, ny, nz = args.grid
+        if (main_wl.dim == 2) != (nz == 1):
+            print("--grid: NZ must be 1 for the 2D workload and above 1 for the 3D one",
+                  file=sys.stderr)
+            return 2
+        size = f"{nx}x{ny}x{nz}" if main_wl.dim == 3 else f"{nx}x{ny}"
+        main_wl = main_wl.replace(name=f"{main_wl.name.rsplit('_', 1)[0]}_{size}", nx=nx, ny=ny, nz=nz)
     print(f"[bench] {main_wl.name}: warmup {args.warmup}, timing {args.steps} steps", file=sys.stderr,
           flush=True)
-    res = run_gpu(main_wl, args.steps, args.warmup)
+    res = run_gpu(main_wl, args.steps, args.warmup, tuned_as=base_wl)
     print(f"[bench] {main_wl.name}: {res['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
     also = None
     if not args.no_also:
@@ -672,9 +685,9 @@ def main() -> int:
         cs["frac_of_copy"] = cs["achieved"] / copy["gbs"]
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = (cpu_baseline(main_wl, nz_crop=128, ny_crop=0, steps=20, one_thread=(32, 0, 4))
-               if main_wl.dim == 3
-               else cpu_baseline(main_wl, nz_crop=0, ny_crop=2048, steps=40,
+        cpu = (cpu_baseline(base_wl, nz_crop=128, ny_crop=0, steps=20, one_thread=(32, 0, 4))
+               if base_wl.dim == 3
+               else cpu_baseline(base_wl, nz_crop=0, ny_crop=2048, steps=40,
                                  one_thread=(0, 256, 8)))
         print(f"[bench] cpu baseline: {cpu['value']:.2f} MLUPS on {cpu['cores']} cores, "
               f"{cpu.get('one_thread', {}).get('value', float('nan')):.2f} MLUPS on one",
