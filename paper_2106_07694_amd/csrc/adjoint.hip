@@ -686,10 +686,14 @@ hipError_t adjoint_t(const AdjDev &A, const lbw_launch &l, hipStream_t st) {
         if (e == hipSuccess) e = launch_one_stage(D, prec, fr, lt, 2, st);
         if (e != hipSuccess) return e;
     }
-    if (D == 2 && l.variant != 1) {
+    // the fused 2D form launches one block row per TY grid rows; a launch
+    // takes at most 65535 block rows, so taller runs take the two-kernel form
+    // (the same sums in the same order: the same bits)
+    constexpr int TX = sizeof(T) == 4 ? 32 : 16, TY = sizeof(T) == 4 ? 8 : 16;
+    const int64_t block_rows = ((int64_t)A.r.ny + TY - 1) / TY;
+    if (D == 2 && l.variant != 1 && block_rows <= 65535) {
         // one kernel per reversed stage, face products kept in LDS
-        constexpr int TX = sizeof(T) == 4 ? 32 : 16, TY = sizeof(T) == 4 ? 8 : 16;
-        const dim3 tg((unsigned)((A.r.nx + TX - 1) / TX), (unsigned)((A.r.ny + TY - 1) / TY));
+        const dim3 tg((unsigned)((A.r.nx + TX - 1) / TX), (unsigned)block_rows);
         k_adj_stage2d<T, SH, 3, TX, TY><<<tg, 256, 0, st>>>(A, (const T *)A.a2, (const T *)A.cbar_next, (T)(2.0 / 3.0));
         k_adj_stage2d<T, SH, 2, TX, TY><<<tg, 256, 0, st>>>(A, (const T *)A.a1, (const T *)A.abar2, (T)0.25);
         k_adj_stage2d<T, SH, 1, TX, TY><<<tg, 256, 0, st>>>(A, (const T *)A.c_n, (const T *)A.abar1, (T)1);

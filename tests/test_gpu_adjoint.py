@@ -419,3 +419,33 @@ def test_c5_configuration_gradient_against_finite_differences():
     assert res[1e-4][0] < 2e-2 and res[1e-4][1] < 2e-2, res
     _check_fd(res, 1e-5)
     assert l2 < 1e-3 and abs(g32[1] - g64[1]) < 1e-5 * abs(g64[1])
+
+
+def test_adjoint_step_on_a_grid_taller_than_one_launch_of_the_fused_form():
+    """The fused 2D reverse stages launch one block row per 16 grid rows (FP64),
+    at most 65535 of them; a run of 3 x 1,048,600 cells (65,538 block rows)
+    takes the two-kernel form instead, through the default launch, and must
+    still equal the oracle's reverse step."""
+    rng = np.random.default_rng(37)
+    cfg = lbw.RunConfig(lattice=9, precision="fp64", nx=3, ny=1_048_600, tau=0.7, vs=0.04,
+                        kappa_c=2e-3, gp_c=3e-3)
+    ocfg = oracle_cfg(cfg)
+    f_n, c_n, _ = _flowing(ocfg, rng)
+    fbar_next = rng.standard_normal((9,) + ocfg.shape)
+    cbar_next = rng.standard_normal(ocfg.shape)
+    dep_bar = 0.7
+    fo, co, vo = oracle.adjoint_step(ocfg, f_n, c_n, fbar_next, cbar_next, dep_bar, None)
+    sol = lbw.Solver(cfg)
+    fb = torch.zeros((9,) + ocfg.shape, dtype=torch.float64, device="cuda")
+    cb = torch.zeros(ocfg.shape, dtype=torch.float64, device="cuda")
+    vs = torch.zeros(1, dtype=torch.float64, device="cuda")
+    work = sol.adjoint_workspace()
+    torch.cuda.synchronize()
+    sol.adjoint_step(_dev(f_n), _dev(c_n), _dev(fbar_next), _dev(cbar_next), dep_bar, fb, cb, vs, work)
+    torch.cuda.synchronize()
+    vs_scale = float(np.sum(np.abs(cbar_next * c_n))) + dep_bar * float(np.sum(np.abs(c_n)))
+    errs = {"cbar": rel(cb.cpu().numpy(), co), "fbar": rel(fb.cpu().numpy(), fo),
+            "vs_bar": abs(vs.item() - vo) / max(abs(vo), vs_scale)}
+    print(f"\nadjoint step on 3 x 1,048,600: {errs}")
+    assert max(errs.values()) < 1e-12, errs
+    sol.close()
