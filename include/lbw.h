@@ -193,7 +193,9 @@ int lbw_create(const lbw_config *cfgs, const lbw_buffers *bufs, int32_t nbatch,
 void lbw_destroy(lbw_handle *h);
 
 /* Choose the kernels' launch shape (the autotuner's knob).  Zero fields keep
- * the defaults; invalid shapes are rejected with LBW_ERR_INVAL. */
+ * the defaults; invalid shapes are rejected with LBW_ERR_INVAL, and so is a
+ * shape whose tiled transport launch for a single run would need 2^32
+ * work-items or more (one block per tile and vertical chunk). */
 int lbw_set_launch(lbw_handle *h, const lbw_launch *launch);
 int lbw_get_launch(const lbw_handle *h, lbw_launch *launch);
 

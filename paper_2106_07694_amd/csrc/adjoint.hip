@@ -682,6 +682,9 @@ hipError_t adjoint_t(const AdjDev &A, const lbw_launch &l, hipStream_t st) {
         const int prec = sizeof(T) == 4 ? LBW_FP32_SHIFTED : LBW_FP64;
         lbw_launch lt = l;
         lt.variant = 0;
+        // one block per tile and chunk, fewer than 2^32 work-items a launch
+        const TileShape sh = resolve_tile_shape(D, lt);
+        if (transport_tiles(D, fr, lt) * sh.tx * sh.ty >= ((int64_t)1 << 32)) return hipErrorInvalidConfiguration;
         e = launch_one_stage(D, prec, fr, lt, 1, st);
         if (e == hipSuccess) e = launch_one_stage(D, prec, fr, lt, 2, st);
         if (e != hipSuccess) return e;

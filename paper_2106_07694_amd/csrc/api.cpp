@@ -276,6 +276,19 @@ lbw::RunDev make_run(const lbw_config &c, const lbw_buffers &b) {
     return r;
 }
 
+// A single run's tiled transport launches one block per tile and vertical
+// chunk, and a dispatch holds fewer than 2^32 work-items: a huge run with
+// short chunks and tiles that fit its lateral sizes badly could exceed that.
+int check_tile_launch(const lbw_handle *h, const lbw_launch &l) {
+    if (h->nbatch > 1 || l.variant == 1) return LBW_OK;   // persistent grid / one thread per node
+    const lbw::TileShape s = lbw::resolve_tile_shape(h->dim, l);
+    const int64_t items = lbw::transport_tiles(h->dim, h->run[0], l) * s.tx * s.ty;
+    if (items >= ((int64_t)1 << 32))
+        return fail(LBW_ERR_INVAL, "the transport launch would need %lld work-items (at most 2^32 - 1): "
+                                   "choose a longer vertical chunk (tile_y)", (long long)items);
+    return LBW_OK;
+}
+
 int check_run(const lbw_handle *h, int32_t run) {
     if (!h) return fail(LBW_ERR_INVAL, "NULL handle");
     if (run < 0 || run >= h->nbatch) return fail(LBW_ERR_INVAL, "run %d out of range [0, %d)", run, h->nbatch);
@@ -330,6 +343,10 @@ int lbw_create(const lbw_config *cfgs, const lbw_buffers *bufs, int32_t nbatch, 
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
         h->num_cu = ncu;
+    if (const int rc = check_tile_launch(h, h->launch)) {
+        delete h;
+        return rc;
+    }
     if (nbatch > 1) {
         const ScratchLayout L = scratch_layout(nbatch, count_views(cfgs, nbatch));
         if (!bufs[0].scratch || bufs[0].scratch_bytes < L.total) {
@@ -391,6 +408,7 @@ int lbw_set_launch(lbw_handle *h, const lbw_launch *l) {
     if (l->reserved != 0) return fail(LBW_ERR_INVAL, "reserved must be 0");
     if (l->graph < 0 || l->graph > 1) return fail(LBW_ERR_INVAL, "graph must be 0 or 1");
     n.graph = l->graph;
+    if (const int rc = check_tile_launch(h, n)) return rc;
     h->launch = n;
     release_graph(h);
     return upload_tables(h);

@@ -270,3 +270,23 @@ def test_binding_refuses_buffers_of_the_wrong_size_type_or_place():
     for name, t, reason in cases:
         with pytest.raises(ValueError, match=reason):
             sol._checked(name, t, 0)
+
+
+def test_tiled_launch_larger_than_one_dispatch_is_refused():
+    """A single run's tiled transport launches one block per tile and chunk;
+    a launch shape whose work-items would reach 2^32 (a huge run with
+    one-plane chunks and tiles that fit its lateral sizes badly) is refused
+    instead of dispatched."""
+    lib = lbw.load()
+    cfg = lbw.RunConfig(lattice=19, nx=33, ny=9, nz=14_000_000, precision="fp32_shifted")
+    c, b = cfg.to_c(), _fake_buffers(cfg)
+    h = ctypes.c_void_p()
+    assert lib.lbw_create(ctypes.byref(c), ctypes.byref(b), 1, None, ctypes.byref(h)) == 0
+    try:
+        assert lib.lbw_set_launch(h, ctypes.byref(lbw.CLaunch(0, 0, 1, 0, 0, 0, 0))) == lbw.ERR_INVAL
+        assert "work-items" in lib.lbw_last_error().decode()
+        # the plain transport (one thread per node) and longer chunks still fit
+        assert lib.lbw_set_launch(h, ctypes.byref(lbw.CLaunch(0, 0, 1, 1, 0, 0, 0))) == 0
+        assert lib.lbw_set_launch(h, ctypes.byref(lbw.CLaunch(0, 0, 64, 0, 0, 0, 0))) == 0
+    finally:
+        lib.lbw_destroy(h)
