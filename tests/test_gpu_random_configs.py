@@ -21,7 +21,7 @@ from parity import as_input, compare, run_gpu, run_oracle
 
 pytestmark = pytest.mark.gpu
 TOL64 = 1e-12
-NCASES = 100
+NCASES = 200
 
 
 def _draw(rng, lattice=None, precision=None, shared=None):
